@@ -1,0 +1,154 @@
+"""Block smoother, transfers, V-cycle and the outer iteration (Section 5).
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
+
+  * block smoother, Definition 5.6: weighted Jacobi on the SFV unknowns with
+    the old PLG unknowns (eq. (5.5)), then an exact solve of the PLG block
+    A22 u2 = b2 - A21 u1 (eq. (5.6)); omega = 1/2.  The exact solve uses a
+    sparse LU of A22 (any exact solve gives the same u2; the banded LU of
+    Definition 5.3 is one way to obtain it);
+  * level hierarchy, eq. (5.7): every level is its own run of Algorithm 1
+    and its own discretisation;
+  * restriction eq. (5.8) and piecewise-constant interpolation eq. (5.9);
+  * V-cycle, Algorithm 3, with a direct bottom solve;
+  * outer iteration: V-cycles until ||b - A u||_inf <= tol ||b||_inf.
+
+Readings of points the paper leaves open:
+  * D11 in eq. (5.5) is the centre weight -5(a+c)/(2h^2) of the symmetric FV
+    formulas for every SFV row, including rows whose stencil reaches ghost
+    cells (the ghosts are filled from the current iterate and treated as
+    given); with this reading the two-grid spectral radii of Table 1 on the
+    unit square are reproduced to every printed digit;
+  * a fine cell whose parent index floor(i/2) is no cut cell of the coarse
+    level (it was merged away) is mapped to the coarse cell that absorbed it;
+  * coarse levels see homogeneous boundary data (the residual equation);
+  * levels: coarsen while the coarser grid is valid (every box face
+    extendable, Algorithm 1 succeeds, every PLG cell has a lattice) and has
+    at least 16 cells per side, unless the number of levels is given.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .discretize import Level
+from .geometry import GeometryError
+
+
+class _Grid:
+    def __init__(self, x0, y0, h, nx, ny):
+        self.x0, self.y0, self.h, self.nx, self.ny = x0, y0, h, nx, ny
+
+
+class Hierarchy:
+    def __init__(self, grid, curves, a, b, c, eps, n_levels=0, omega=0.5, nu=(3, 3), min_cells=16):
+        self.omega = float(omega)
+        self.nu1, self.nu2 = nu
+        self.levels = [Level(grid, curves, a, b, c, eps)]
+        while n_levels == 0 or len(self.levels) < n_levels:
+            g = self.levels[-1].grid
+            if g.nx % 2 or g.ny % 2 or g.nx // 2 < min_cells or g.ny // 2 < min_cells:
+                if n_levels:
+                    raise GeometryError("cannot build the requested number of levels")
+                break
+            cg = _Grid(g.x0, g.y0, 2 * g.h, g.nx // 2, g.ny // 2)
+            try:
+                self.levels.append(Level(cg, curves, a, b, c, eps))
+            except GeometryError:
+                if n_levels:
+                    raise
+                break
+        self.R = [self._restriction(l) for l in range(len(self.levels) - 1)]
+        self.P = [4.0 * R.T.tocsr() for R in self.R]
+        self._smoother_setup()
+        self.bottom = spla.splu(self.levels[-1].A.tocsc())
+
+    def _restriction(self, l):
+        """I_h^{2h} of eq. (5.8) as a sparse matrix (coarse x fine)."""
+        fine, coarse = self.levels[l], self.levels[l + 1]
+        ci, cj = fine.cells_i // 2, fine.cells_j // 2
+        parent = coarse.idx[cj, ci].copy()
+        for k in np.nonzero(parent < 0)[0]:
+            cell = (int(ci[k]), int(cj[k]))
+            own = coarse.cg.owner.get(cell)
+            if own is None:
+                raise GeometryError("fine cell without a coarse parent")
+            parent[k] = coarse.idx[own[1], own[0]]
+        return sp.csr_matrix((np.full(fine.n, 0.25), (parent, np.arange(fine.n))),
+                             shape=(coarse.n, fine.n))
+
+    def _smoother_setup(self):
+        self.sm = []
+        for L in self.levels:
+            A11, A12, A21, A22 = L.blocks()
+            # D11: the centre weight of the symmetric FV operator, -5(a+c)/(2h^2),
+            # for every SFV row (ghost values count as given during a sweep).
+            # This reading reproduces Table 1 to all printed digits; using the
+            # diagonal after ghost elimination does not.
+            d11 = np.full(A11.shape[0], -2.5 * (L.a + L.c) / (L.h * L.h))
+            lu22 = spla.splu(A22.tocsc()) if A22.shape[0] else None
+            self.sm.append((A11, A12, A21, A22, d11, lu22, ~L.is_plg, L.is_plg))
+
+    # -- Definition 5.6 ---------------------------------------------------------
+    def smooth(self, l, u, b):
+        A11, A12, A21, A22, d11, lu22, s, p = self.sm[l]
+        u = u.copy()
+        u1, u2 = u[s], u[p]
+        u1 = u1 + self.omega * (b[s] - A11 @ u1 - A12 @ u2) / d11        # eq. (5.5)
+        if lu22 is not None:
+            u2 = lu22.solve(b[p] - A21 @ u1)                                # eq. (5.6)
+        u[s], u[p] = u1, u2
+        return u
+
+    # -- Algorithm 3 -----------------------------------------------------------
+    def vcycle(self, l, u, b):
+        L = self.levels[l]
+        if l == len(self.levels) - 1:
+            return self.bottom.solve(b)
+        for _ in range(self.nu1):
+            u = self.smooth(l, u, b)
+        r2 = self.R[l] @ (b - L.A @ u)
+        e2 = self.vcycle(l + 1, np.zeros(self.levels[l + 1].n), r2)
+        u = u + self.P[l] @ e2
+        for _ in range(self.nu2):
+            u = self.smooth(l, u, b)
+        return u
+
+    def solve(self, b, u0=None, tol=1e-10, max_iters=100, history=None):
+        """Outer V-cycle iteration; returns (u, iterations, relative residual)."""
+        A = self.levels[0].A
+        u = np.zeros_like(b) if u0 is None else u0.copy()
+        bn = np.abs(b).max()
+        rel = np.abs(b - A @ u).max() / bn
+        it = 0
+        while rel > tol and it < max_iters:
+            u = self.vcycle(0, u, b)
+            it += 1
+            rel = np.abs(b - A @ u).max() / bn
+            if history is not None:
+                history.append((u.copy(), rel))
+        return u, it, rel
+
+    # -- eq. (5.10) -----------------------------------------------------------
+    def two_grid_operator(self, nu1, nu2):
+        """TG = T^nu2 [I - P (A^{2h})^{-1} R A^h] T^nu1 as a LinearOperator on
+        level 0, with the coarse solve exact (parity unpinned for domains with
+        PLG cells; pinned on the unit square by Table 1)."""
+        A = self.levels[0].A
+        lu_c = spla.splu(self.levels[1].A.tocsc())
+        R, P = self.R[0], self.P[0]
+        zero = np.zeros(A.shape[0])
+
+        def T(e):
+            return self.smooth(0, e, zero)
+
+        def mv(e):
+            e = np.asarray(e).ravel()
+            for _ in range(nu1):
+                e = T(e)
+            e = e - P @ lu_c.solve(R @ (A @ e))
+            for _ in range(nu2):
+                e = T(e)
+            return e
+        return spla.LinearOperator(A.shape, matvec=mv, dtype=float)

@@ -1,0 +1,152 @@
+"""Pins of the oracle's discretisation and multigrid solver against values the
+paper prints (Tables 1 and 2), polynomial exactness and direct solves."""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import workloads as W
+from conftest import golden
+from oracle.discretize import Level, PLG, SFV
+from oracle.multigrid import Hierarchy
+from oracle.rhs import cell_averages, rhs
+
+POLY4 = {(0, 0): 0.3, (1, 0): -0.7, (0, 1): 0.2, (2, 0): 0.5, (1, 1): -0.4, (0, 2): 0.9, (3, 0): 0.25,
+         (2, 1): -0.6, (1, 2): 0.35, (0, 3): -0.45, (4, 0): 0.15, (3, 1): 0.55, (2, 2): -0.3,
+         (1, 3): 0.2, (0, 4): -0.1}
+POLY3 = {k: v for k, v in POLY4.items() if sum(k) <= 3}
+
+
+def _errors(level, u, uexact):
+    e = u - uexact
+    vol = level.cg.volfrac[level.cells_j, level.cells_i]
+    return (np.abs(e).max(), float(np.sum(vol * np.abs(e)) / vol.sum()),
+            math.sqrt(float(np.sum(vol * e * e) / vol.sum())))
+
+
+@pytest.mark.parametrize("row", [0, 1])
+def test_table2_unit_square_errors(row):
+    """Section 6.1, Table 2: errors of the exact discrete solution on the
+    unit square, to the three printed digits."""
+    n, linf, l1, l2 = golden("table2_unit_square.txt")[row]
+    P = W.unit_square_config(int(n))
+    L = Level(P.grid, P.curves, P.a, P.b, P.c, P.eps)
+    assert not L.is_plg.any()
+    b, _, _ = rhs(L, P.solution)
+    u = spla.spsolve(L.A.tocsc(), b)
+    got = _errors(L, u, cell_averages(L, P.solution.u))
+    for g, want in zip(got, (linf, l1, l2)):
+        assert float("%.2e" % g) == pytest.approx(want, rel=0.006)
+
+
+def test_table1_two_grid_radius_unit_square():
+    """Section 5.3, Table 1: spectral radius of TG on the unit square, all
+    five (nu1, nu2) pairs, three printed digits (h = 1/64 over 1/32)."""
+    P = W.unit_square_config(64)
+    H = Hierarchy(P.grid, P.curves, P.a, P.b, P.c, P.eps, n_levels=2)
+    for nu1, nu2, rho in golden("table1_unit_square_rho.txt"):
+        T = H.two_grid_operator(int(nu1), int(nu2))
+        ev = spla.eigs(T, k=3, which="LM", return_eigenvectors=False, maxiter=5000, tol=1e-8)
+        assert max(abs(ev)) == pytest.approx(rho, abs=6e-4)
+
+
+def _poly_problem(base, coeffs):
+    P = base
+    return W.Problem(P.name, P.grid, P.curves, P.a, P.b, P.c, W.Poly(coeffs, P.a, P.b, P.c), P.eps)
+
+
+@pytest.mark.parametrize("maker,n,coeffs", [
+    (W.unit_disk_config, 64, POLY4),
+    (W.three_disks_config, 128, POLY3),
+    (W.star_config, 128, POLY3),
+    (lambda s, n: W.unit_square_config(n, 1.0, 0.5, 2.0), 32, POLY3),
+])
+def test_polynomial_solution_is_exact(maker, n, coeffs):
+    """Every row is exact on the polynomials it must reproduce (degree 4 for
+    eq. (4.7) and the PLG fits; the corner ghosts of the cross term are exact
+    to degree 3), so the discrete solution equals the exact cell averages."""
+    P = _poly_problem(maker(0, n), coeffs)
+    L = Level(P.grid, P.curves, P.a, P.b, P.c, P.eps)
+    b, _, _ = rhs(L, P.solution)
+    ue = cell_averages(L, P.solution.u)
+    tau = L.A @ ue - b
+    assert np.abs(tau).max() <= 1e-9 * np.abs(b).max()
+    u = spla.spsolve(L.A.tocsc(), b)
+    assert np.abs(u - ue).max() <= 1e-9 * np.abs(ue).max()
+
+
+def test_plg_rows_exact_on_pi4_and_weighted_min_norm():
+    """eqs. (4.14)-(4.18): M beta = phibar, and W^{-1} beta lies in the row
+    space of M (the optimality condition of the weighted minimum-norm
+    problem, Lemma 4.4)."""
+    P = W.unit_disk_config(0, 64)
+    L = Level(P.grid, P.curves, P.a, P.b, P.c, P.eps)
+    checked = 0
+    for (i, j), (beta, bb) in L.beta.items():
+        lat = L.lattice[(i, j)]
+        M = np.array([L._avg_monomials((i + d[0], j + d[1]), d) for d in lat]).T
+        w = np.array([max(math.hypot(*d), 0.5) for d in lat])
+        full = beta
+        if bb is not None:
+            M = np.hstack([M, L.boundary_average_of_basis(i, j)[:, None]])
+            w = np.append(w, 0.5)
+            full = np.append(beta, bb)
+            # W^{-1} beta = M^T y for some y
+            y = np.linalg.lstsq(M.T, w * full, rcond=None)[0]
+            assert np.abs(M.T @ y - w * full).max() <= 1e-8 * np.abs(w * full).max()
+        phibar = L._lphi(i, j)
+        assert np.abs(M @ full - phibar).max() <= 1e-10 * np.abs(phibar).max()
+        checked += 1
+    assert checked == int(L.is_plg.sum())
+
+
+@pytest.fixture(scope="module")
+def disk_hierarchy():
+    P = W.unit_disk_config(3, 64)
+    H = Hierarchy(P.grid, P.curves, P.a, P.b, P.c, P.eps)
+    b, _, _ = rhs(H.levels[0], P.solution)
+    return P, H, b
+
+
+def test_block_smoother_zeroes_plg_residual(disk_hierarchy):
+    """After one block-smoother sweep r2 = 0 (Definition 5.6)."""
+    P, H, b = disk_hierarchy
+    L = H.levels[0]
+    u = H.smooth(0, np.random.default_rng(1).standard_normal(L.n), b)
+    r = b - L.A @ u
+    assert np.abs(r[L.is_plg]).max() <= 1e-10 * np.abs(b).max()
+    assert np.abs(r[~L.is_plg]).max() > 1e-3 * np.abs(b).max()
+
+
+def test_vcycle_converges_to_direct_solution(disk_hierarchy):
+    """The V-cycle iteration converges to u* = A^{-1} b (eq. (4.19))."""
+    P, H, b = disk_hierarchy
+    A = H.levels[0].A
+    u, it, rel = H.solve(b, tol=1e-12, max_iters=60)
+    ustar = spla.spsolve(A.tocsc(), b)
+    assert rel <= 1e-12
+    assert np.abs(u - ustar).max() <= 1e-10 * np.abs(ustar).max()
+
+
+def test_vcycle_is_affine(disk_hierarchy):
+    """Vcycle(u, b) = u + Vcycle(0, b - A u): the defect-correction form used
+    by the mixed-precision path equals Algorithm 3 in exact arithmetic."""
+    P, H, b = disk_hierarchy
+    L = H.levels[0]
+    u0 = np.random.default_rng(2).standard_normal(L.n)
+    v1 = H.vcycle(0, u0, b)
+    v2 = u0 + H.vcycle(0, np.zeros(L.n), b - L.A @ u0)
+    assert np.abs(v1 - v2).max() <= 1e-9 * np.abs(v1).max()
+
+
+def test_fourth_order_convergence_disk():
+    """Solution error ratio near 16 per halving of h (Tables 2-5 behaviour)."""
+    errs = []
+    for n in (64, 128):
+        P = W.unit_disk_config(0, n)
+        L = Level(P.grid, P.curves, P.a, P.b, P.c, P.eps)
+        b, _, _ = rhs(L, P.solution)
+        u = spla.spsolve(L.A.tocsc(), b)
+        errs.append(np.abs(u - cell_averages(L, P.solution.u)).max())
+    assert errs[0] / errs[1] > 8.0
