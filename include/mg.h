@@ -1,0 +1,171 @@
+/*
+ * mg.h -- C ABI of the MI355X cut-cell multigrid library.
+ *
+ * Solves a u_xx + b u_xy + c u_yy = f in Omega, N u = g on dOmega
+ * (Section 1, eqs. (1.1)-(1.2); b^2 - 4ac < 0) with the fourth-order
+ * finite-volume cut-cell discretisation (Section 4) and the cut-cell V-cycle
+ * with the block smoother (Section 5, Definition 5.6, Algorithm 3).
+ *
+ * Conventions
+ *  - Omega is the grid box minus holes.  curves[0] must be the grid box
+ *    itself, counter-clockwise, one line segment per side (bottom, right,
+ *    top, left), each carrying the boundary condition of that side
+ *    (Dirichlet or Neumann).  curves[1..] are holes made of line segments
+ *    and circular arcs, closed, clockwise (Omega on the left, Section 2),
+ *    strictly inside the box.
+ *  - Cell arrays (f, u, b, r) are row-major with a halo of 2 cells on each
+ *    side: cell (i, j), 0 <= i < nx, 0 <= j < ny, lives at index
+ *    (j + 2) * (nx + 4) + (i + 2).  Entries of inactive cells (outside
+ *    Omega or merged into a neighbour, Algorithm 1) and of the halo are
+ *    ignored on input and written as 0 on output.
+ *  - f holds cell averages <f>_i over the cut cells (eq. (4.1)), not point
+ *    values.  g holds boundary averages (eq. (4.2)) in the layout returned
+ *    by mg_boundary_layout: first the 2nx + 2ny box faces (bottom faces
+ *    i = 0..nx-1, then top faces, then left faces j = 0..ny-1, then right
+ *    faces; Dirichlet: average of u, Neumann: average of du/dn with n the
+ *    outward normal), then one value per irregular cut cell, <<N u>> over
+ *    its cut boundary B_i.
+ *  - Pointers named *_dev are device pointers (HIP), owned by the caller,
+ *    valid on the device the handle was created on.  Every call is ordered
+ *    on the HIP stream `stream` (NULL = the null stream); calls that return
+ *    host scalars synchronise that stream before returning.
+ *  - A handle owns all of its device memory and must not be used from two
+ *    host threads at once.
+ *  - Every entry point returns an mg_status; MG_OK is 0.  On error nothing
+ *    is written to outputs except where stated.
+ */
+#ifndef MG_H
+#define MG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mg_handle_s *mg_handle;
+
+typedef enum {
+    MG_OK = 0,
+    MG_ERR_INVALID_ARG = -1,   /* bad pointer, size, coefficient or option */
+    MG_ERR_GEOMETRY = -2,      /* the grid does not resolve the geometry (Algorithm 1
+                                  precondition), or no poised lattice exists */
+    MG_ERR_SINGULAR = -3,      /* a dense factorisation met a zero pivot */
+    MG_ERR_NO_CONVERGENCE = -4,/* max_iters reached; u holds the last iterate */
+    MG_ERR_DIVERGED = -5,      /* residual grew for 3 iterations or became NaN */
+    MG_ERR_OOM = -6,           /* device allocation failed */
+    MG_ERR_HIP = -7,           /* a HIP runtime call failed */
+    MG_ERR_UNSUPPORTED = -8    /* e.g. a Robin condition on a box side */
+} mg_status;
+
+typedef enum { MG_BC_DIRICHLET = 0, MG_BC_NEUMANN = 1, MG_BC_ROBIN = 2 } mg_bc;
+typedef enum { MG_SEG_LINE = 0, MG_SEG_ARC = 1 } mg_seg_kind;
+
+/* One boundary segment.  LINE: p = {x0, y0, x1, y1}; ARC: p = {cx, cy, r,
+ * theta0, theta1} with signed sweep theta1 - theta0.  bc with the Robin
+ * coefficients: N u = alpha1 u + alpha2 du/dn (eq. (1.2)). */
+typedef struct {
+    int kind;
+    double p[5];
+    int bc;
+    double alpha1, alpha2;
+} mg_segment;
+
+typedef struct { int n_seg; const mg_segment *seg; } mg_curve;
+
+/* Finest grid: cells (x0 + i h, x0 + (i+1) h) x (y0 + j h, y0 + (j+1) h). */
+typedef struct { double x0, y0, h; int nx, ny; } mg_grid;
+
+typedef enum { MG_FP64 = 0, MG_MIXED = 1 } mg_precision;
+
+typedef struct {
+    double eps;        /* volume-fraction threshold of Algorithm 1 (default 0.08) */
+    double omega;      /* Jacobi weight of eq. (5.5) (default 0.5) */
+    int nu1, nu2;      /* pre/post smoothing sweeps of Algorithm 3 (default 3, 3) */
+    int n_levels;      /* 0 = coarsen while the coarser grid is valid and >= min_coarse cells per side */
+    int min_coarse;    /* default 16 */
+    int precision;     /* mg_precision (default MG_FP64) */
+    int max_iters;     /* outer iterations of mg_solve (default 100) */
+} mg_options;
+
+typedef struct {
+    int n_levels;
+    int nx[16], ny[16];
+    int n_active[16];          /* cut cells in C^h_eps per level */
+    int n_plg[16];             /* PLG cells per level (Definition 4.1) */
+    int n_sep[16];             /* separator unknowns of the PLG block solve per level */
+    int n_face, n_irr;         /* boundary-data layout sizes (finest level) */
+    long long nnz_plg;         /* nonzeros of the PLG rows, all levels */
+    long long device_bytes;    /* device memory held by the handle */
+    double setup_seconds;
+} mg_info;
+
+/* Defaults listed in mg_options. */
+mg_status mg_default_options(mg_options *opt);
+
+/* Builds the level hierarchy (eq. (5.7)): on every level the cut cells and
+ * Algorithm 1, the SFV/PLG classification (Definition 4.1), the poised
+ * lattices and the weighted minimum-norm fits (eqs. (4.10)-(4.18), computed
+ * in FP64 on the GPU), the PLG block solver and the bottom-level inverse.
+ * opt may be NULL (defaults).  On success *out owns the device data. */
+mg_status mg_setup(const mg_grid *grid, int n_curves, const mg_curve *curves,
+                   double a, double b, double c, const mg_options *opt,
+                   void *stream, mg_handle *out);
+
+/* Outer iteration: b = f - N g (eq. (4.19)), then V-cycles (Algorithm 3;
+ * in MG_MIXED precision an FP32 V-cycle on the FP64 residual, added in FP64)
+ * until ||b - A u||_inf <= tol ||b||_inf or max_iters.  u_dev is the initial
+ * guess on entry and the solution on exit.  *iters and *rel_residual are
+ * written on MG_OK and on MG_ERR_NO_CONVERGENCE. */
+mg_status mg_solve(mg_handle h, const double *f_dev, const double *g_dev, double *u_dev,
+                   double tol, void *stream, int *iters, double *rel_residual);
+
+/* b_dev = f - N g on the finest level (eq. (4.19)). */
+mg_status mg_rhs(mg_handle h, const double *f_dev, const double *g_dev, double *b_dev, void *stream);
+
+/* One FP64 V-cycle (Algorithm 3) on A u = b, updating u_dev in place. */
+mg_status mg_vcycle(mg_handle h, const double *b_dev, double *u_dev, void *stream);
+
+/* One block-smoother sweep (Definition 5.6) on level `level`; u_dev, b_dev
+ * use that level's padded layout (nx_l + 4 columns). */
+mg_status mg_smooth(mg_handle h, int level, const double *b_dev, double *u_dev, void *stream);
+
+/* r_dev = b - A u on level `level` (r_dev may be NULL) and *rnorm = ||r||_inf
+ * over active cells (rnorm may be NULL). */
+mg_status mg_residual(mg_handle h, int level, const double *b_dev, const double *u_dev,
+                      double *r_dev, double *rnorm, void *stream);
+
+mg_status mg_query(mg_handle h, mg_info *info);
+
+/* Host copies of one level's structure: kind[ny*nx] (0 inactive, 1 SFV,
+ * 2 PLG, row-major without halo; may be NULL), and the PLG rows of A in
+ * CSR form over PLG cells in row-major cell order: row_ptr[n_plg + 1],
+ * col[nnz] (row-major cell index j*nx + i), val[nnz]; beta_b[n_plg] holds
+ * the boundary coefficient of irregular rows and 0 otherwise.  Call with
+ * col == NULL to get *nnz only. */
+mg_status mg_export_level(mg_handle h, int level, int *kind, int *n_plg, long long *nnz,
+                          int *row_ptr, int *col, double *val, double *beta_b);
+
+/* Quadrature rules that let callers form the inputs.
+ * Cells: for every active cell that is not a full grid cell, nodes and
+ * weights with sum_k w_k F(x_k, y_k) = <F> over the cut cell; full cells
+ * take any rule of the caller's choosing.  Boundary: for every entry of g,
+ * nodes, weights summing to 1 and the outward unit normal, so that
+ * sum_k w_k (N u)(x_k, y_k) = g_entry (box faces use the face's own BC,
+ * irregular cells the BC of the segment each node lies on: bc[k],
+ * alpha1[k], alpha2[k]).  CSR layout: ptr[n + 1] offsets into the node
+ * arrays.  Call with x == NULL to get the sizes (*n, *nnodes) only.
+ * cell[k] (cells only) is the row-major cell index of entry k. */
+mg_status mg_cell_quadrature(mg_handle h, int *n, long long *nnodes, int *cell, long long *ptr,
+                             double *x, double *y, double *w);
+mg_status mg_boundary_quadrature(mg_handle h, int *n, long long *nnodes, long long *ptr,
+                                 double *x, double *y, double *w, double *nx, double *ny,
+                                 int *bc, double *alpha1, double *alpha2);
+
+mg_status mg_destroy(mg_handle h);
+const char *mg_error_string(mg_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MG_H */

@@ -22,11 +22,12 @@ Readings of points the paper leaves open (each also listed in the design doc):
     smoother diverge (spectral radius above 1 on the unit square);
   * lattice selection (the cited PLG algorithm is not reproduced): K is the
     set of active cells in the 7x7 index box centred at i (9x9 if needed);
-    its nodes are taken nearest-first (key |d|^2, then the angle of d in
-    [0, 2pi), d = j - i) whenever they raise the exact rank of the
-    point-sample matrix [d^alpha], |alpha| <= 4, until 15 are chosen.  A 5x5
-    box shifted inward gives lopsided rows on coarse levels that make the
-    two-grid correction diverge on the star domain;
+    a nearest-first greedy with an exact rank test is run under each of the
+    8 grid symmetries, and the lattice whose full-cell fit has the smallest
+    weighted norm ||beta||_{W^{-1}} is kept (see ``select_lattice``).  A
+    single greedy pass, or a 5x5 box shifted inward, gives lopsided rows with
+    a positive centre weight on coarse levels, which make the two-grid
+    correction diverge;
   * the basis centre p is the centre of the grid cell of i;
   * the minimum-W^{-1}-norm solution is computed as beta = W^{1/2} gamma with
     gamma the minimum-2-norm solution of (M W^{1/2}) gamma = phibar, which is
@@ -35,13 +36,12 @@ Readings of points the paper leaves open (each also listed in the design doc):
 from __future__ import annotations
 
 import math
-from fractions import Fraction
 
 import numpy as np
 import scipy.sparse as sp
 
-from .geometry import (MONOS, MONO_INDEX, CutGrid, GeometryError, _GL, seg_deriv, seg_normal,
-                       seg_point, shift_moments)
+from .geometry import (MONOS, MONO_INDEX, CutGrid, GeometryError, _GL, full_cell_moments, seg_deriv,
+                       seg_normal, seg_point, shift_moments)
 from .stencil import corner_ghost_weights, ghost_weights, operator_terms
 
 NBASIS = len(MONOS)        # dim Pi_4^2 = 15
@@ -54,11 +54,12 @@ SFV, PLG = 1, 2
 # lattices
 # ----------------------------------------------------------------------------
 def _mono_row(d):
-    return [Fraction(d[0] ** a * d[1] ** b) for a, b in MONOS]
+    return [d[0] ** a * d[1] ** b for a, b in MONOS]
 
 
 class _Echelon:
-    """Incremental row echelon form over the rationals (exact rank test)."""
+    """Incremental row echelon form over the integers (fraction-free, exact
+    rank test over the rationals)."""
 
     def __init__(self):
         self.rows = []           # (pivot column, row)
@@ -67,8 +68,14 @@ class _Echelon:
         v = list(v)
         for piv, r in self.rows:
             if v[piv] != 0:
-                f = v[piv] / r[piv]
-                v = [x - f * y for x, y in zip(v, r)]
+                f, g = r[piv], v[piv]
+                v = [f * x - g * y for x, y in zip(v, r)]
+                # keep the entries small: divide by the gcd
+                gg = 0
+                for x in v:
+                    gg = math.gcd(gg, x)
+                if gg > 1:
+                    v = [x // gg for x in v]
         for k, x in enumerate(v):
             if x != 0:
                 self.rows.append((k, v))
@@ -93,29 +100,68 @@ def _angle(d):
 
 _LATTICE_MEMO = {}
 
+# the 8 symmetries of the grid (rotations by 90 degrees and reflections)
+_SYMMETRIES = ((1, 0, 0, 1), (0, -1, 1, 0), (-1, 0, 0, -1), (0, 1, -1, 0),
+               (1, 0, 0, -1), (0, 1, 1, 0), (-1, 0, 0, 1), (0, -1, -1, 0))
 
-def select_lattice(window):
+
+def _regular_fit_norm(lat, abc):
+    """||beta||^2 in the W^{-1} norm of eq. (4.17) for the lattice `lat` of
+    full cells with spacing 1 (beta solves M beta = phibar of eq. (4.14))."""
+    a, b, c = abc
+    full = full_cell_moments()
+    M = np.array([shift_moments(full, d[0], d[1]) for d in lat]).T
+    phibar = np.zeros(NBASIS)
+    for k, (p, q) in enumerate(MONOS):
+        s = 0.0
+        if p >= 2:
+            s += a * p * (p - 1) * full[MONO_INDEX[(p - 2, q)]]
+        if p >= 1 and q >= 1:
+            s += b * p * q * full[MONO_INDEX[(p - 1, q - 1)]]
+        if q >= 2:
+            s += c * q * (q - 1) * full[MONO_INDEX[(p, q - 2)]]
+        phibar[k] = s
+    beta = np.linalg.solve(M, phibar)
+    w = np.array([max(math.hypot(d[0], d[1]), W_MIN) for d in lat])
+    return float(np.sum(w * beta * beta))
+
+
+def select_lattice(window, abc):
     """window: frozenset of offsets d (|d|_inf <= 4) of the active cells around
-    the PLG cell i.  K is the centred 7x7 box (the centred 9x9 box if the 7x7
-    one holds no poised subset); its nodes are taken nearest-first, ordered by
-    (|d|^2, angle of d in [0, 2pi)), whenever they raise the exact rank of the
-    point-sample matrix [d^alpha], |alpha| <= 4.  Returns the 15 offsets of
-    S_PLG(i) in selection order."""
-    hit = _LATTICE_MEMO.get(window)
+    the PLG cell i; abc: the coefficients (a, b, c).
+
+    K is the set of active cells in the 7x7 box centred at i (the 9x9 box if
+    the 7x7 one holds no poised subset).  For each of the 8 symmetries g of
+    the grid, nodes of K are taken nearest-first, ordered by (|d|^2, angle of
+    g(d) in [0, 2pi)), whenever they raise the exact rank of the point-sample
+    matrix [d^alpha], |alpha| <= 4, until 15 are chosen.  Of these (up to 8)
+    poised lattices the one whose fit for full cells has the smallest
+    ||beta||_{W^{-1}} (eqs. (4.16)-(4.17)) is kept; a tie within a relative
+    1e-9 keeps the earlier symmetry.  Returns the 15 offsets of S_PLG(i)."""
+    key = (window, abc)
+    hit = _LATTICE_MEMO.get(key)
     if hit is not None:
         return hit
-    key = lambda d: (d[0] * d[0] + d[1] * d[1], _angle(d))
-    result = None
+    best, bestv = None, None
     for half in (3, 4):
         box = [d for d in window if abs(d[0]) <= half and abs(d[1]) <= half]
-        if len(box) >= NBASIS:
-            result = _greedy(sorted(box, key=key))
-        if result is not None:
+        if len(box) < NBASIS:
+            continue
+        for g in _SYMMETRIES:
+            order = sorted(box, key=lambda d: (d[0] * d[0] + d[1] * d[1],
+                                               _angle((g[0] * d[0] + g[1] * d[1], g[2] * d[0] + g[3] * d[1]))))
+            lat = _greedy(order)
+            if lat is None:
+                continue
+            v = _regular_fit_norm(lat, abc)
+            if bestv is None or v < bestv * (1.0 - 1e-9):
+                best, bestv = lat, v
+        if best is not None:
             break
-    if result is None:
+    if best is None:
         raise GeometryError("no poised lattice for a PLG cell")
-    _LATTICE_MEMO[window] = result
-    return result
+    _LATTICE_MEMO[key] = best
+    return best
 
 
 # ----------------------------------------------------------------------------
@@ -285,7 +331,7 @@ class Level:
     def _lattice(self, i, j):
         win = frozenset((dx, dy) for dx in range(-4, 5) for dy in range(-4, 5)
                         if self.cg.is_active(i + dx, j + dy))
-        return select_lattice(win)
+        return select_lattice(win, (self.a, self.b, self.c))
 
     def _avg_monomials(self, cell, d):
         """<((x - p)/h)^alpha>_cell for p the centre of grid cell cell - d."""

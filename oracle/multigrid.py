@@ -115,15 +115,29 @@ class Hierarchy:
             u = self.smooth(l, u, b)
         return u
 
-    def solve(self, b, u0=None, tol=1e-10, max_iters=100, history=None):
-        """Outer V-cycle iteration; returns (u, iterations, relative residual)."""
+    # -- Algorithm 4 -----------------------------------------------------------
+    def fmg(self, l, r):
+        """FMG cycle on the residual equation A^h e = r^h; returns e."""
+        if l == len(self.levels) - 1:
+            return self.bottom.solve(r)
+        e2 = self.fmg(l + 1, self.R[l] @ r)
+        e = self.P[l] @ e2
+        return self.vcycle(l, e, r)
+
+    def solve(self, b, u0=None, tol=1e-10, max_iters=100, history=None, cycle="V"):
+        """Outer iteration with V-cycles (u <- Vcycle(u, b)) or FMG cycles on
+        the residual equation (u <- u + FMG(b - A u), Section 5.4); returns
+        (u, iterations, relative residual)."""
         A = self.levels[0].A
         u = np.zeros_like(b) if u0 is None else u0.copy()
         bn = np.abs(b).max()
         rel = np.abs(b - A @ u).max() / bn
         it = 0
         while rel > tol and it < max_iters:
-            u = self.vcycle(0, u, b)
+            if cycle == "V":
+                u = self.vcycle(0, u, b)
+            else:
+                u = u + self.fmg(0, b - A @ u)
             it += 1
             rel = np.abs(b - A @ u).max() / bn
             if history is not None:

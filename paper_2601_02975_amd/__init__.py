@@ -1,0 +1,291 @@
+"""Python binding of libmgcut.so, the MI355X cut-cell multigrid library.
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+Device arrays are torch tensors on the current HIP device (PyTorch supplies
+device memory and the stream); importing fails loudly when the library has
+not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmgcut.so")
+
+MG_OK = 0
+STATUS = {0: "MG_OK", -1: "MG_ERR_INVALID_ARG", -2: "MG_ERR_GEOMETRY", -3: "MG_ERR_SINGULAR",
+          -4: "MG_ERR_NO_CONVERGENCE", -5: "MG_ERR_DIVERGED", -6: "MG_ERR_OOM", -7: "MG_ERR_HIP",
+          -8: "MG_ERR_UNSUPPORTED"}
+BC = {"D": 0, "N": 1, "R": 2}
+FP64, MIXED = 0, 1
+
+
+class MGError(RuntimeError):
+    def __init__(self, code, where):
+        super().__init__("%s failed: %s (%d)" % (where, STATUS.get(code, "?"), code))
+        self.code = code
+
+
+class mg_segment(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("p", ctypes.c_double * 5), ("bc", ctypes.c_int),
+                ("alpha1", ctypes.c_double), ("alpha2", ctypes.c_double)]
+
+
+class mg_curve(ctypes.Structure):
+    _fields_ = [("n_seg", ctypes.c_int), ("seg", ctypes.POINTER(mg_segment))]
+
+
+class mg_grid(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_double), ("y0", ctypes.c_double), ("h", ctypes.c_double),
+                ("nx", ctypes.c_int), ("ny", ctypes.c_int)]
+
+
+class mg_options(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("omega", ctypes.c_double), ("nu1", ctypes.c_int),
+                ("nu2", ctypes.c_int), ("n_levels", ctypes.c_int), ("min_coarse", ctypes.c_int),
+                ("precision", ctypes.c_int), ("max_iters", ctypes.c_int)]
+
+
+class mg_info(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int), ("nx", ctypes.c_int * 16), ("ny", ctypes.c_int * 16),
+                ("n_active", ctypes.c_int * 16), ("n_plg", ctypes.c_int * 16), ("n_sep", ctypes.c_int * 16),
+                ("n_face", ctypes.c_int), ("n_irr", ctypes.c_int), ("nnz_plg", ctypes.c_longlong),
+                ("device_bytes", ctypes.c_longlong), ("setup_seconds", ctypes.c_double)]
+
+
+def load_library():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libmgcut.so is not built (run __graft_entry__.build() or "
+                          "python paper_2601_02975_amd/build.py)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D, LL = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong
+    pI, pD, pLL = ctypes.POINTER(I), ctypes.POINTER(D), ctypes.POINTER(LL)
+    sig = {
+        "mg_default_options": [ctypes.POINTER(mg_options)],
+        "mg_setup": [ctypes.POINTER(mg_grid), I, ctypes.POINTER(mg_curve), D, D, D, ctypes.POINTER(mg_options), P,
+                     ctypes.POINTER(P)],
+        "mg_solve": [P, P, P, P, D, P, pI, pD],
+        "mg_rhs": [P, P, P, P, P],
+        "mg_vcycle": [P, P, P, P],
+        "mg_smooth": [P, I, P, P, P],
+        "mg_residual": [P, I, P, P, P, pD, P],
+        "mg_query": [P, ctypes.POINTER(mg_info)],
+        "mg_export_level": [P, I, pI, pI, pLL, pI, pI, pD, pD],
+        "mg_cell_quadrature": [P, pI, pLL, pI, pLL, pD, pD, pD],
+        "mg_boundary_quadrature": [P, pI, pLL, pLL, pD, pD, pD, pD, pD, pI, pD, pD],
+        "mg_destroy": [P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.mg_error_string.argtypes = [ctypes.c_int]
+    lib.mg_error_string.restype = ctypes.c_char_p
+    return lib
+
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        _LIB = load_library()
+    return _LIB
+
+
+def _check(code, where):
+    if code != MG_OK:
+        raise MGError(code, where)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def _lp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong))
+
+
+class Solver:
+    """A handle of the C library for one problem (grid, curves, a, b, c)."""
+
+    def __init__(self, grid, curves, a, b, c, eps=0.08, omega=0.5, nu=(3, 3), n_levels=0, min_coarse=16,
+                 precision=FP64, max_iters=100):
+        L = lib()
+        self._segs = []
+        carr = (mg_curve * len(curves))()
+        for k, curve in enumerate(curves):
+            segs = (mg_segment * len(curve))()
+            for s, sg in enumerate(curve):
+                segs[s].kind = 0 if sg.kind == "line" else 1
+                for t in range(5):
+                    segs[s].p[t] = float(sg.p[t]) if t < len(sg.p) else 0.0
+                segs[s].bc = BC[sg.bc]
+                segs[s].alpha1 = float(sg.alpha1)
+                segs[s].alpha2 = float(sg.alpha2)
+            self._segs.append(segs)
+            carr[k].n_seg = len(curve)
+            carr[k].seg = ctypes.cast(segs, ctypes.POINTER(mg_segment))
+        g = mg_grid(grid.x0, grid.y0, grid.h, grid.nx, grid.ny)
+        opt = mg_options()
+        L.mg_default_options(ctypes.byref(opt))
+        opt.eps, opt.omega, opt.nu1, opt.nu2 = eps, omega, nu[0], nu[1]
+        opt.n_levels, opt.min_coarse, opt.precision, opt.max_iters = n_levels, min_coarse, precision, max_iters
+        self.grid = grid
+        self.nx, self.ny = grid.nx, grid.ny
+        h = ctypes.c_void_p()
+        _check(L.mg_setup(ctypes.byref(g), len(curves), carr, a, b, c, ctypes.byref(opt), _stream(),
+                          ctypes.byref(h)), "mg_setup")
+        self.h = h
+        self.info = self.query()
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- layout helpers ----------------------------------------------------------
+    def padded_shape(self, level=0):
+        return (self.info["ny"][level] + 4, self.info["nx"][level] + 4)
+
+    def empty(self, level=0, dtype=None):
+        import torch
+        return torch.zeros(self.padded_shape(level), dtype=dtype or torch.float64, device="cuda")
+
+    # -- entry points ------------------------------------------------------------
+    def solve(self, f, g, u, tol=1e-10):
+        it = ctypes.c_int()
+        rel = ctypes.c_double()
+        code = lib().mg_solve(self.h, _ptr(f), _ptr(g), _ptr(u), tol, _stream(), ctypes.byref(it), ctypes.byref(rel))
+        if code not in (MG_OK, -4):
+            _check(code, "mg_solve")
+        return it.value, rel.value, code
+
+    def rhs(self, f, g, b):
+        _check(lib().mg_rhs(self.h, _ptr(f), _ptr(g), _ptr(b), _stream()), "mg_rhs")
+
+    def vcycle(self, b, u):
+        _check(lib().mg_vcycle(self.h, _ptr(b), _ptr(u), _stream()), "mg_vcycle")
+
+    def smooth(self, level, b, u):
+        _check(lib().mg_smooth(self.h, level, _ptr(b), _ptr(u), _stream()), "mg_smooth")
+
+    def residual(self, level, b, u, r=None):
+        nrm = ctypes.c_double()
+        _check(lib().mg_residual(self.h, level, _ptr(b), _ptr(u), _ptr(r), ctypes.byref(nrm), _stream()),
+               "mg_residual")
+        return nrm.value
+
+    def query(self):
+        inf = mg_info()
+        _check(lib().mg_query(self.h, ctypes.byref(inf)), "mg_query")
+        n = inf.n_levels
+        return {"n_levels": n, "nx": list(inf.nx[:n]), "ny": list(inf.ny[:n]), "n_active": list(inf.n_active[:n]),
+                "n_plg": list(inf.n_plg[:n]), "n_sep": list(inf.n_sep[:n]), "n_face": inf.n_face,
+                "n_irr": inf.n_irr, "nnz_plg": inf.nnz_plg, "device_bytes": inf.device_bytes,
+                "setup_seconds": inf.setup_seconds}
+
+    def export_level(self, level):
+        nx, ny = self.info["nx"][level], self.info["ny"][level]
+        kind = np.zeros(nx * ny, np.int32)
+        m = ctypes.c_int()
+        nnz = ctypes.c_longlong()
+        _check(lib().mg_export_level(self.h, level, _ip(kind), ctypes.byref(m), ctypes.byref(nnz), None, None, None,
+                                     None), "mg_export_level")
+        rp = np.zeros(m.value + 1, np.int32)
+        col = np.zeros(max(nnz.value, 1), np.int32)
+        val = np.zeros(max(nnz.value, 1))
+        bb = np.zeros(max(m.value, 1))
+        _check(lib().mg_export_level(self.h, level, None, None, None, _ip(rp), _ip(col), _dp(val), _dp(bb)),
+               "mg_export_level")
+        return kind.reshape(ny, nx), rp, col[:nnz.value], val[:nnz.value], bb[:m.value]
+
+    def cell_quadrature(self):
+        n = ctypes.c_int()
+        nn = ctypes.c_longlong()
+        _check(lib().mg_cell_quadrature(self.h, ctypes.byref(n), ctypes.byref(nn), None, None, None, None, None),
+               "mg_cell_quadrature")
+        cell = np.zeros(max(n.value, 1), np.int32)
+        ptr = np.zeros(n.value + 1, np.int64)
+        x, y, w = (np.zeros(max(nn.value, 1)) for _ in range(3))
+        _check(lib().mg_cell_quadrature(self.h, ctypes.byref(n), ctypes.byref(nn), _ip(cell), _lp(ptr), _dp(x), _dp(y),
+                                        _dp(w)), "mg_cell_quadrature")
+        return cell[:n.value], ptr, x[:nn.value], y[:nn.value], w[:nn.value]
+
+    def boundary_quadrature(self):
+        n = ctypes.c_int()
+        nn = ctypes.c_longlong()
+        _check(lib().mg_boundary_quadrature(self.h, ctypes.byref(n), ctypes.byref(nn), None, None, None, None, None,
+                                            None, None, None, None), "mg_boundary_quadrature")
+        ptr = np.zeros(n.value + 1, np.int64)
+        x, y, w, nxv, nyv, a1, a2 = (np.zeros(max(nn.value, 1)) for _ in range(7))
+        bc = np.zeros(max(nn.value, 1), np.int32)
+        _check(lib().mg_boundary_quadrature(self.h, ctypes.byref(n), ctypes.byref(nn), _lp(ptr), _dp(x), _dp(y),
+                                            _dp(w), _dp(nxv), _dp(nyv), _ip(bc), _dp(a1), _dp(a2)),
+               "mg_boundary_quadrature")
+        k = nn.value
+        return ptr, x[:k], y[:k], w[:k], nxv[:k], nyv[:k], bc[:k], a1[:k], a2[:k]
+
+    # -- inputs ------------------------------------------------------------------
+    def project(self, sol):
+        """Host arrays (f, g) of cell averages of sol.f and boundary averages of
+        N sol.u in the library's layout, from its quadrature rules (regular
+        cells: tensor Gauss-Legendre)."""
+        g0 = self.grid
+        nx, ny, h = g0.nx, g0.ny, g0.h
+        f = np.zeros((ny + 4, nx + 4))
+        npts = 8 if max(nx, ny) <= 1024 else 4
+        s, w = np.polynomial.legendre.leggauss(npts)
+        kind, _, _, _, _ = self.export_level(0)
+        xs = g0.x0 + (np.arange(nx)[:, None] + 0.5 + 0.5 * s[None, :]) * h          # nx x npts
+        chunk = max(1, (1 << 22) // (nx * npts * npts))
+        for j0 in range(0, ny, chunk):
+            j1 = min(ny, j0 + chunk)
+            ys = g0.y0 + (np.arange(j0, j1)[:, None] + 0.5 + 0.5 * s[None, :]) * h  # rows x npts
+            vals = sol.f(xs[None, :, :, None], ys[:, None, None, :])                # rows x nx x a x b
+            f[j0 + 2:j1 + 2, 2:nx + 2] = 0.25 * np.einsum("a,b,rnab->rn", w, w, vals)
+        cell, ptr, qx, qy, qw = self.cell_quadrature()
+        if len(cell):
+            v = sol.f(qx, qy) * qw
+            avg = np.add.reduceat(v, ptr[:-1]) if len(v) else np.zeros(0)
+            f[cell // nx + 2, cell % nx + 2] = avg
+        f[2:ny + 2, 2:nx + 2][kind == 0] = 0.0
+        ptr, bx, by, bw, bnx, bny, bc, a1, a2 = self.boundary_quadrature()
+        u = sol.u(bx, by)
+        dn = sol.ux(bx, by) * bnx + sol.uy(bx, by) * bny
+        val = np.where(bc == 0, u, np.where(bc == 1, dn, a1 * u + a2 * dn))
+        g = np.add.reduceat(val * bw, ptr[:-1])
+        return f, g
+
+
+def to_padded(grid_vals, nx, ny):
+    out = np.zeros((ny + 4, nx + 4))
+    out[2:ny + 2, 2:nx + 2] = grid_vals
+    return out
+
+
+def from_padded(p, nx, ny):
+    return np.asarray(p)[2:ny + 2, 2:nx + 2]

@@ -1,0 +1,857 @@
+// C ABI of the cut-cell multigrid library: setup orchestration, device data,
+// the V-cycle driver (Algorithm 3) and the outer iteration.
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <memory>
+
+#include "kernels_launch.hpp"
+#include "level.hpp"
+#include "mg.h"
+#include "plgsolve.hpp"
+
+using namespace mgc;
+
+namespace {
+
+#define HIPCHECK(x)                                                                             \
+    do {                                                                                        \
+        hipError_t e_ = (x);                                                                    \
+        if (e_ != hipSuccess) fail(MG_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int SEG_MAX = 256;       // longest PLG segment (dense inverse per segment)
+constexpr int BOTTOM_MAX = 8192;   // largest dense bottom inverse (right-hand side staged in 64 KiB of LDS)
+
+struct DevLevel {
+    LevelArgs args{};
+    size_t ncells = 0;
+    uint8_t *mask = nullptr;
+    int *plgidx = nullptr;
+    double *u64[2] = {nullptr, nullptr}, *b64 = nullptr, *rplg64 = nullptr;
+    float *u32[2] = {nullptr, nullptr}, *b32 = nullptr, *rplg32 = nullptr;
+    int m = 0;
+    int *plg_cell = nullptr, *full_ptr = nullptr, *full_col = nullptr;
+    double *full_val64 = nullptr;
+    float *full_val32 = nullptr;
+    PlgDev<double> P64;
+    PlgDev<float> P32;
+    int ex_nt = 0;
+    int *ex_ptr = nullptr, *ex_target = nullptr, *ex_child = nullptr;   // restriction to the next level
+    int pex_n = 0;
+    int *pex_fine = nullptr, *pex_coarse = nullptr;                     // prolongation from the next level
+    int nbot = 0;
+    int *bot_cells = nullptr;
+    double *ainv = nullptr;
+    int cur = 0;
+};
+
+}  // namespace
+
+struct mg_handle_s {
+    int device = 0;
+    mg_options opt{};
+    double a = 0, b = 0, c = 0;
+    Curves curves;
+    std::vector<std::unique_ptr<Level>> levels;
+    std::vector<PlgSolver> solvers;
+    std::vector<DevLevel> dev;
+    int nrhs = 0;
+    int *rhs_ptr = nullptr, *rhs_cell = nullptr, *rhs_gidx = nullptr;
+    double *rhs_coef = nullptr;
+    double *partial = nullptr, *host_scalar = nullptr;
+    int npartial = 0;
+    std::vector<void *> allocs;
+    long long bytes = 0;
+    double setup_seconds = 0.0;
+    std::string last_error;
+
+    template <typename T>
+    T *alloc(size_t n) {
+        if (n == 0) n = 1;
+        void *p = nullptr;
+        if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) fail(MG_ERR_OOM, "device allocation failed");
+        HIPCHECK(hipMemset(p, 0, n * sizeof(T)));
+        allocs.push_back(p);
+        bytes += (long long)(n * sizeof(T));
+        return (T *)p;
+    }
+    template <typename T>
+    T *upload(const std::vector<T> &v) {
+        T *p = alloc<T>(v.size());
+        if (!v.empty()) HIPCHECK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+        return p;
+    }
+    template <typename T>
+    T *upload_f32(const std::vector<double> &v) {
+        std::vector<float> f(v.begin(), v.end());
+        return upload(f);
+    }
+};
+
+namespace {
+
+size_t padded_index(int nx, int cell) { return (size_t)(cell / nx + 2) * (nx + 4) + (cell % nx + 2); }
+
+LevelArgs make_args(const Level &L, double omega) {
+    LevelArgs a{};
+    a.nx = L.g.nx;
+    a.ny = L.g.ny;
+    a.pitch = L.g.nx + 4;
+    a.h = L.g.h;
+    double h2 = L.g.h * L.g.h;
+    a.cxx = L.a / h2;
+    a.cxy = L.b / h2;
+    a.cyy = L.c / h2;
+    a.omega_over_d = omega / (-2.5 * (L.a + L.c) / h2);
+    for (int s = 0; s < 4; ++s) a.bc[s] = L.cg.box_bc[s] == MG_BC_NEUMANN ? 1 : 0;
+    a.mixed = L.b != 0.0;
+    return a;
+}
+
+// batched weighted minimum-norm fits on the GPU, then the PLG rows
+void fit_level(mg_handle h, Level &L, hipStream_t st) {
+    std::vector<double> M, phi, w;
+    std::vector<int> ncol;
+    L.fit_inputs(M, phi, w, ncol);
+    const int m = (int)L.plg_cells.size();
+    L.row_ptr.assign(m + 1, 0);
+    L.col.clear();
+    L.val.clear();
+    L.beta_b.assign(m, 0.0);
+    if (m == 0) return;
+    double *dM, *dphi, *dw, *dwork, *dbeta;
+    int *dncol, *dstat;
+    HIPCHECK(hipMalloc(&dM, M.size() * 8));
+    HIPCHECK(hipMalloc(&dphi, phi.size() * 8));
+    HIPCHECK(hipMalloc(&dw, w.size() * 8));
+    HIPCHECK(hipMalloc(&dncol, ncol.size() * 4));
+    HIPCHECK(hipMalloc(&dwork, (size_t)m * 511 * 8));
+    HIPCHECK(hipMalloc(&dbeta, (size_t)m * 16 * 8));
+    HIPCHECK(hipMalloc(&dstat, (size_t)m * 4));
+    HIPCHECK(hipMemcpy(dM, M.data(), M.size() * 8, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(dphi, phi.data(), phi.size() * 8, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(dw, w.data(), w.size() * 8, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(dncol, ncol.data(), ncol.size() * 4, hipMemcpyHostToDevice));
+    launch_fit(m, dM, dphi, dw, dncol, dwork, dbeta, dstat, st);
+    HIPCHECK(hipGetLastError());
+    std::vector<double> beta((size_t)m * 16);
+    std::vector<int> stat(m);
+    HIPCHECK(hipStreamSynchronize(st));
+    HIPCHECK(hipMemcpy(beta.data(), dbeta, beta.size() * 8, hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(stat.data(), dstat, stat.size() * 4, hipMemcpyDeviceToHost));
+    (void)hipFree(dM); (void)hipFree(dphi); (void)hipFree(dw); (void)hipFree(dncol); (void)hipFree(dwork); (void)hipFree(dbeta); (void)hipFree(dstat);
+    const int nx = L.g.nx;
+    for (int r = 0; r < m; ++r) {
+        if (!stat[r]) fail(MG_ERR_SINGULAR, "a PLG fit has a rank-deficient sample matrix");
+        int cell = L.plg_cells[r];
+        for (int k = 0; k < NB; ++k) {
+            L.col.push_back(cell + L.lattices[r][k][1] * nx + L.lattices[r][k][0]);
+            L.val.push_back(beta[(size_t)r * 16 + k]);
+        }
+        if (ncol[r] == NB + 1) L.beta_b[r] = beta[(size_t)r * 16 + NB];
+        L.row_ptr[r + 1] = (int)L.col.size();
+    }
+}
+
+// dense inverse of a row-major n x n matrix on the GPU (rocSOLVER)
+std::vector<double> gpu_inverse(int n, const std::vector<double> &A) {
+    rocblas_handle rb;
+    if (rocblas_create_handle(&rb) != rocblas_status_success) fail(MG_ERR_HIP, "rocblas_create_handle failed");
+    double *dA;
+    rocblas_int *ipiv, *info;
+    HIPCHECK(hipMalloc(&dA, (size_t)n * n * 8));
+    HIPCHECK(hipMalloc(&ipiv, (size_t)n * sizeof(rocblas_int)));
+    HIPCHECK(hipMalloc(&info, sizeof(rocblas_int)));
+    HIPCHECK(hipMemcpy(dA, A.data(), (size_t)n * n * 8, hipMemcpyHostToDevice));
+    // a row-major matrix is its transpose in column-major storage; the inverse
+    // of the transpose is the transpose of the inverse, so the result read
+    // back row-major is A^{-1}
+    rocsolver_dgetrf(rb, n, n, dA, n, ipiv, info);
+    rocblas_int hinfo = 0;
+    HIPCHECK(hipMemcpy(&hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost));
+    if (hinfo != 0) {
+        (void)hipFree(dA); (void)hipFree(ipiv); (void)hipFree(info);
+        rocblas_destroy_handle(rb);
+        fail(MG_ERR_SINGULAR, "the bottom-level matrix is singular");
+    }
+    rocsolver_dgetri(rb, n, dA, n, ipiv, info);
+    std::vector<double> out((size_t)n * n);
+    HIPCHECK(hipDeviceSynchronize());
+    HIPCHECK(hipMemcpy(out.data(), dA, (size_t)n * n * 8, hipMemcpyDeviceToHost));
+    (void)hipFree(dA); (void)hipFree(ipiv); (void)hipFree(info);
+    rocblas_destroy_handle(rb);
+    return out;
+}
+
+void upload_level(mg_handle h, int l, bool last, hipStream_t st) {
+    Level &L = *h->levels[l];
+    const PlgSolver &S = h->solvers[l];
+    DevLevel &D = h->dev[l];
+    const int nx = L.g.nx, ny = L.g.ny;
+    D.args = make_args(L, h->opt.omega);
+    D.ncells = (size_t)(nx + 4) * (ny + 4);
+    std::vector<uint8_t> mask(D.ncells, 0);
+    std::vector<int> plgidx(D.ncells, -1);
+    for (int cell = 0; cell < nx * ny; ++cell) mask[padded_index(nx, cell)] = L.kind[cell];
+    for (int q = 0; q < S.m; ++q) plgidx[padded_index(nx, L.plg_cells[S.order[q]])] = q;
+    D.mask = h->upload(mask);
+    D.plgidx = h->upload(plgidx);
+    for (int k = 0; k < 2; ++k) {
+        D.u64[k] = h->alloc<double>(D.ncells);
+        D.u32[k] = h->alloc<float>(D.ncells);
+    }
+    D.b64 = h->alloc<double>(D.ncells);
+    D.b32 = h->alloc<float>(D.ncells);
+    // PLG rows in solve order
+    D.m = S.m;
+    std::vector<int> cell(S.m), fptr(S.m + 1, 0), fcol, aptr(S.m + 1, 0), acol;
+    std::vector<double> fval, aval;
+    for (int q = 0; q < S.m; ++q) {
+        int r = S.order[q];
+        cell[q] = (int)padded_index(nx, L.plg_cells[r]);
+        for (int e = L.row_ptr[r]; e < L.row_ptr[r + 1]; ++e) {
+            int c = L.col[e];
+            fcol.push_back((int)padded_index(nx, c));
+            fval.push_back(L.val[e]);
+            if (L.kind[c] == 1) {
+                acol.push_back((int)padded_index(nx, c));
+                aval.push_back(L.val[e]);
+            }
+        }
+        fptr[q + 1] = (int)fcol.size();
+        aptr[q + 1] = (int)acol.size();
+    }
+    D.plg_cell = h->upload(cell);
+    D.full_ptr = h->upload(fptr);
+    D.full_col = h->upload(fcol);
+    D.full_val64 = h->upload(fval);
+    D.full_val32 = h->upload_f32<float>(fval);
+    D.rplg64 = h->alloc<double>(S.m);
+    D.rplg32 = h->alloc<float>(S.m);
+    int *a21_ptr = h->upload(aptr), *a21_col = h->upload(acol);
+    int *seg_start = h->upload(S.seg_start);
+    long long *inv_off = h->upload(S.inv_off), *f_off = h->upload(S.f_off);
+    int *fcols_ptr = h->upload(S.fcols_ptr), *fcols = h->upload(S.fcols);
+    int *sb_ptr = h->upload(S.sb_ptr), *sb_col = h->upload(S.sb_col);
+    int max_seg = 0;
+    for (int j = 0; j < S.nseg; ++j) max_seg = std::max(max_seg, S.seg_start[j + 1] - S.seg_start[j]);
+    // the segment and separator right-hand sides are staged in LDS (FP64)
+    if ((size_t)max_seg * 8 > 65536 || (size_t)S.nsep * 8 > 65536)
+        fail(MG_ERR_UNSUPPORTED, "PLG block partition exceeds the LDS budget");
+    auto fill = [&](auto &P, auto *a21v, auto *inv, auto *F, auto *sinv, auto *sbv, auto *y, auto *xs) {
+        P.m = S.m; P.nseg = S.nseg; P.nsep = S.nsep; P.sep_begin = S.sep_begin;
+        P.cell = D.plg_cell; P.a21_ptr = a21_ptr; P.a21_col = a21_col; P.a21_val = a21v;
+        P.seg_start = seg_start; P.inv_off = inv_off; P.inv = inv; P.f_off = f_off; P.F = F;
+        P.fcols_ptr = fcols_ptr; P.fcols = fcols; P.sinv = sinv; P.sb_ptr = sb_ptr; P.sb_col = sb_col;
+        P.sb_val = sbv; P.y = y; P.xs = xs; P.max_seg = max_seg;
+    };
+    fill(D.P64, h->upload(aval), h->upload(S.inv), h->upload(S.F), h->upload(S.sinv), h->upload(S.sb_val),
+         h->alloc<double>(S.m), h->alloc<double>(S.nsep));
+    fill(D.P32, h->upload_f32<float>(aval), h->upload_f32<float>(S.inv), h->upload_f32<float>(S.F),
+         h->upload_f32<float>(S.sinv), h->upload_f32<float>(S.sb_val), h->alloc<float>(S.m), h->alloc<float>(S.nsep));
+    // transfers to the next level
+    if (!last) {
+        const Level &C = *h->levels[l + 1];
+        std::vector<std::pair<int, int>> ex;        // (coarse target cell, fine cell)
+        for (int cellf = 0; cellf < nx * ny; ++cellf) {
+            if (!L.cg.active[cellf]) continue;
+            int ci = (cellf % nx) / 2, cj = (cellf / nx) / 2;
+            int cc = cj * C.g.nx + ci;
+            if (C.cg.active[cc]) continue;
+            int own = C.cg.owner[cc];
+            if (own < 0) fail(MG_ERR_GEOMETRY, "fine cell without a coarse parent");
+            ex.push_back({own, cellf});
+        }
+        std::sort(ex.begin(), ex.end());
+        std::vector<int> ptr{0}, tgt, child, pf, pc;
+        for (size_t k = 0; k < ex.size(); ++k) {
+            if (k == 0 || ex[k].first != ex[k - 1].first) {
+                if (k) ptr.push_back((int)k);
+                tgt.push_back((int)padded_index(C.g.nx, ex[k].first));
+            }
+            child.push_back((int)padded_index(nx, ex[k].second));
+            pf.push_back((int)padded_index(nx, ex[k].second));
+            pc.push_back((int)padded_index(C.g.nx, ex[k].first));
+        }
+        if (!ex.empty()) ptr.push_back((int)ex.size());
+        D.ex_nt = (int)tgt.size();
+        D.ex_ptr = h->upload(ptr);
+        D.ex_target = h->upload(tgt);
+        D.ex_child = h->upload(child);
+        D.pex_n = (int)pf.size();
+        D.pex_fine = h->upload(pf);
+        D.pex_coarse = h->upload(pc);
+    } else {
+        // bottom: dense inverse over the active cells
+        std::vector<int> act, pos((size_t)nx * ny, -1);
+        for (int cellc = 0; cellc < nx * ny; ++cellc)
+            if (L.cg.active[cellc]) {
+                pos[cellc] = (int)act.size();
+                act.push_back(cellc);
+            }
+        const int n = (int)act.size();
+        if (n > BOTTOM_MAX) fail(MG_ERR_UNSUPPORTED, "the coarsest level has too many cells for the dense bottom solve");
+        std::vector<double> A((size_t)n * n, 0.0);
+        std::vector<std::pair<int, double>> cells, gd;
+        for (int r = 0; r < n; ++r) {
+            int cl = act[r];
+            if (L.kind[cl] == 1) {
+                L.sfv_row(cl % nx, cl / nx, cells, gd);
+                for (auto &e : cells) A[(size_t)r * n + pos[e.first]] += e.second;
+            } else {
+                int pr = L.plg_row[cl];
+                for (int e = L.row_ptr[pr]; e < L.row_ptr[pr + 1]; ++e) A[(size_t)r * n + pos[L.col[e]]] += L.val[e];
+            }
+        }
+        std::vector<double> inv = gpu_inverse(n, A);
+        std::vector<int> bc(n);
+        for (int r = 0; r < n; ++r) bc[r] = (int)padded_index(nx, act[r]);
+        D.nbot = n;
+        D.bot_cells = h->upload(bc);
+        D.ainv = h->upload(inv);
+    }
+    (void)st;
+}
+
+void upload_rhs(mg_handle h) {
+    const Level &L = *h->levels[0];
+    const int nx = L.g.nx, ny = L.g.ny;
+    std::vector<int> ptr{0}, cell, gidx;
+    std::vector<double> coef;
+    std::vector<std::pair<int, double>> cells, gd;
+    for (int cl = 0; cl < nx * ny; ++cl) {
+        std::map<int, double> acc;
+        if (L.kind[cl] == 1) {
+            L.sfv_row(cl % nx, cl / nx, cells, gd);
+            for (auto &e : gd) acc[e.first] += e.second;
+        } else if (L.kind[cl] == 2 && L.g_of_cell[cl] >= 0) {
+            acc[L.g_of_cell[cl]] += L.beta_b[L.plg_row[cl]];
+        }
+        if (acc.empty()) continue;
+        cell.push_back((int)padded_index(nx, cl));
+        for (auto &kv : acc) {
+            gidx.push_back(kv.first);
+            coef.push_back(kv.second);
+        }
+        ptr.push_back((int)gidx.size());
+    }
+    h->nrhs = (int)cell.size();
+    h->rhs_ptr = h->upload(ptr);
+    h->rhs_cell = h->upload(cell);
+    h->rhs_gidx = h->upload(gidx);
+    h->rhs_coef = h->upload(coef);
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle (Algorithm 3)
+template <typename T>
+struct Prec;
+template <>
+struct Prec<double> {
+    static double *u(DevLevel &D, int k) { return D.u64[k]; }
+    static double *b(DevLevel &D) { return D.b64; }
+    static double *rplg(DevLevel &D) { return D.rplg64; }
+    static const double *fval(DevLevel &D) { return D.full_val64; }
+    static PlgDev<double> &P(DevLevel &D) { return D.P64; }
+};
+template <>
+struct Prec<float> {
+    static float *u(DevLevel &D, int k) { return D.u32[k]; }
+    static float *b(DevLevel &D) { return D.b32; }
+    static float *rplg(DevLevel &D) { return D.rplg32; }
+    static const float *fval(DevLevel &D) { return D.full_val32; }
+    static PlgDev<float> &P(DevLevel &D) { return D.P32; }
+};
+
+template <typename T>
+void smooth(mg_handle h, int l, hipStream_t st) {
+    DevLevel &D = h->dev[l];
+    T *uo = Prec<T>::u(D, D.cur), *un = Prec<T>::u(D, 1 - D.cur);
+    launch_jacobi<T>(D.args, uo, Prec<T>::b(D), un, D.mask, st);
+    launch_plg_solve<T>(Prec<T>::P(D), Prec<T>::b(D), un, st);
+    D.cur = 1 - D.cur;
+}
+
+template <typename T>
+void vcycle(mg_handle h, int l, hipStream_t st) {
+    DevLevel &D = h->dev[l];
+    const int last = (int)h->dev.size() - 1;
+    if (l == last) {
+        launch_bottom<T, T>(D.nbot, D.bot_cells, D.ainv, Prec<T>::b(D), Prec<T>::u(D, D.cur), st);
+        return;
+    }
+    for (int k = 0; k < h->opt.nu1; ++k) smooth<T>(h, l, st);
+    DevLevel &C = h->dev[l + 1];
+    T *u = Prec<T>::u(D, D.cur);
+    launch_plg_residual<T>(D.m, D.plg_cell, D.full_ptr, D.full_col, Prec<T>::fval(D), Prec<T>::b(D), u,
+                           Prec<T>::rplg(D), st);
+    launch_restrict<T>(D.args, C.args, u, Prec<T>::b(D), D.mask, D.plgidx, Prec<T>::rplg(D), C.mask, Prec<T>::b(C),
+                       Prec<T>::u(C, 0), D.ex_nt, D.ex_ptr, D.ex_target, D.ex_child, st);
+    C.cur = 0;
+    vcycle<T>(h, l + 1, st);
+    launch_prolong<T>(D.args, C.args, D.mask, C.mask, Prec<T>::u(C, C.cur), Prec<T>::u(D, D.cur), D.pex_n, D.pex_fine,
+                      D.pex_coarse, st);
+    for (int k = 0; k < h->opt.nu2; ++k) smooth<T>(h, l, st);
+}
+
+double device_absmax_finish(mg_handle h, int nblocks, hipStream_t st) {
+    launch_absmax(nblocks, h->partial, nullptr, h->partial + h->npartial - 1, 1, st);
+    HIPCHECK(hipMemcpyAsync(h->host_scalar, h->partial + h->npartial - 1, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    return *h->host_scalar;
+}
+
+double residual_norm(mg_handle h, int l, const double *u, const double *b, float *r32, double *r64, hipStream_t st) {
+    DevLevel &D = h->dev[l];
+    launch_plg_residual<double>(D.m, D.plg_cell, D.full_ptr, D.full_col, D.full_val64, b, u, D.rplg64, st);
+    int nb = launch_residual_norm(D.args, u, b, D.mask, D.plgidx, D.rplg64, r32, r64, h->partial, st);
+    return device_absmax_finish(h, nb, st);
+}
+
+mg_status guard(mg_handle h, const std::function<void()> &fn) {
+    try {
+        fn();
+        return MG_OK;
+    } catch (const status_error &e) {
+        if (h) h->last_error = e.what();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        return MG_ERR_OOM;
+    } catch (const std::exception &e) {
+        if (h) h->last_error = e.what();
+        return MG_ERR_INVALID_ARG;
+    }
+}
+
+void build_ghost_table() {
+    double gw[2][2][4];
+    for (int bc = 0; bc < 2; ++bc)
+        for (int d = 1; d <= 2; ++d) {
+            double w[5];
+            ghost_weights(bc == 0 ? MG_BC_DIRICHLET : MG_BC_NEUMANN, d, w);
+            for (int k = 0; k < 4; ++k) gw[bc][d - 1][k] = w[k];
+        }
+    upload_ghost_table(gw);
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+mg_status mg_default_options(mg_options *opt) {
+    if (!opt) return MG_ERR_INVALID_ARG;
+    opt->eps = 0.08;
+    opt->omega = 0.5;
+    opt->nu1 = 3;
+    opt->nu2 = 3;
+    opt->n_levels = 0;
+    opt->min_coarse = 16;
+    opt->precision = MG_FP64;
+    opt->max_iters = 100;
+    return MG_OK;
+}
+
+mg_status mg_setup(const mg_grid *grid, int n_curves, const mg_curve *curves, double a, double b, double c,
+                   const mg_options *opt, void *stream, mg_handle *out) {
+    if (!grid || !curves || !out || n_curves < 1) return MG_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!(b * b - 4 * a * c < 0) || !(a > 0 || a < 0) || std::isnan(a) || std::isnan(b) || std::isnan(c))
+        return MG_ERR_INVALID_ARG;
+    if (grid->nx < 4 || grid->ny < 4 || !(grid->h > 0) || (long long)grid->nx * grid->ny > (1LL << 28))
+        return MG_ERR_INVALID_ARG;
+    mg_options o;
+    mg_default_options(&o);
+    if (opt) o = *opt;
+    if (!(o.eps > 0 && o.eps < 1) || o.nu1 < 0 || o.nu2 < 0 || o.max_iters < 1 || o.min_coarse < 4 ||
+        (o.precision != MG_FP64 && o.precision != MG_MIXED) || o.n_levels < 0 || o.n_levels > 16)
+        return MG_ERR_INVALID_ARG;
+    for (int k = 0; k < n_curves; ++k) {
+        if (curves[k].n_seg < 1 || !curves[k].seg) return MG_ERR_INVALID_ARG;
+        for (int s = 0; s < curves[k].n_seg; ++s) {
+            const mg_segment &sg = curves[k].seg[s];
+            if ((sg.kind != MG_SEG_LINE && sg.kind != MG_SEG_ARC) || sg.bc < 0 || sg.bc > 2) return MG_ERR_INVALID_ARG;
+            for (double v : sg.p)
+                if (std::isnan(v)) return MG_ERR_INVALID_ARG;
+            if (k == 0 && sg.bc == MG_BC_ROBIN) return MG_ERR_UNSUPPORTED;
+        }
+    }
+    auto h = std::make_unique<mg_handle_s>();
+    hipStream_t st = (hipStream_t)stream;
+    mg_status rc = guard(h.get(), [&]() {
+        auto t0 = std::chrono::steady_clock::now();
+        HIPCHECK(hipGetDevice(&h->device));
+        h->opt = o;
+        h->a = a; h->b = b; h->c = c;
+        for (int k = 0; k < n_curves; ++k) {
+            std::vector<Seg> segs;
+            for (int s = 0; s < curves[k].n_seg; ++s) {
+                const mg_segment &sg = curves[k].seg[s];
+                Seg q;
+                q.kind = sg.kind;
+                for (int t = 0; t < 5; ++t) q.p[t] = sg.p[t];
+                q.bc = sg.bc;
+                q.al1 = sg.alpha1;
+                q.al2 = sg.alpha2;
+                segs.push_back(q);
+            }
+            h->curves.c.push_back(segs);
+        }
+        build_ghost_table();
+        mg_grid g = *grid;
+        while (true) {
+            auto L = std::make_unique<Level>();
+            L->g = g;
+            L->a = a; L->b = b; L->c = c;
+            L->curves = &h->curves;
+            try {
+                build_cutgrid(h->curves, g, o.eps, L->cg);
+                L->classify();
+                fit_level(h.get(), *L, st);
+            } catch (const status_error &e) {
+                if (h->levels.empty() || e.code != MG_ERR_GEOMETRY || o.n_levels) throw;
+                break;
+            }
+            h->levels.push_back(std::move(L));
+            if (o.n_levels && (int)h->levels.size() == o.n_levels) break;
+            if (g.nx % 2 || g.ny % 2 || g.nx / 2 < o.min_coarse || g.ny / 2 < o.min_coarse) {
+                if (o.n_levels) fail(MG_ERR_GEOMETRY, "cannot build the requested number of levels");
+                break;
+            }
+            if (h->levels.size() == 16) break;
+            g.h *= 2;
+            g.nx /= 2;
+            g.ny /= 2;
+        }
+        const int nl = (int)h->levels.size();
+        h->solvers.resize(nl);
+        for (int l = 0; l < nl; ++l) build_plg_solver(*h->levels[l], SEG_MAX, h->solvers[l]);
+        h->dev.resize(nl);
+        for (int l = 0; l < nl; ++l) upload_level(h.get(), l, l == nl - 1, st);
+        upload_rhs(h.get());
+        int maxtiles = 1;
+        for (auto &D : h->dev) maxtiles = std::max(maxtiles, ((D.args.nx + 63) / 64) * ((D.args.ny + 15) / 16));
+        h->npartial = std::max(maxtiles, 1024) + 1;
+        h->partial = h->alloc<double>(h->npartial);
+        HIPCHECK(hipHostMalloc((void **)&h->host_scalar, sizeof(double)));
+        HIPCHECK(hipDeviceSynchronize());
+        h->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    });
+    if (rc != MG_OK) {
+        mg_destroy(h.release());
+        return rc;
+    }
+    *out = h.release();
+    return MG_OK;
+}
+
+mg_status mg_rhs(mg_handle h, const double *f_dev, const double *g_dev, double *b_dev, void *stream) {
+    if (!h || !f_dev || !b_dev || (!g_dev && h->nrhs)) return MG_ERR_INVALID_ARG;
+    return guard(h, [&]() {
+        DevLevel &D = h->dev[0];
+        launch_rhs(D.ncells, D.mask, f_dev, b_dev, h->nrhs, h->rhs_ptr, h->rhs_cell, h->rhs_gidx, h->rhs_coef, g_dev,
+                   (hipStream_t)stream);
+        HIPCHECK(hipGetLastError());
+    });
+}
+
+mg_status mg_vcycle(mg_handle h, const double *b_dev, double *u_dev, void *stream) {
+    if (!h || !b_dev || !u_dev) return MG_ERR_INVALID_ARG;
+    return guard(h, [&]() {
+        hipStream_t st = (hipStream_t)stream;
+        DevLevel &D = h->dev[0];
+        double *keep_u = D.u64[0], *keep_b = D.b64;
+        D.u64[0] = u_dev;
+        D.b64 = const_cast<double *>(b_dev);
+        D.cur = 0;
+        vcycle<double>(h, 0, st);
+        if (D.cur != 0) HIPCHECK(hipMemcpyAsync(u_dev, D.u64[1], D.ncells * 8, hipMemcpyDeviceToDevice, st));
+        D.u64[0] = keep_u;
+        D.b64 = keep_b;
+        D.cur = 0;
+        HIPCHECK(hipGetLastError());
+    });
+}
+
+mg_status mg_smooth(mg_handle h, int level, const double *b_dev, double *u_dev, void *stream) {
+    if (!h || !b_dev || !u_dev || level < 0 || level >= (int)h->dev.size()) return MG_ERR_INVALID_ARG;
+    return guard(h, [&]() {
+        hipStream_t st = (hipStream_t)stream;
+        DevLevel &D = h->dev[level];
+        launch_jacobi<double>(D.args, u_dev, b_dev, D.u64[1], D.mask, st);
+        launch_plg_solve<double>(D.P64, b_dev, D.u64[1], st);
+        HIPCHECK(hipMemcpyAsync(u_dev, D.u64[1], D.ncells * 8, hipMemcpyDeviceToDevice, st));
+        HIPCHECK(hipGetLastError());
+    });
+}
+
+mg_status mg_residual(mg_handle h, int level, const double *b_dev, const double *u_dev, double *r_dev, double *rnorm,
+                      void *stream) {
+    if (!h || !b_dev || !u_dev || level < 0 || level >= (int)h->dev.size()) return MG_ERR_INVALID_ARG;
+    return guard(h, [&]() {
+        double v = residual_norm(h, level, u_dev, b_dev, nullptr, r_dev, (hipStream_t)stream);
+        if (rnorm) *rnorm = v;
+    });
+}
+
+mg_status mg_solve(mg_handle h, const double *f_dev, const double *g_dev, double *u_dev, double tol, void *stream,
+                   int *iters, double *rel_residual) {
+    if (!h || !f_dev || !u_dev || !(tol > 0) || (!g_dev && h->nrhs)) return MG_ERR_INVALID_ARG;
+    mg_status result = MG_OK;
+    mg_status rc = guard(h, [&]() {
+        hipStream_t st = (hipStream_t)stream;
+        DevLevel &D = h->dev[0];
+        launch_rhs(D.ncells, D.mask, f_dev, D.b64, h->nrhs, h->rhs_ptr, h->rhs_cell, h->rhs_gidx, h->rhs_coef, g_dev, st);
+        int nb = 1024;
+        launch_absmax((int)D.ncells, D.b64, D.mask, h->partial, nb, st);
+        double bnorm = device_absmax_finish(h, nb, st);
+        if (bnorm == 0.0) bnorm = 1.0;
+        const bool mixed = h->opt.precision == MG_MIXED;
+        double *keep_u = D.u64[0];
+        D.u64[0] = u_dev;
+        int it = 0, grow = 0;
+        double rel = residual_norm(h, 0, u_dev, D.b64, mixed ? D.b32 : nullptr, nullptr, st) / bnorm;
+        double prev = rel;
+        while (rel > tol && it < h->opt.max_iters) {
+            if (mixed) {
+                HIPCHECK(hipMemsetAsync(D.u32[0], 0, D.ncells * sizeof(float), st));
+                D.cur = 0;
+                vcycle<float>(h, 0, st);
+                launch_add_correction(D.ncells, D.mask, D.u32[D.cur], u_dev, st);
+                D.cur = 0;
+            } else {
+                D.cur = 0;
+                vcycle<double>(h, 0, st);
+                if (D.cur != 0) HIPCHECK(hipMemcpyAsync(u_dev, D.u64[1], D.ncells * 8, hipMemcpyDeviceToDevice, st));
+                D.cur = 0;
+            }
+            ++it;
+            rel = residual_norm(h, 0, u_dev, D.b64, mixed ? D.b32 : nullptr, nullptr, st) / bnorm;
+            if (std::isnan(rel)) { result = MG_ERR_DIVERGED; break; }
+            grow = rel > prev ? grow + 1 : 0;
+            if (grow >= 3) { result = MG_ERR_DIVERGED; break; }
+            prev = rel;
+        }
+        launch_zero_inactive(D.ncells, D.mask, u_dev, st);
+        HIPCHECK(hipStreamSynchronize(st));
+        D.u64[0] = keep_u;
+        if (result == MG_OK && rel > tol) result = MG_ERR_NO_CONVERGENCE;
+        if (iters) *iters = it;
+        if (rel_residual) *rel_residual = rel;
+    });
+    return rc != MG_OK ? rc : result;
+}
+
+mg_status mg_query(mg_handle h, mg_info *info) {
+    if (!h || !info) return MG_ERR_INVALID_ARG;
+    std::memset(info, 0, sizeof(*info));
+    info->n_levels = (int)h->levels.size();
+    for (int l = 0; l < info->n_levels && l < 16; ++l) {
+        const Level &L = *h->levels[l];
+        info->nx[l] = L.g.nx;
+        info->ny[l] = L.g.ny;
+        info->n_active[l] = L.n_active;
+        info->n_plg[l] = (int)L.plg_cells.size();
+        info->n_sep[l] = h->solvers[l].nsep;
+        info->nnz_plg += (long long)L.col.size();
+    }
+    info->n_face = h->levels[0]->n_face;
+    info->n_irr = h->levels[0]->n_irr;
+    info->device_bytes = h->bytes;
+    info->setup_seconds = h->setup_seconds;
+    return MG_OK;
+}
+
+mg_status mg_export_level(mg_handle h, int level, int *kind, int *n_plg, long long *nnz, int *row_ptr, int *col,
+                          double *val, double *beta_b) {
+    if (!h || level < 0 || level >= (int)h->levels.size()) return MG_ERR_INVALID_ARG;
+    const Level &L = *h->levels[level];
+    if (kind) for (size_t k = 0; k < L.kind.size(); ++k) kind[k] = L.kind[k];
+    if (n_plg) *n_plg = (int)L.plg_cells.size();
+    if (nnz) *nnz = (long long)L.col.size();
+    if (col) {
+        if (!row_ptr || !val) return MG_ERR_INVALID_ARG;
+        for (size_t k = 0; k < L.row_ptr.size(); ++k) row_ptr[k] = L.row_ptr[k];
+        for (size_t k = 0; k < L.col.size(); ++k) {
+            col[k] = L.col[k];
+            val[k] = L.val[k];
+        }
+        if (beta_b) for (size_t k = 0; k < L.beta_b.size(); ++k) beta_b[k] = L.beta_b[k];
+    }
+    return MG_OK;
+}
+
+// Quadrature for cell averages over irregular cells: Green's theorem,
+// ∬ F = ∮ G dy with G(x, y) the integral of F(., y) from the cell-centre
+// abscissa to x; Gauss-Legendre along each boundary piece (16 points on curve
+// pieces, 8 on cell sides) times 16 inner points; full grid cells absorbed by
+// a merge use an 8 x 8 tensor rule.  Weights are divided by the cell volume.
+mg_status mg_cell_quadrature(mg_handle h, int *n, long long *nnodes, int *cell, long long *ptr, double *x, double *y,
+                             double *w) {
+    if (!h || !n || !nnodes) return MG_ERR_INVALID_ARG;
+    const Level &L = *h->levels[0];
+    const CutGrid &cg = L.cg;
+    std::vector<double> g16x, g16w, g8x, g8w;
+    gauss_legendre(16, g16x, g16w);
+    gauss_legendre(8, g8x, g8w);
+    const double hh = L.g.h;
+    long long cnt = 0;
+    int ncell = 0;
+    for (size_t s = 0; s < cg.irr_cells.size(); ++s) {
+        const int c0 = cg.irr_cells[s];
+        const CellData &d = cg.irr[s];
+        if (!cg.active[c0]) continue;
+        const double vol = d.mom[0] * hh * hh;
+        if (ptr && x) ptr[ncell] = cnt;
+        if (cell && x) cell[ncell] = c0;
+        auto emit = [&](double px, double py, double pw) {
+            if (x) {
+                x[cnt] = px;
+                y[cnt] = py;
+                w[cnt] = pw / vol;
+            }
+            ++cnt;
+        };
+        for (int ci : d.members) {
+            const Comp &c = cg.comps[ci];
+            const double X0 = L.g.x0 + c.ci * hh, Y0 = L.g.y0 + c.cj * hh, xr = X0 + 0.5 * hh;
+            if (c.full) {
+                for (int a = 0; a < 8; ++a)
+                    for (int b = 0; b < 8; ++b)
+                        emit(X0 + (0.5 + 0.5 * g8x[a]) * hh, Y0 + (0.5 + 0.5 * g8x[b]) * hh, 0.25 * hh * hh * g8w[a] * g8w[b]);
+                continue;
+            }
+            for (const LoopItem &it : c.items) {
+                if (!it.is_edge) {
+                    const Seg &sg = h->curves.c[it.piece.curve][it.piece.seg];
+                    for (int k = 0; k < 16; ++k) {
+                        double t = 0.5 * (it.piece.tb - it.piece.ta) * g16x[k] + 0.5 * (it.piece.ta + it.piece.tb);
+                        double px, py, dx, dy;
+                        sg.point(t, px, py);
+                        sg.deriv(t, dx, dy);
+                        double ow = 0.5 * (it.piece.tb - it.piece.ta) * g16w[k] * dy;
+                        double half = 0.5 * (px - xr);
+                        for (int q = 0; q < 16; ++q) emit(xr + half * (1.0 + g16x[q]), py, ow * g16w[q] * half);
+                    }
+                } else if (it.side == 1 || it.side == 3) {
+                    double px = it.side == 1 ? X0 + hh : X0;
+                    double ya = it.side == 1 ? Y0 + it.s0 * hh : Y0 + (1.0 - it.s0) * hh;
+                    double yb = it.side == 1 ? Y0 + it.s1 * hh : Y0 + (1.0 - it.s1) * hh;
+                    for (int k = 0; k < 8; ++k) {
+                        double py = 0.5 * (yb - ya) * g8x[k] + 0.5 * (ya + yb);
+                        double ow = 0.5 * (yb - ya) * g8w[k];
+                        double half = 0.5 * (px - xr);
+                        for (int q = 0; q < 16; ++q) emit(xr + half * (1.0 + g16x[q]), py, ow * g16w[q] * half);
+                    }
+                }
+            }
+        }
+        ++ncell;
+    }
+    if (ptr && x) ptr[ncell] = cnt;
+    *n = ncell;
+    *nnodes = cnt;
+    return MG_OK;
+}
+
+// Quadrature for the boundary data g: 8 Gauss points per box face, 16 per
+// curve piece of an irregular cell, weights normalised to 1 per entry.
+mg_status mg_boundary_quadrature(mg_handle h, int *n, long long *nnodes, long long *ptr, double *x, double *y,
+                                 double *w, double *nxo, double *nyo, int *bc, double *alpha1, double *alpha2) {
+    if (!h || !n || !nnodes) return MG_ERR_INVALID_ARG;
+    const Level &L = *h->levels[0];
+    const CutGrid &cg = L.cg;
+    const int nx = L.g.nx, ny = L.g.ny;
+    const double hh = L.g.h;
+    std::vector<double> g16x, g16w, g8x, g8w;
+    gauss_legendre(16, g16x, g16w);
+    gauss_legendre(8, g8x, g8w);
+    long long cnt = 0;
+    int entry = 0;
+    auto emit = [&](double px, double py, double pw, double n0, double n1, int b, double a1, double a2) {
+        if (x) {
+            x[cnt] = px; y[cnt] = py; w[cnt] = pw; nxo[cnt] = n0; nyo[cnt] = n1;
+            bc[cnt] = b; alpha1[cnt] = a1; alpha2[cnt] = a2;
+        }
+        ++cnt;
+    };
+    const double x1 = L.g.x0 + nx * hh, y1 = L.g.y0 + ny * hh;
+    // bottom, top, left, right faces
+    for (int side : {0, 2, 3, 1}) {
+        const Seg &sg = h->curves.c[0][side];
+        int m = (side == 0 || side == 2) ? nx : ny;
+        for (int k = 0; k < m; ++k) {
+            if (ptr && x) ptr[entry] = cnt;
+            for (int q = 0; q < 8; ++q) {
+                double s = L.g.x0 + (k + 0.5 + 0.5 * g8x[q]) * hh, tt = L.g.y0 + (k + 0.5 + 0.5 * g8x[q]) * hh;
+                if (side == 0) emit(s, L.g.y0, 0.5 * g8w[q], 0.0, -1.0, sg.bc, sg.al1, sg.al2);
+                else if (side == 2) emit(s, y1, 0.5 * g8w[q], 0.0, 1.0, sg.bc, sg.al1, sg.al2);
+                else if (side == 3) emit(L.g.x0, tt, 0.5 * g8w[q], -1.0, 0.0, sg.bc, sg.al1, sg.al2);
+                else emit(x1, tt, 0.5 * g8w[q], 1.0, 0.0, sg.bc, sg.al1, sg.al2);
+            }
+            ++entry;
+        }
+    }
+    for (int cl = 0; cl < nx * ny; ++cl) {
+        if (L.g_of_cell[cl] < 0) continue;
+        const CellData &d = cg.irr[cg.irr_slot[cl]];
+        if (ptr && x) ptr[entry] = cnt;
+        double len = 0.0;
+        for (auto &bp : d.bp) {
+            const Seg &sg = h->curves.c[bp.curve][bp.seg];
+            for (int q = 0; q < 16; ++q) {
+                double t = 0.5 * (bp.tb - bp.ta) * g16x[q] + 0.5 * (bp.ta + bp.tb), dx, dy;
+                sg.deriv(t, dx, dy);
+                len += 0.5 * (bp.tb - bp.ta) * g16w[q] * std::hypot(dx, dy);
+            }
+        }
+        for (auto &bp : d.bp) {
+            const Seg &sg = h->curves.c[bp.curve][bp.seg];
+            for (int q = 0; q < 16; ++q) {
+                double t = 0.5 * (bp.tb - bp.ta) * g16x[q] + 0.5 * (bp.ta + bp.tb), px, py, dx, dy;
+                sg.point(t, px, py);
+                sg.deriv(t, dx, dy);
+                double sp = std::hypot(dx, dy);
+                emit(px, py, 0.5 * (bp.tb - bp.ta) * g16w[q] * sp / len, dy / sp, -dx / sp, sg.bc, sg.al1, sg.al2);
+            }
+        }
+        ++entry;
+    }
+    if (ptr && x) ptr[entry] = cnt;
+    *n = entry;
+    *nnodes = cnt;
+    return MG_OK;
+}
+
+mg_status mg_destroy(mg_handle h) {
+    if (!h) return MG_OK;
+    for (void *p : h->allocs) (void)hipFree(p);
+    if (h->host_scalar) (void)hipHostFree(h->host_scalar);
+    delete h;
+    return MG_OK;
+}
+
+const char *mg_error_string(mg_status s) {
+    switch (s) {
+        case MG_OK: return "ok";
+        case MG_ERR_INVALID_ARG: return "invalid argument";
+        case MG_ERR_GEOMETRY: return "the grid does not resolve the geometry";
+        case MG_ERR_SINGULAR: return "singular matrix";
+        case MG_ERR_NO_CONVERGENCE: return "no convergence within max_iters";
+        case MG_ERR_DIVERGED: return "the iteration diverged";
+        case MG_ERR_OOM: return "out of device memory";
+        case MG_ERR_HIP: return "HIP runtime error";
+        case MG_ERR_UNSUPPORTED: return "unsupported configuration";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,408 @@
+// One level's linear system (Section 4): SFV/PLG classification
+// (Definition 4.1), SFV rows with ghost cells eliminated (Section 4.1), poised
+// lattices (Definitions 4.2-4.3) and the inputs of the weighted minimum-norm
+// fits (eqs. (4.10)-(4.18)); the fits themselves run on the GPU.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <unordered_map>
+
+#include "level.hpp"
+
+namespace mgc {
+
+// ---------------------------------------------------------------------------
+// ghost weights (Section 4.1): (w_i, w_{i-1}, w_{i-2}, w_{i-3}, w_face) for
+// the ghost 1 or 2 cells beyond the face.  The second Dirichlet face weight is
+// 300/12: the value that reproduces all polynomials of degree <= 4.
+void ghost_weights(int bc, int which, double w[5]) {
+    static const double D[2][5] = {{-77.0 / 12, 43.0 / 12, -17.0 / 12, 3.0 / 12, 60.0 / 12},
+                                   {-505.0 / 12, 335.0 / 12, -145.0 / 12, 27.0 / 12, 300.0 / 12}};
+    static const double N[2][5] = {{5.0 / 10, 9.0 / 10, -5.0 / 10, 1.0 / 10, 12.0 / 10},
+                                   {-15.0 / 2, 29.0 / 2, -15.0 / 2, 3.0 / 2, 12.0 / 2}};
+    const double *src = (bc == MG_BC_DIRICHLET) ? D[which - 1] : N[which - 1];
+    for (int k = 0; k < 5; ++k) w[k] = src[k];
+}
+
+// Corner ghost (beyond the x-face by m cells and the y-face by k cells):
+// the face-ghost formula of one face applied to the ghosts of the other,
+// averaged over both orders; the face data beyond the corner are the cubic
+// extrapolation of that face's data along the face.
+void corner_weights(int bcx, int bcy, int m, int k, double h, double wu[4][4], double wgy[4], double wgx[4]) {
+    static const double E[2][4] = {{4, -6, 4, -1}, {10, -20, 15, -4}};
+    double gx[5], gy[5];
+    ghost_weights(bcx, m, gx);
+    ghost_weights(bcy, k, gy);
+    double sx = bcx == MG_BC_NEUMANN ? h : 1.0, sy = bcy == MG_BC_NEUMANN ? h : 1.0;
+    for (int p = 0; p < 4; ++p)
+        for (int q = 0; q < 4; ++q) wu[p][q] = gx[p] * gy[q];
+    for (int p = 0; p < 4; ++p) wgy[p] = 0.5 * gy[4] * sy * (gx[p] + E[m - 1][p]);
+    for (int q = 0; q < 4; ++q) wgx[q] = 0.5 * gx[4] * sx * (gy[q] + E[k - 1][q]);
+}
+
+// SFV stencil of L = a d_xx + b d_xy + c d_yy, eq. (4.7) and the mixed term
+void sfv_terms(double a, double b, double c, double h, std::vector<std::array<double, 3>> &terms) {
+    static const double d1[5] = {1.0 / 12, -8.0 / 12, 0.0, 8.0 / 12, -1.0 / 12};
+    static const double d2[5] = {-1.0 / 12, 16.0 / 12, -30.0 / 12, 16.0 / 12, -1.0 / 12};
+    double w[5][5] = {};
+    for (int m = 0; m < 5; ++m) {
+        w[m][2] += a * d2[m];
+        w[2][m] += c * d2[m];
+    }
+    if (b != 0.0)
+        for (int m1 = 0; m1 < 5; ++m1)
+            for (int m2 = 0; m2 < 5; ++m2) w[m1][m2] += b * d1[m1] * d1[m2];
+    terms.clear();
+    for (int m1 = 0; m1 < 5; ++m1)
+        for (int m2 = 0; m2 < 5; ++m2)
+            if (w[m1][m2] != 0.0) terms.push_back({(double)(m1 - 2), (double)(m2 - 2), w[m1][m2] / (h * h)});
+}
+
+int Level::face_index(int side, int k) const {
+    switch (side) {
+        case 0: return k;
+        case 2: return g.nx + k;
+        case 3: return 2 * g.nx + k;
+        default: return 2 * g.nx + g.ny + k;
+    }
+}
+
+// Row of an SFV cell with ghosts eliminated: coefficients on interior cells
+// (cells[]) and on boundary data (gidx[]).
+void Level::sfv_row(int i, int j, std::vector<std::pair<int, double>> &cells,
+                    std::vector<std::pair<int, double>> &gdat) const {
+    const int nx = g.nx, ny = g.ny;
+    const double h = g.h;
+    std::vector<std::array<double, 3>> terms;
+    sfv_terms(a, b, c, h, terms);
+    cells.clear();
+    gdat.clear();
+    for (auto &t : terms) {
+        int qi = i + (int)t[0], qj = j + (int)t[1];
+        double w = t[2];
+        bool outx = qi < 0 || qi >= nx, outy = qj < 0 || qj >= ny;
+        if (!outx && !outy) {
+            cells.push_back({qj * nx + qi, w});
+        } else if (outx && outy) {
+            int xside = qi < 0 ? 3 : 1, yside = qj < 0 ? 0 : 2;
+            int m = qi < 0 ? -qi : qi - nx + 1, k = qj < 0 ? -qj : qj - ny + 1;
+            double wu[4][4], wgy[4], wgx[4];
+            corner_weights(cg.box_bc[xside], cg.box_bc[yside], m, k, h, wu, wgy, wgx);
+            for (int p = 0; p < 4; ++p) {
+                int col = xside == 3 ? p : nx - 1 - p;
+                for (int q = 0; q < 4; ++q) {
+                    int row = yside == 0 ? q : ny - 1 - q;
+                    cells.push_back({row * nx + col, w * wu[p][q]});
+                }
+                gdat.push_back({face_index(yside, col), w * wgy[p]});
+                int row = yside == 0 ? p : ny - 1 - p;
+                gdat.push_back({face_index(xside, row), w * wgx[p]});
+            }
+        } else {
+            int side, depth, along;
+            if (qj < 0) { side = 0; depth = -qj; along = qi; }
+            else if (qj >= ny) { side = 2; depth = qj - ny + 1; along = qi; }
+            else if (qi < 0) { side = 3; depth = -qi; along = qj; }
+            else { side = 1; depth = qi - nx + 1; along = qj; }
+            double gw[5];
+            int bc = cg.box_bc[side];
+            ghost_weights(bc, depth, gw);
+            for (int k = 0; k < 4; ++k) {
+                int ci, cj;
+                if (side == 0) { ci = along; cj = k; }
+                else if (side == 2) { ci = along; cj = ny - 1 - k; }
+                else if (side == 3) { ci = k; cj = along; }
+                else { ci = nx - 1 - k; cj = along; }
+                cells.push_back({cj * nx + ci, w * gw[k]});
+            }
+            gdat.push_back({face_index(side, along), w * gw[4] * (bc == MG_BC_NEUMANN ? h : 1.0)});
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Definition 4.1
+void Level::classify() {
+    const int nx = g.nx, ny = g.ny;
+    if (nx < 4 || ny < 4) fail(MG_ERR_GEOMETRY, "grid too small for ghost cells");
+    const auto &R = cg.regular;
+    for (int j = 0; j < ny; ++j)
+        for (int k = 0; k < 4; ++k)
+            if (!R[(size_t)j * nx + k] || !R[(size_t)j * nx + nx - 1 - k])
+                fail(MG_ERR_GEOMETRY, "a box face is not extendable");
+    for (int i = 0; i < nx; ++i)
+        for (int k = 0; k < 4; ++k)
+            if (!R[(size_t)k * nx + i] || !R[(size_t)(ny - 1 - k) * nx + i])
+                fail(MG_ERR_GEOMETRY, "a box face is not extendable");
+    // every position outside the box within 2 cells is a (face or corner) ghost
+    auto ok = [&](int i, int j) {
+        if (i >= 0 && i < nx && j >= 0 && j < ny) return (bool)R[(size_t)j * nx + i];
+        return i >= -2 && i < nx + 2 && j >= -2 && j < ny + 2;
+    };
+    kind.assign((size_t)nx * ny, 0);
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            size_t cell = (size_t)j * nx + i;
+            if (!cg.active[cell]) continue;
+            bool sfv = true;
+            if (b == 0.0) {
+                for (int m = -2; m <= 2 && sfv; ++m) sfv = ok(i + m, j) && ok(i, j + m);
+            } else {
+                for (int m1 = -2; m1 <= 2 && sfv; ++m1)
+                    for (int m2 = -2; m2 <= 2 && sfv; ++m2) sfv = ok(i + m1, j + m2);
+            }
+            kind[cell] = sfv ? 1 : 2;
+        }
+    plg_cells.clear();
+    plg_row.assign((size_t)nx * ny, -1);
+    for (int cell = 0; cell < nx * ny; ++cell)
+        if (kind[cell] == 2) {
+            plg_row[cell] = (int)plg_cells.size();
+            plg_cells.push_back(cell);
+        }
+    n_active = 0;
+    for (auto v : cg.active) n_active += v ? 1 : 0;
+    n_face = 2 * nx + 2 * ny;
+    g_of_cell.assign((size_t)nx * ny, -1);
+    n_irr = 0;
+    for (int cell = 0; cell < nx * ny; ++cell)
+        if (cg.active[cell] && !cg.regular[cell]) g_of_cell[cell] = n_face + n_irr++;
+}
+
+// ---------------------------------------------------------------------------
+// lattice selection
+namespace {
+
+constexpr uint64_t PRIME = (1ULL << 61) - 1;
+
+uint64_t mulmod(uint64_t a, uint64_t b) { return (uint64_t)((unsigned __int128)a * b % PRIME); }
+uint64_t powmod(uint64_t a, uint64_t e) {
+    uint64_t r = 1;
+    while (e) {
+        if (e & 1) r = mulmod(r, a);
+        a = mulmod(a, a);
+        e >>= 1;
+    }
+    return r;
+}
+uint64_t tomod(long long v) {
+    long long r = v % (long long)PRIME;
+    return r < 0 ? (uint64_t)(r + (long long)PRIME) : (uint64_t)r;
+}
+
+// Incremental echelon form of point-sample rows [d^alpha] modulo the prime
+// 2^61 - 1.  Rows independent modulo a prime are independent over the
+// rationals; the converse fails only if the prime divides a nonzero minor of
+// integers below 4^60, which does not happen for these small lattices.
+struct Echelon {
+    std::vector<std::pair<int, std::array<uint64_t, NB>>> rows;
+    bool try_add(int dx, int dy) {
+        std::array<uint64_t, NB> v;
+        for (int k = 0; k < NB; ++k) {
+            long long t = 1;
+            for (int a = 0; a < MONO_P[k]; ++a) t *= dx;
+            for (int b = 0; b < MONO_Q[k]; ++b) t *= dy;
+            v[k] = tomod(t);
+        }
+        for (auto &pr : rows) {
+            int pv = pr.first;
+            if (v[pv] == 0) continue;
+            uint64_t f = mulmod(v[pv], powmod(pr.second[pv], PRIME - 2));
+            for (int k = 0; k < NB; ++k) v[k] = (v[k] + PRIME - mulmod(f, pr.second[k])) % PRIME;
+        }
+        for (int k = 0; k < NB; ++k)
+            if (v[k]) {
+                rows.push_back({k, v});
+                return true;
+            }
+        return false;
+    }
+};
+
+double angle_of(int x, int y) {
+    double t = std::atan2((double)y, (double)x);
+    if (t < 0) t += 2.0 * M_PI;
+    return t;
+}
+
+// LU solve with partial pivoting, n <= 15
+bool dense_solve(int n, double *A, double *b) {
+    std::vector<int> piv(n);
+    for (int k = 0; k < n; ++k) {
+        int p = k;
+        for (int r = k + 1; r < n; ++r)
+            if (std::fabs(A[r * n + k]) > std::fabs(A[p * n + k])) p = r;
+        if (A[p * n + k] == 0.0) return false;
+        if (p != k) {
+            for (int c = 0; c < n; ++c) std::swap(A[k * n + c], A[p * n + c]);
+            std::swap(b[k], b[p]);
+        }
+        for (int r = k + 1; r < n; ++r) {
+            double f = A[r * n + k] / A[k * n + k];
+            for (int c = k; c < n; ++c) A[r * n + c] -= f * A[k * n + c];
+            b[r] -= f * b[k];
+        }
+    }
+    for (int k = n - 1; k >= 0; --k) {
+        double s = b[k];
+        for (int c = k + 1; c < n; ++c) s -= A[k * n + c] * b[c];
+        b[k] = s / A[k * n + k];
+    }
+    return true;
+}
+
+// ||beta||^2_{W^{-1}} of the full-cell fit on a lattice (eqs. (4.14), (4.17))
+double regular_fit_norm(const std::vector<std::array<int, 2>> &lat, double a, double b, double c) {
+    double full[NB];
+    full_moments(full);
+    double M[NB * NB], rhs[NB];
+    for (int k = 0; k < NB; ++k) {
+        double sh[NB];
+        shift_moments(full, lat[k][0], lat[k][1], sh);
+        for (int r = 0; r < NB; ++r) M[r * NB + k] = sh[r];
+    }
+    for (int r = 0; r < NB; ++r) {
+        int p = MONO_P[r], q = MONO_Q[r];
+        double s = 0.0;
+        if (p >= 2) s += a * p * (p - 1) * full[mono_index(p - 2, q)];
+        if (p >= 1 && q >= 1) s += b * p * q * full[mono_index(p - 1, q - 1)];
+        if (q >= 2) s += c * q * (q - 1) * full[mono_index(p, q - 2)];
+        rhs[r] = s;
+    }
+    if (!dense_solve(NB, M, rhs)) return INFINITY;
+    double v = 0.0;
+    for (int k = 0; k < NB; ++k) v += std::max(std::hypot((double)lat[k][0], (double)lat[k][1]), 0.5) * rhs[k] * rhs[k];
+    return v;
+}
+
+}  // namespace
+
+// Lattice S_PLG(i): K = active cells of the 7x7 box centred at i (9x9 if no
+// poised subset exists).  For each of the 8 grid symmetries g, take nodes
+// nearest-first by (|d|^2, angle of g(d) in [0, 2pi)) when they raise the
+// exact rank of the point-sample matrix [d^alpha], |alpha| <= 4, until 15.
+// Keep the lattice of smallest full-cell ||beta||_{W^{-1}}; ties within a
+// relative 1e-9 keep the earlier symmetry.
+std::vector<std::array<int, 2>> Level::lattice(int i, int j, LatticeMemo &memo) const {
+    const int nx = g.nx, ny = g.ny;
+    __uint128_t key = 0;
+    for (int dy = -4; dy <= 4; ++dy)
+        for (int dx = -4; dx <= 4; ++dx) {
+            int qi = i + dx, qj = j + dy;
+            bool act = qi >= 0 && qi < nx && qj >= 0 && qj < ny && cg.active[(size_t)qj * nx + qi];
+            key = (key << 1) | (act ? 1 : 0);
+        }
+    auto it = memo.find(key);
+    if (it != memo.end()) return it->second;
+    static const int SYM[8][4] = {{1, 0, 0, 1}, {0, -1, 1, 0}, {-1, 0, 0, -1}, {0, 1, -1, 0},
+                                  {1, 0, 0, -1}, {0, 1, 1, 0}, {-1, 0, 0, 1}, {0, -1, -1, 0}};
+    std::vector<std::array<int, 2>> best;
+    double bestv = 0.0;
+    for (int half : {3, 4}) {
+        std::vector<std::array<int, 2>> box;
+        for (int dy = -half; dy <= half; ++dy)
+            for (int dx = -half; dx <= half; ++dx) {
+                int qi = i + dx, qj = j + dy;
+                if (qi >= 0 && qi < nx && qj >= 0 && qj < ny && cg.active[(size_t)qj * nx + qi]) box.push_back({dx, dy});
+            }
+        if ((int)box.size() < NB) continue;
+        for (auto &s : SYM) {
+            std::vector<std::pair<std::pair<int, double>, std::array<int, 2>>> ord;
+            for (auto &d : box)
+                ord.push_back({{d[0] * d[0] + d[1] * d[1], angle_of(s[0] * d[0] + s[1] * d[1], s[2] * d[0] + s[3] * d[1])}, d});
+            std::sort(ord.begin(), ord.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
+            Echelon ech;
+            std::vector<std::array<int, 2>> lat;
+            for (auto &o : ord) {
+                if (ech.try_add(o.second[0], o.second[1])) lat.push_back(o.second);
+                if ((int)lat.size() == NB) break;
+            }
+            if ((int)lat.size() < NB) continue;
+            double v = regular_fit_norm(lat, a, b, c);
+            if (best.empty() || v < bestv * (1.0 - 1e-9)) {
+                best = lat;
+                bestv = v;
+            }
+        }
+        if (!best.empty()) break;
+    }
+    if (best.empty()) fail(MG_ERR_GEOMETRY, "no poised lattice for a PLG cell");
+    memo[key] = best;
+    return best;
+}
+
+// ---------------------------------------------------------------------------
+// fit inputs: M (15 x ncol, column-major per cell), phibar, weights
+void Level::fit_inputs(std::vector<double> &Mall, std::vector<double> &phi, std::vector<double> &wall,
+                       std::vector<int> &ncol) {
+    const int nx = g.nx;
+    const double h = g.h;
+    const int m = (int)plg_cells.size();
+    Mall.assign((size_t)m * NB * (NB + 1), 0.0);
+    phi.assign((size_t)m * NB, 0.0);
+    wall.assign((size_t)m * (NB + 1), 0.0);
+    ncol.assign(m, NB);
+    lattices.resize(m);
+    LatticeMemo memo;
+    std::vector<double> gx, gw;
+    gauss_legendre(16, gx, gw);
+    for (int r = 0; r < m; ++r) {
+        int cell = plg_cells[r];
+        int i = cell % nx, j = cell / nx;
+        lattices[r] = lattice(i, j, memo);
+        double *M = &Mall[(size_t)r * NB * (NB + 1)];
+        for (int k = 0; k < NB; ++k) {
+            int qi = i + lattices[r][k][0], qj = j + lattices[r][k][1];
+            double mom[NB], sh[NB];
+            cell_moments(cg, qi, qj, mom);
+            shift_moments(mom, lattices[r][k][0], lattices[r][k][1], sh);
+            for (int q = 0; q < NB; ++q) M[(size_t)k * NB + q] = sh[q] / mom[0];
+            wall[(size_t)r * (NB + 1) + k] = std::max(std::hypot((double)lattices[r][k][0], (double)lattices[r][k][1]), 0.5);
+        }
+        double mom[NB];
+        cell_moments(cg, i, j, mom);
+        for (int q = 0; q < NB; ++q) {
+            int p = MONO_P[q], qq = MONO_Q[q];
+            double s = 0.0;
+            if (p >= 2) s += a * p * (p - 1) * mom[mono_index(p - 2, qq)];
+            if (p >= 1 && qq >= 1) s += b * p * qq * mom[mono_index(p - 1, qq - 1)];
+            if (qq >= 2) s += c * qq * (qq - 1) * mom[mono_index(p, qq - 2)];
+            phi[(size_t)r * NB + q] = s / mom[0] / (h * h);
+        }
+        if (!cg.regular[cell]) {
+            // boundary column <<N phi_alpha>>_{B_i}
+            double xc = g.x0 + (i + 0.5) * h, yc = g.y0 + (j + 0.5) * h;
+            double tot[NB] = {}, len = 0.0;
+            const CellData &d = cg.irr[cg.irr_slot[cell]];
+            for (auto &bp : d.bp) {
+                const Seg &s = curves->c[bp.curve][bp.seg];
+                for (int n = 0; n < 16; ++n) {
+                    double t = 0.5 * (bp.tb - bp.ta) * gx[n] + 0.5 * (bp.ta + bp.tb);
+                    double x, y, dx, dy;
+                    s.point(t, x, y);
+                    s.deriv(t, dx, dy);
+                    double sp = std::hypot(dx, dy);
+                    double ds = 0.5 * (bp.tb - bp.ta) * gw[n] * sp;
+                    double nxv = dy / sp, nyv = -dx / sp;
+                    double X = (x - xc) / h, Y = (y - yc) / h;
+                    for (int q = 0; q < NB; ++q) {
+                        int p = MONO_P[q], qq = MONO_Q[q];
+                        double ph = std::pow(X, p) * std::pow(Y, qq);
+                        double gxv = p >= 1 ? p * std::pow(X, p - 1) * std::pow(Y, qq) / h : 0.0;
+                        double gyv = qq >= 1 ? qq * std::pow(X, p) * std::pow(Y, qq - 1) / h : 0.0;
+                        double dn = gxv * nxv + gyv * nyv;
+                        double val = s.bc == MG_BC_DIRICHLET ? ph : (s.bc == MG_BC_NEUMANN ? dn : s.al1 * ph + s.al2 * dn);
+                        tot[q] += ds * val;
+                    }
+                    len += ds;
+                }
+            }
+            for (int q = 0; q < NB; ++q) M[(size_t)NB * NB + q] = tot[q] / len;
+            wall[(size_t)r * (NB + 1) + NB] = 0.5;
+            ncol[r] = NB + 1;
+        }
+    }
+}
+
+}  // namespace mgc

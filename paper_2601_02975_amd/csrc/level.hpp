@@ -1,0 +1,41 @@
+// Host-side description of one multigrid level.
+#pragma once
+
+#include <array>
+#include <map>
+#include <utility>
+#include <vector>
+
+#include "mg_internal.hpp"
+
+namespace mgc {
+
+using LatticeMemo = std::map<__uint128_t, std::vector<std::array<int, 2>>>;
+
+void ghost_weights(int bc, int which, double w[5]);
+void corner_weights(int bcx, int bcy, int m, int k, double h, double wu[4][4], double wgy[4], double wgx[4]);
+
+struct Level {
+    mg_grid g{};
+    double a = 0, b = 0, c = 0;
+    const Curves *curves = nullptr;
+    CutGrid cg;
+    std::vector<uint8_t> kind;                    // 0 inactive, 1 SFV, 2 PLG (row-major)
+    std::vector<int> plg_cells;                   // PLG cells, row-major order
+    std::vector<int> plg_row;                     // cell -> PLG row or -1
+    std::vector<std::vector<std::array<int, 2>>> lattices;
+    int n_active = 0, n_face = 0, n_irr = 0;
+    std::vector<int> g_of_cell;                   // irregular cell -> index into g
+    // assembled PLG rows (row-major PLG order): columns are cell indices
+    std::vector<int> row_ptr, col;
+    std::vector<double> val, beta_b;
+
+    int face_index(int side, int k) const;
+    void classify();
+    std::vector<std::array<int, 2>> lattice(int i, int j, LatticeMemo &memo) const;
+    void fit_inputs(std::vector<double> &M, std::vector<double> &phi, std::vector<double> &w, std::vector<int> &ncol);
+    void sfv_row(int i, int j, std::vector<std::pair<int, double>> &cells,
+                 std::vector<std::pair<int, double>> &gdat) const;
+};
+
+}  // namespace mgc

@@ -1,0 +1,312 @@
+// Exact solve with the PLG block A22 (eq. (5.6)), set up for the GPU.
+//
+// The PLG cells are ordered along the boundary curves (Definition 5.1): by
+// the curve closest to the cell centre, then by the parameter of the closest
+// point on it.  In that order A22 is banded apart from O(1) wrap-around
+// couplings (Lemma 5.2).  The paper factors it as a bordered band LU
+// (Definition 5.3), whose triangular solves are sequential chains of length
+// m.  Here the chain of each curve is cut into segments separated by runs of
+// "separator" unknowns at least one bandwidth long, so that segments couple
+// only through separators; any remaining coupling moves its column into the
+// separator set.  With B the segment blocks and S the separators,
+//     y = B^{-1} t_B,  x_S = S'^{-1} (t_S - A_SB y),  x_B = y - B^{-1} A_BS x_S,
+// where S' = A_SS - A_SB B^{-1} A_BS.  B^{-1} (per segment), B^{-1} A_BS and
+// S'^{-1} are dense and precomputed, so a solve is three parallel passes.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "plgsolve.hpp"
+
+namespace mgc {
+
+namespace {
+
+// closest point of a segment to (px, py): returns squared distance and t
+void closest_on_seg(const Seg &s, double px, double py, double &d2, double &t) {
+    if (s.kind == MG_SEG_LINE) {
+        double dx = s.p[2] - s.p[0], dy = s.p[3] - s.p[1];
+        double L2 = dx * dx + dy * dy;
+        t = L2 > 0 ? ((px - s.p[0]) * dx + (py - s.p[1]) * dy) / L2 : 0.0;
+        t = std::min(1.0, std::max(0.0, t));
+    } else {
+        double th = std::atan2(py - s.p[1], px - s.p[0]);
+        double t0 = s.p[3], sw = s.p[4] - s.p[3];
+        // parameter of the angle th, unwrapped into the sweep if possible
+        double u = (th - t0) / sw;
+        double per = 2.0 * M_PI / std::fabs(sw);
+        u -= per * std::floor(u / per);          // u in [0, per)
+        if (u <= 1.0) {
+            t = u;
+        } else {
+            // outside the arc: nearer end point
+            double x0, y0, x1, y1;
+            s.point(0.0, x0, y0);
+            s.point(1.0, x1, y1);
+            t = (std::hypot(px - x0, py - y0) <= std::hypot(px - x1, py - y1)) ? 0.0 : 1.0;
+        }
+    }
+    double x, y;
+    s.point(t, x, y);
+    d2 = (x - px) * (x - px) + (y - py) * (y - py);
+}
+
+// in-place inverse by Gauss-Jordan with partial pivoting (row-major n x n)
+bool invert_dense(int n, std::vector<double> &A) {
+    std::vector<double> I((size_t)n * n, 0.0);
+    for (int k = 0; k < n; ++k) I[(size_t)k * n + k] = 1.0;
+    for (int k = 0; k < n; ++k) {
+        int p = k;
+        for (int r = k + 1; r < n; ++r)
+            if (std::fabs(A[(size_t)r * n + k]) > std::fabs(A[(size_t)p * n + k])) p = r;
+        if (A[(size_t)p * n + k] == 0.0) return false;
+        if (p != k)
+            for (int c = 0; c < n; ++c) {
+                std::swap(A[(size_t)k * n + c], A[(size_t)p * n + c]);
+                std::swap(I[(size_t)k * n + c], I[(size_t)p * n + c]);
+            }
+        double inv = 1.0 / A[(size_t)k * n + k];
+        for (int c = 0; c < n; ++c) {
+            A[(size_t)k * n + c] *= inv;
+            I[(size_t)k * n + c] *= inv;
+        }
+#pragma omp parallel for schedule(static)
+        for (int r = 0; r < n; ++r) {
+            if (r == k) continue;
+            double f = A[(size_t)r * n + k];
+            if (f == 0.0) continue;
+            double *ar = &A[(size_t)r * n], *ir = &I[(size_t)r * n];
+            const double *ak = &A[(size_t)k * n], *ik = &I[(size_t)k * n];
+            for (int c = 0; c < n; ++c) {
+                ar[c] -= f * ak[c];
+                ir[c] -= f * ik[c];
+            }
+        }
+    }
+    A.swap(I);
+    return true;
+}
+
+}  // namespace
+
+void build_plg_solver(const Level &L, int seg_max, PlgSolver &S) {
+    const int nx = L.g.nx;
+    const int m = (int)L.plg_cells.size();
+    S = PlgSolver();
+    S.m = m;
+    if (m == 0) return;
+    const auto &curves = L.curves->c;
+    // Definition 5.1 ordering
+    struct Key { int curve; double s; int cell; };
+    std::vector<Key> keys(m);
+    for (int r = 0; r < m; ++r) {
+        int cell = L.plg_cells[r];
+        double px = L.g.x0 + (cell % nx + 0.5) * L.g.h, py = L.g.y0 + (cell / nx + 0.5) * L.g.h;
+        double best = 1e300;
+        Key k{0, 0.0, cell};
+        // PLG cells arise near the holes; the box is grid-aligned (ghost cells)
+        for (size_t ci = curves.size() > 1 ? 1 : 0; ci < curves.size(); ++ci)
+            for (size_t si = 0; si < curves[ci].size(); ++si) {
+                double d2, t;
+                closest_on_seg(curves[ci][si], px, py, d2, t);
+                if (d2 < best) {
+                    best = d2;
+                    k.curve = (int)ci;
+                    k.s = (si + t) / curves[ci].size();
+                }
+            }
+        keys[r] = k;
+    }
+    std::vector<int> order(m);
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(), [&](int a, int b) {
+        if (keys[a].curve != keys[b].curve) return keys[a].curve < keys[b].curve;
+        if (keys[a].s != keys[b].s) return keys[a].s < keys[b].s;
+        return keys[a].cell < keys[b].cell;
+    });
+    std::vector<int> pos(m);
+    for (int k = 0; k < m; ++k) pos[order[k]] = k;
+    // A22 couplings in the curve order: for each ordered position, the PLG
+    // columns of its row
+    std::vector<std::vector<std::pair<int, double>>> a22(m);
+    for (int r = 0; r < m; ++r)
+        for (int e = L.row_ptr[r]; e < L.row_ptr[r + 1]; ++e) {
+            int pr = L.plg_row[L.col[e]];
+            if (pr >= 0) a22[pos[r]].push_back({pos[pr], L.val[e]});
+        }
+    // chains per curve and bandwidth
+    std::vector<int> chain_of(m);
+    std::vector<std::pair<int, int>> chains;
+    for (int k = 0; k < m;) {
+        int c = keys[order[k]].curve, k1 = k;
+        while (k1 < m && keys[order[k1]].curve == c) ++k1;
+        for (int q = k; q < k1; ++q) chain_of[q] = (int)chains.size();
+        chains.push_back({k, k1});
+        k = k1;
+    }
+    std::vector<int> seg_of(m, -1);                 // -1 = separator
+    int nseg = 0;
+    for (auto &ch : chains) {
+        int len = ch.second - ch.first;
+        if (len <= seg_max) {
+            for (int q = ch.first; q < ch.second; ++q) seg_of[q] = nseg;
+            ++nseg;
+            continue;
+        }
+        int w = 1;
+        for (int q = ch.first; q < ch.second; ++q)
+            for (auto &e : a22[q])
+                if (chain_of[e.first] == chain_of[q]) {
+                    int d = std::abs(e.first - q);
+                    if (d < len / 2) w = std::max(w, d);
+                }
+        int seglen = std::max(seg_max - w, 2 * w);
+        int q = ch.first + w;                       // separator at the chain start
+        while (q < ch.second) {
+            int e = std::min(ch.second, q + seglen);
+            if (ch.second - e < seglen / 4) e = ch.second;   // no tiny tail segment
+            for (int k = q; k < e; ++k) seg_of[k] = nseg;
+            ++nseg;
+            q = e + w;                              // next separator run
+        }
+    }
+    // any coupling between different segments moves its column to S
+    bool changed = true;
+    while (changed) {
+        changed = false;
+        for (int q = 0; q < m; ++q) {
+            if (seg_of[q] < 0) continue;
+            for (auto &e : a22[q])
+                if (seg_of[e.first] >= 0 && seg_of[e.first] != seg_of[q]) {
+                    seg_of[e.first] = -1;
+                    changed = true;
+                }
+        }
+    }
+    // final order: segments (curve order inside), then separators
+    std::vector<std::vector<int>> segpos(nseg);
+    std::vector<int> seppos;
+    for (int q = 0; q < m; ++q) {
+        if (seg_of[q] >= 0) segpos[seg_of[q]].push_back(q);
+        else seppos.push_back(q);
+    }
+    S.seg_start.push_back(0);
+    std::vector<int> newpos(m, -1);
+    for (auto &sp : segpos) {
+        if (sp.empty()) continue;
+        for (int q : sp) {
+            newpos[q] = (int)S.order.size();
+            S.order.push_back(order[q]);
+        }
+        S.seg_start.push_back((int)S.order.size());
+    }
+    S.nseg = (int)S.seg_start.size() - 1;
+    S.nsep = (int)seppos.size();
+    S.sep_begin = (int)S.order.size();
+    for (int q : seppos) {
+        newpos[q] = (int)S.order.size();
+        S.order.push_back(order[q]);
+    }
+    // dense blocks
+    const int nb = S.nseg, ns = S.nsep, sb = S.sep_begin;
+    std::vector<std::vector<std::pair<int, double>>> A(m);   // rows/cols in final order
+    for (int q = 0; q < m; ++q)
+        for (auto &e : a22[q]) A[newpos[q]].push_back({newpos[e.first], e.second});
+    S.inv_off.assign(nb + 1, 0);
+    S.f_off.assign(nb + 1, 0);
+    S.fcols_ptr.assign(nb + 1, 0);
+    for (int j = 0; j < nb; ++j) {
+        long long Lj = S.seg_start[j + 1] - S.seg_start[j];
+        S.inv_off[j + 1] = S.inv_off[j] + Lj * Lj;
+    }
+    S.inv.assign(S.inv_off[nb], 0.0);
+    std::vector<std::vector<int>> fcols(nb);
+    std::vector<double> Sp((size_t)ns * ns, 0.0);
+    for (int r = sb; r < m; ++r)
+        for (auto &e : A[r])
+            if (e.first >= sb) Sp[(size_t)(r - sb) * ns + (e.first - sb)] += e.second;
+    std::vector<std::vector<double>> Fj(nb);
+    bool singular = false;
+#pragma omp parallel for schedule(dynamic)
+    for (int j = 0; j < nb; ++j) {
+        int s0 = S.seg_start[j], Lj = S.seg_start[j + 1] - s0;
+        std::vector<double> B((size_t)Lj * Lj, 0.0);
+        std::vector<int> cols;
+        for (int r = s0; r < s0 + Lj; ++r)
+            for (auto &e : A[r]) {
+                if (e.first >= s0 && e.first < s0 + Lj) B[(size_t)(r - s0) * Lj + (e.first - s0)] += e.second;
+                else if (e.first >= sb) cols.push_back(e.first - sb);
+            }
+        std::sort(cols.begin(), cols.end());
+        cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+        if (!invert_dense(Lj, B)) {
+#pragma omp critical
+            singular = true;
+            continue;
+        }
+        // stored column-major: inv[c * Lj + r] = B^{-1}[r][c]
+        double *dst = &S.inv[S.inv_off[j]];
+        for (int r = 0; r < Lj; ++r)
+            for (int c = 0; c < Lj; ++c) dst[(size_t)c * Lj + r] = B[(size_t)r * Lj + c];
+        // F = B^{-1} A_{j,S}
+        int k = (int)cols.size();
+        std::vector<double> AS((size_t)Lj * k, 0.0);
+        for (int r = s0; r < s0 + Lj; ++r)
+            for (auto &e : A[r])
+                if (e.first >= sb) {
+                    int kk = (int)(std::lower_bound(cols.begin(), cols.end(), e.first - sb) - cols.begin());
+                    AS[(size_t)(r - s0) * k + kk] += e.second;
+                }
+        std::vector<double> F((size_t)Lj * k, 0.0);
+        for (int r = 0; r < Lj; ++r)
+            for (int c = 0; c < Lj; ++c) {
+                double v = B[(size_t)r * Lj + c];
+                if (v == 0.0) continue;
+                for (int kk = 0; kk < k; ++kk) F[(size_t)r * k + kk] += v * AS[(size_t)c * k + kk];
+            }
+        Fj[j] = F;
+        fcols[j] = cols;
+    }
+    if (singular) fail(MG_ERR_SINGULAR, "a PLG segment block is singular");
+    for (int j = 0; j < nb; ++j) {
+        int Lj = S.seg_start[j + 1] - S.seg_start[j], k = (int)fcols[j].size();
+        S.f_off[j + 1] = S.f_off[j] + (long long)Lj * k;
+        S.fcols_ptr[j + 1] = S.fcols_ptr[j] + k;
+    }
+    S.F.assign(S.f_off[nb], 0.0);
+    S.fcols.clear();
+    for (int j = 0; j < nb; ++j) {
+        int Lj = S.seg_start[j + 1] - S.seg_start[j], k = (int)fcols[j].size();
+        // column-major: F[kk * Lj + r]
+        for (int r = 0; r < Lj; ++r)
+            for (int kk = 0; kk < k; ++kk) S.F[S.f_off[j] + (size_t)kk * Lj + r] = Fj[j][(size_t)r * k + kk];
+        for (int c : fcols[j]) S.fcols.push_back(c);
+        // Schur complement: S' -= A_{S,j} F_j
+        int s0 = S.seg_start[j];
+        for (int r = sb; r < m; ++r)
+            for (auto &e : A[r])
+                if (e.first >= s0 && e.first < s0 + Lj) {
+                    int lr = e.first - s0;
+                    for (int kk = 0; kk < k; ++kk)
+                        Sp[(size_t)(r - sb) * ns + fcols[j][kk]] -= e.second * Fj[j][(size_t)lr * k + kk];
+                }
+    }
+    if (ns > 0) {
+        if (!invert_dense(ns, Sp)) fail(MG_ERR_SINGULAR, "the PLG separator block is singular");
+        S.sinv.assign((size_t)ns * ns, 0.0);
+        for (int r = 0; r < ns; ++r)
+            for (int c = 0; c < ns; ++c) S.sinv[(size_t)c * ns + r] = Sp[(size_t)r * ns + c];
+    }
+    // separator rows: couplings to segment unknowns (positions < sb)
+    S.sb_ptr.assign(ns + 1, 0);
+    for (int r = sb; r < m; ++r) {
+        for (auto &e : A[r])
+            if (e.first < sb) {
+                S.sb_col.push_back(e.first);
+                S.sb_val.push_back(e.second);
+            }
+        S.sb_ptr[r - sb + 1] = (int)S.sb_col.size();
+    }
+}
+
+}  // namespace mgc

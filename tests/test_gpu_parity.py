@@ -1,0 +1,188 @@
+"""Parity of the HIP library (through its C ABI) with the FP64 oracle.
+
+Inputs are seeded and synthetic (workloads.py).  Values flow only from the
+oracle into the GPU path (b, u0), never the other way.  Tolerances: the FP64
+kernels must match the oracle to 1e-12 relative except where a step solves a
+linear system by a different exact method (the PLG block: sparse LU in the
+oracle, segment inverses on the GPU; the fits: SVD least squares in the
+oracle, Householder QR on the GPU), where the bound is the conditioning of
+that system times the unit roundoff, stated per test.
+"""
+import functools
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "disk64": lambda: W.unit_disk_config(0, 64),
+    "three_disks128": lambda: W.three_disks_config(0, 128),
+    "star128": lambda: W.star_config(0, 128),
+    "square_cross32": lambda: W.unit_square_config(32, 1.0, 0.5, 2.0),
+}
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@functools.lru_cache(maxsize=None)
+def oracle(name):
+    from oracle.multigrid import Hierarchy
+    P = CASES[name]()
+    return P, Hierarchy(P.grid, P.curves, P.a, P.b, P.c, P.eps)
+
+
+@functools.lru_cache(maxsize=None)
+def product(name, precision=0):
+    import paper_2601_02975_amd as mg
+    P = CASES[name]()
+    return mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=precision)
+
+
+def to_dev(L, v):
+    torch = _torch()
+    out = np.zeros((L.ny + 4, L.nx + 4))
+    out[L.cells_j + 2, L.cells_i + 2] = v
+    return torch.tensor(out, dtype=torch.float64, device="cuda")
+
+
+def from_dev(L, t):
+    return t.cpu().numpy()[L.cells_j + 2, L.cells_i + 2]
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_setup_parity(name):
+    """Classification (Definition 4.1), lattices and fitted coefficients of
+    every PLG row on every level.  Fits are weighted minimum-norm solutions of
+    15 x 16 systems with cond(M W^{1/2}) up to ~1e4: bound 1e-10 relative."""
+    P, H = oracle(name)
+    S = product(name)
+    assert S.info["n_levels"] == len(H.levels)
+    worst = 0.0
+    for l, L in enumerate(H.levels):
+        kind, rp, col, val, bb = S.export_level(l)
+        assert np.array_equal(kind, L.kind), "classification differs on level %d" % l
+        pj, pi = np.nonzero(L.kind == 2)
+        assert len(rp) == len(pi) + 1
+        for r, (i, j) in enumerate(zip(pi, pj)):
+            lat = L.lattice[(int(i), int(j))]
+            beta, bbo = L.beta[(int(i), int(j))]
+            want = [(j + d[1]) * L.nx + i + d[0] for d in lat]
+            assert list(col[rp[r]:rp[r + 1]]) == want
+            scale = max(np.abs(beta).max(), abs(bbo) if bbo is not None else 0.0)
+            worst = max(worst, np.abs(val[rp[r]:rp[r + 1]] - beta).max() / scale)
+            if bbo is None:
+                assert bb[r] == 0.0
+            else:
+                worst = max(worst, abs(bb[r] - bbo) / scale)
+    print("max relative coefficient difference %.2e" % worst)
+    assert worst <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["disk64", "three_disks128", "square_cross32"])
+def test_rhs_parity(name):
+    """b = f - N g (eq. (4.19)) from the oracle's f and g: same layout."""
+    from oracle.rhs import rhs
+    torch = _torch()
+    P, H = oracle(name)
+    S = product(name)
+    L = H.levels[0]
+    b, f, g = rhs(L, P.solution)
+    assert S.info["n_face"] + S.info["n_irr"] == len(g)
+    bd = torch.zeros_like(to_dev(L, f))
+    S.rhs(to_dev(L, f), torch.tensor(g, device="cuda"), bd)
+    assert rel(from_dev(L, bd), b) <= 1e-13
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_smoother_parity_all_levels(name):
+    """One block-smoother sweep (Definition 5.6) from a seeded random state."""
+    P, H = oracle(name)
+    S = product(name)
+    rng = np.random.default_rng(11)
+    for l, L in enumerate(H.levels):
+        u = rng.standard_normal(L.n)
+        b = rng.standard_normal(L.n) / (L.h * L.h)
+        want = H.smooth(l, u, b)
+        ud = to_dev(L, u)
+        S.smooth(l, to_dev(L, b), ud)
+        got = from_dev(L, ud)
+        err = rel(got, want)
+        print("level %d smoother rel diff %.2e" % (l, err))
+        assert err <= 1e-11
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_residual_parity(name):
+    P, H = oracle(name)
+    S = product(name)
+    rng = np.random.default_rng(12)
+    for l, L in enumerate(H.levels):
+        u = rng.standard_normal(L.n)
+        b = rng.standard_normal(L.n) / (L.h * L.h)
+        want = b - L.A @ u
+        rd = to_dev(L, np.zeros(L.n))
+        nrm = S.residual(l, to_dev(L, b), to_dev(L, u), rd)
+        assert rel(from_dev(L, rd), want) <= 1e-13
+        assert nrm == pytest.approx(np.abs(want).max(), rel=1e-13)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_vcycle_iterates(name):
+    """u_k of the V-cycle iteration (Algorithm 3) from u_0 = 0 with the
+    oracle's right-hand side, k = 1..4."""
+    from oracle.rhs import rhs
+    P, H = oracle(name)
+    S = product(name)
+    L = H.levels[0]
+    b, _, _ = rhs(L, P.solution)
+    bd = to_dev(L, b)
+    uo = np.zeros(L.n)
+    ud = to_dev(L, uo)
+    for k in range(4):
+        uo = H.vcycle(0, uo, b)
+        S.vcycle(bd, ud)
+        err = rel(from_dev(L, ud), uo)
+        print("iterate %d rel diff %.2e" % (k + 1, err))
+        assert err <= 1e-11
+
+
+@pytest.mark.parametrize("name", ["disk64", "three_disks128"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_matches_oracle(name, precision):
+    """mg_solve to 1e-10 (FP64, and FP32 V-cycles in FP64 defect correction)
+    from the library's own projection of f and g: relative residual <= 1e-10
+    and the discretisation error equal to the oracle's within 1% plus the
+    algebraic error allowed by the tolerance."""
+    from oracle.rhs import cell_averages
+    torch = _torch()
+    P, H = oracle(name)
+    S = product(name, precision)
+    L = H.levels[0]
+    f, g = S.project(P.solution)
+    u = torch.zeros_like(torch.tensor(f, device="cuda"))
+    it, relres, code = S.solve(torch.tensor(f, device="cuda"), torch.tensor(g, device="cuda"), u, 1e-10)
+    assert code == 0 and relres <= 1e-10, (code, relres, it)
+    from oracle.rhs import rhs
+    b, _, _ = rhs(L, P.solution)
+    uo, ito, relo = H.solve(b, tol=1e-12, max_iters=200)
+    exact = cell_averages(L, P.solution.u)
+    ug = from_dev(L, u)
+    err_g = np.abs(ug - exact).max()
+    err_o = np.abs(uo - exact).max()
+    alg = np.abs(ug - uo).max()
+    print("iters %d rel %.2e err_gpu %.3e err_oracle %.3e |u_gpu-u_oracle| %.2e" % (it, relres, err_g, err_o, alg))
+    assert abs(err_g - err_o) <= 0.01 * err_o + alg
+    assert alg <= 1e-6 * np.abs(uo).max()
