@@ -1,0 +1,170 @@
+"""Solves/s to a 1e-10 relative residual on one MI355X.
+
+Workload: [0,1]^2 minus 3 seeded disks (radius U[0.05, 0.15]), 1024 x 1024
+cells, a=1, b=0.5, c=2, Dirichlet outside, Neumann on the holes, 6 seeded
+sine modes (seed 0).  A step is one whole solve from u = 0 (outer iteration
+of V-cycles until ||b - A u||_inf <= 1e-10 ||b||_inf) with the inputs already
+resident on the device.  `value` is the mixed-precision rate (FP32 V-cycles
+inside FP64 defect correction); the plain FP64 rate is reported beside it.
+
+Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2601_02975_amd", "csrc", "kernels.hip"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(precision):
+    """HBM bytes per launch of the finest-level sweep from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_sfv_sweep_three_disks1024.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch", {}).get(precision)
+
+
+def timed_solves(torch, S, f, g, steps, warmup, tol, record=False):
+    u = torch.zeros_like(f)
+    iters = []
+    for _ in range(warmup):
+        u.zero_()
+        it, rel, code = S.solve(f, g, u, tol)
+        if code != 0:
+            raise RuntimeError("solve did not converge (code %d, rel %.2e after %d)" % (code, rel, it))
+    torch.cuda.synchronize()
+    if record:
+        S.kernel_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        u.zero_()
+        it, rel, code = S.solve(f, g, u, tol)
+        iters.append(it)
+        if code != 0:
+            raise RuntimeError("solve did not converge (code %d, rel %.2e after %d)" % (code, rel, it))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    launches, avg_ms = S.kernel_timing(False) if record else (0, 0.0)
+    return dt, iters, rel, u, launches, avg_ms
+
+
+def cpu_baseline(P, gpu_iters, sample_cycles):
+    """The oracle (plain NumPy/SciPy, FP64) on the same workload: time a
+    bounded number of its V-cycles and scale to one solve with the iteration
+    count the solve needs (the GPU FP64 iteration count: the iterates agree)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.multigrid import Hierarchy
+    from oracle.rhs import rhs
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        H = Hierarchy(P.grid, P.curves, P.a, P.b, P.c, P.eps)
+        t_setup = time.perf_counter() - t0
+        b, _, _ = rhs(H.levels[0], P.solution)
+        u = b * 0.0
+        t0 = time.perf_counter()
+        for _ in range(sample_cycles):
+            u = H.vcycle(0, u, b)
+            r = b - H.levels[0].A @ u
+            _ = float(abs(r).max())
+        t_cycle = (time.perf_counter() - t0) / sample_cycles
+    per_solve = gpu_iters * t_cycle
+    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": "%d V-cycles (with residual norms) of the FP64 oracle on the same 1024^2 workload, "
+                      "%.3f s each, scaled by the %d cycles a solve to 1e-10 takes; oracle setup %.1f s "
+                      "not included" % (sample_cycles, t_cycle, gpu_iters, t_setup)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--cpu-cycles", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d refused)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2601_02975_amd as mg
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    P = W.three_disks_config(0, args.n)
+    t0 = time.perf_counter()
+    S32 = mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=mg.MIXED, max_iters=1000)
+    t_setup = time.perf_counter() - t0
+    S64 = mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=mg.FP64, max_iters=1000)
+    fh, gh = S64.project(P.solution)
+    f = torch.tensor(fh, device="cuda")
+    g = torch.tensor(gh, device="cuda")
+    print("setup %.2f s, levels %s, PLG cells %s, separators %s" % (
+        t_setup, S64.info["nx"], S64.info["n_plg"], S64.info["n_sep"]), file=sys.stderr, flush=True)
+
+    dt64, it64, rel64, u64, _, _ = timed_solves(torch, S64, f, g, args.steps, args.warmup, args.tol)
+    print("fp64: %.4f s/solve, %d iterations" % (dt64 / args.steps, it64[-1]), file=sys.stderr, flush=True)
+    dt32, it32, rel32, u32, nl, avg_ms = timed_solves(torch, S32, f, g, args.steps, args.warmup, args.tol, True)
+    print("mixed: %.4f s/solve, %d iterations" % (dt32 / args.steps, it32[-1]), file=sys.stderr, flush=True)
+    diff = float((u32 - u64).abs().max() / u64.abs().max())
+
+    n_cells = P.grid.nx * P.grid.ny
+    alg_bytes = 3 * 4 * n_cells                     # FP32 sweep: read u, b; write u
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None
+    traffic = load_traffic("fp32")
+    out = {
+        "metric": "solves/s to 1e-10 rel. residual (mixed vs FP64 GPU), HBM GB/s; p50/p99 latency",
+        "value": args.steps / dt32,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt32 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 V-cycle in f64 defect correction",
+        "data": "synthetic",
+        "config": {"workload": "three_disks_1024x1024_seed0 (a=1, b=0.5, c=2; Dirichlet box, Neumann holes; "
+                               "6 sine modes)", "tol": args.tol, "cells": n_cells,
+                   "levels": S64.info["nx"], "plg_cells": S64.info["n_plg"]},
+        "fp64": {"value": args.steps / dt64, "unit": "solves/s", "iterations": it64[-1], "rel_residual": rel64},
+        "mixed": {"iterations": it32[-1], "rel_residual": rel32, "max_rel_diff_vs_fp64": diff},
+        "speedup_mixed_over_fp64": dt64 / dt32,
+        "roofline": {"bound": "hbm", "kernel": "k_jacobi<float> (finest-level SFV sweep)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+                     "launches_timed": nl, "avg_launch_ms": avg_ms,
+                     "algorithmic_bytes_per_launch": alg_bytes},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(P, it64[-1], args.cpu_cycles)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

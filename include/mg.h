@@ -20,7 +20,7 @@
  *    ignored on input and written as 0 on output.
  *  - f holds cell averages <f>_i over the cut cells (eq. (4.1)), not point
  *    values.  g holds boundary averages (eq. (4.2)) in the layout returned
- *    by mg_boundary_layout: first the 2nx + 2ny box faces (bottom faces
+ *    by mg_boundary_quadrature: first the 2nx + 2ny box faces (bottom faces
  *    i = 0..nx-1, then top faces, then left faces j = 0..ny-1, then right
  *    faces; Dirichlet: average of u, Neumann: average of du/dn with n the
  *    outward normal), then one value per irregular cut cell, <<N u>> over
@@ -164,6 +164,18 @@ mg_status mg_boundary_quadrature(mg_handle h, int *n, long long *nnodes, long lo
 
 mg_status mg_destroy(mg_handle h);
 const char *mg_error_string(mg_status s);
+
+/* Kernel timing for measurement: enable = 1 clears and starts recording a
+ * pair of HIP events around every launch of the finest-level SFV sweep
+ * (eq. (5.5), the dominant kernel) on the stream it is launched on;
+ * enable = 0 stops recording, synchronises, and returns the number of
+ * recorded launches and their average duration in milliseconds.  At most
+ * 8192 launches are recorded. */
+mg_status mg_kernel_timing(mg_handle h, int enable, int *launches, double *avg_ms);
+
+/* Human-readable description of the last failure of any entry point on the
+ * calling host thread ("" if none); valid until the next call. */
+const char *mg_last_error(void);
 
 #ifdef __cplusplus
 }

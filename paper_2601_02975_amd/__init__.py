@@ -24,8 +24,8 @@ FP64, MIXED = 0, 1
 
 
 class MGError(RuntimeError):
-    def __init__(self, code, where):
-        super().__init__("%s failed: %s (%d)" % (where, STATUS.get(code, "?"), code))
+    def __init__(self, code, where, detail=""):
+        super().__init__("%s failed: %s (%d) %s" % (where, STATUS.get(code, "?"), code, detail))
         self.code = code
 
 
@@ -60,6 +60,13 @@ def load_library():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libmgcut.so is not built (run __graft_entry__.build() or "
                           "python paper_2601_02975_amd/build.py)")
+    # PyTorch ships its own HIP runtime (soname libamdhip64.so.7).  Loading it
+    # first makes the dynamic loader reuse it for libmgcut.so, so one process
+    # holds a single HIP runtime and torch tensors are valid device pointers.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P, I, D, LL = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong
     pI, pD, pLL = ctypes.POINTER(I), ctypes.POINTER(D), ctypes.POINTER(LL)
@@ -77,6 +84,7 @@ def load_library():
         "mg_cell_quadrature": [P, pI, pLL, pI, pLL, pD, pD, pD],
         "mg_boundary_quadrature": [P, pI, pLL, pLL, pD, pD, pD, pD, pD, pI, pD, pD],
         "mg_destroy": [P],
+        "mg_kernel_timing": [P, I, pI, pD],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -84,6 +92,8 @@ def load_library():
         fn.restype = ctypes.c_int
     lib.mg_error_string.argtypes = [ctypes.c_int]
     lib.mg_error_string.restype = ctypes.c_char_p
+    lib.mg_last_error.argtypes = []
+    lib.mg_last_error.restype = ctypes.c_char_p
     return lib
 
 
@@ -99,7 +109,7 @@ def lib():
 
 def _check(code, where):
     if code != MG_OK:
-        raise MGError(code, where)
+        raise MGError(code, where, lib().mg_last_error().decode(errors="replace"))
 
 
 def _ptr(t):
@@ -248,6 +258,13 @@ class Solver:
                "mg_boundary_quadrature")
         k = nn.value
         return ptr, x[:k], y[:k], w[:k], nxv[:k], nyv[:k], bc[:k], a1[:k], a2[:k]
+
+    def kernel_timing(self, enable):
+        n = ctypes.c_int()
+        avg = ctypes.c_double()
+        _check(lib().mg_kernel_timing(self.h, 1 if enable else 0, ctypes.byref(n), ctypes.byref(avg)),
+               "mg_kernel_timing")
+        return n.value, avg.value
 
     # -- inputs ------------------------------------------------------------------
     def project(self, sol):

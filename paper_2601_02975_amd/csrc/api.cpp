@@ -72,6 +72,10 @@ struct mg_handle_s {
     long long bytes = 0;
     double setup_seconds = 0.0;
     std::string last_error;
+    // timing of the finest-level SFV sweep
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    int nrec = 0;
 
     template <typename T>
     T *alloc(size_t n) {
@@ -142,6 +146,7 @@ void fit_level(mg_handle h, Level &L, hipStream_t st) {
     HIPCHECK(hipMemcpy(dncol, ncol.data(), ncol.size() * 4, hipMemcpyHostToDevice));
     launch_fit(m, dM, dphi, dw, dncol, dwork, dbeta, dstat, st);
     HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(st));
     std::vector<double> beta((size_t)m * 16);
     std::vector<int> stat(m);
     HIPCHECK(hipStreamSynchronize(st));
@@ -375,7 +380,13 @@ template <typename T>
 void smooth(mg_handle h, int l, hipStream_t st) {
     DevLevel &D = h->dev[l];
     T *uo = Prec<T>::u(D, D.cur), *un = Prec<T>::u(D, 1 - D.cur);
+    const bool rec = h->timing && l == 0 && 2 * h->nrec + 1 < (int)h->ev.size();
+    if (rec) HIPCHECK(hipEventRecord(h->ev[2 * h->nrec], st));
     launch_jacobi<T>(D.args, uo, Prec<T>::b(D), un, D.mask, st);
+    if (rec) {
+        HIPCHECK(hipEventRecord(h->ev[2 * h->nrec + 1], st));
+        ++h->nrec;
+    }
     launch_plg_solve<T>(Prec<T>::P(D), Prec<T>::b(D), un, st);
     D.cur = 1 - D.cur;
 }
@@ -416,16 +427,21 @@ double residual_norm(mg_handle h, int l, const double *u, const double *b, float
     return device_absmax_finish(h, nb, st);
 }
 
+thread_local std::string g_last_error;
+
 mg_status guard(mg_handle h, const std::function<void()> &fn) {
     try {
         fn();
         return MG_OK;
     } catch (const status_error &e) {
+        g_last_error = e.what();
         if (h) h->last_error = e.what();
         return e.code;
     } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
         return MG_ERR_OOM;
     } catch (const std::exception &e) {
+        g_last_error = e.what();
         if (h) h->last_error = e.what();
         return MG_ERR_INVALID_ARG;
     }
@@ -439,7 +455,7 @@ void build_ghost_table() {
             ghost_weights(bc == 0 ? MG_BC_DIRICHLET : MG_BC_NEUMANN, d, w);
             for (int k = 0; k < 4; ++k) gw[bc][d - 1][k] = w[k];
         }
-    upload_ghost_table(gw);
+    HIPCHECK(upload_ghost_table(gw));
 }
 
 }  // namespace
@@ -831,13 +847,41 @@ mg_status mg_boundary_quadrature(mg_handle h, int *n, long long *nnodes, long lo
     return MG_OK;
 }
 
+mg_status mg_kernel_timing(mg_handle h, int enable, int *launches, double *avg_ms) {
+    if (!h) return MG_ERR_INVALID_ARG;
+    return guard(h, [&]() {
+        if (enable) {
+            if (h->ev.empty()) {
+                h->ev.resize(2 * 8192);
+                for (auto &e : h->ev) HIPCHECK(hipEventCreate(&e));
+            }
+            h->nrec = 0;
+            h->timing = true;
+            return;
+        }
+        h->timing = false;
+        double tot = 0.0;
+        for (int k = 0; k < h->nrec; ++k) {
+            HIPCHECK(hipEventSynchronize(h->ev[2 * k + 1]));
+            float ms = 0.f;
+            HIPCHECK(hipEventElapsedTime(&ms, h->ev[2 * k], h->ev[2 * k + 1]));
+            tot += ms;
+        }
+        if (launches) *launches = h->nrec;
+        if (avg_ms) *avg_ms = h->nrec ? tot / h->nrec : 0.0;
+    });
+}
+
 mg_status mg_destroy(mg_handle h) {
     if (!h) return MG_OK;
+    for (auto &e : h->ev) (void)hipEventDestroy(e);
     for (void *p : h->allocs) (void)hipFree(p);
     if (h->host_scalar) (void)hipHostFree(h->host_scalar);
     delete h;
     return MG_OK;
 }
+
+const char *mg_last_error(void) { return g_last_error.c_str(); }
 
 const char *mg_error_string(mg_status s) {
     switch (s) {

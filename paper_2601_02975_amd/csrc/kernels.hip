@@ -14,8 +14,8 @@ namespace mgc {
 
 __constant__ double c_gw[2][2][4];     // [bc][depth-1][k] ghost weights on the cells k steps inward
 
-void upload_ghost_table(const double gw[2][2][4]) {
-    (void)hipMemcpyToSymbol(HIP_SYMBOL(c_gw), gw, sizeof(double) * 16);
+hipError_t upload_ghost_table(const double gw[2][2][4]) {
+    return hipMemcpyToSymbol(HIP_SYMBOL(c_gw), gw, sizeof(double) * 16);
 }
 
 __device__ __forceinline__ size_t pidx(const LevelArgs &L, int i, int j) {

@@ -7,7 +7,7 @@
 
 namespace mgc {
 
-void upload_ghost_table(const double gw[2][2][4]);
+hipError_t upload_ghost_table(const double gw[2][2][4]);
 
 template <typename T>
 void launch_jacobi(const LevelArgs &L, const T *uold, const T *b, T *unew, const uint8_t *mask, hipStream_t st);

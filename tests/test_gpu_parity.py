@@ -103,7 +103,10 @@ def test_rhs_parity(name):
     assert S.info["n_face"] + S.info["n_irr"] == len(g)
     bd = torch.zeros_like(to_dev(L, f))
     S.rhs(to_dev(L, f), torch.tensor(g, device="cuda"), bd)
-    assert rel(from_dev(L, bd), b) <= 1e-13
+    # both sides sum the same terms in different orders: the difference is
+    # bounded by a few units of roundoff of the summed magnitudes
+    mag = np.abs(f) + abs(L.N) @ np.abs(g)
+    assert np.abs(from_dev(L, bd) - b).max() <= 16 * np.finfo(float).eps * mag.max()
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -186,3 +189,26 @@ def test_solve_matches_oracle(name, precision):
     print("iters %d rel %.2e err_gpu %.3e err_oracle %.3e |u_gpu-u_oracle| %.2e" % (it, relres, err_g, err_o, alg))
     assert abs(err_g - err_o) <= 0.01 * err_o + alg
     assert alg <= 1e-6 * np.abs(uo).max()
+
+
+@pytest.mark.parametrize("name", ["disk64", "three_disks128"])
+def test_mixed_step_is_fp32_accurate(name):
+    """One defect-correction step with an FP32 V-cycle (MG_MIXED) against one
+    FP64 V-cycle from u = 0: they differ by FP32 rounding (well above FP64
+    roundoff, well below the V-cycle's own error)."""
+    torch = _torch()
+    import paper_2601_02975_amd as mg
+    P, H = oracle(name)
+    L = H.levels[0]
+    S64 = product(name, 0)
+    S32 = mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=1, max_iters=1)
+    f, g = S64.project(P.solution)
+    ft, gt = torch.tensor(f, device="cuda"), torch.tensor(g, device="cuda")
+    u64 = torch.zeros_like(ft)
+    u32 = torch.zeros_like(ft)
+    S64f = mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=0, max_iters=1)
+    S64f.solve(ft, gt, u64, 1e-14)
+    S32.solve(ft, gt, u32, 1e-14)
+    d = rel(from_dev(L, u32), from_dev(L, u64))
+    print("one mixed step vs one FP64 V-cycle: rel diff %.2e" % d)
+    assert 1e-12 < d < 1e-4
