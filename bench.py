@@ -103,6 +103,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--cpu-cycles", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 256 MiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d refused)" % args.gpus,
@@ -126,6 +128,14 @@ def main():
     print("setup %.2f s, levels %s, PLG cells %s, separators %s" % (
         t_setup, S64.info["nx"], S64.info["n_plg"], S64.info["n_sep"]), file=sys.stderr, flush=True)
 
+    if args.calibrate_copy:
+        src_t = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+        dst_t = torch.empty_like(src_t)
+        for _ in range(3):
+            dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        print("calibration copy: 3 x %d bytes read and written" % (src_t.numel() * 8), file=sys.stderr)
+        del src_t, dst_t
     dt64, it64, rel64, u64, _, _ = timed_solves(torch, S64, f, g, args.steps, args.warmup, args.tol)
     print("fp64: %.4f s/solve, %d iterations" % (dt64 / args.steps, it64[-1]), file=sys.stderr, flush=True)
     dt32, it32, rel32, u32, nl, avg_ms = timed_solves(torch, S32, f, g, args.steps, args.warmup, args.tol, True)

@@ -72,6 +72,10 @@ struct mg_handle_s {
     long long bytes = 0;
     double setup_seconds = 0.0;
     std::string last_error;
+    // captured outer iteration per precision (0 FP64, 1 mixed)
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t iter_exec[2] = {nullptr, nullptr};
+    hipGraph_t iter_graph[2] = {nullptr, nullptr};
     // timing of the finest-level SFV sweep
     bool timing = false;
     std::vector<hipEvent_t> ev;
@@ -251,17 +255,18 @@ void upload_level(mg_handle h, int l, bool last, hipStream_t st) {
     // the segment and separator right-hand sides are staged in LDS (FP64)
     if ((size_t)max_seg * 8 > 65536 || (size_t)S.nsep * 8 > 65536)
         fail(MG_ERR_UNSUPPORTED, "PLG block partition exceeds the LDS budget");
-    auto fill = [&](auto &P, auto *a21v, auto *inv, auto *F, auto *sinv, auto *sbv, auto *y, auto *xs) {
+    auto fill = [&](auto &P, auto *a21v, auto *inv, auto *F, auto *sinv, auto *sbv, auto *y, auto *xs, auto *t, auto *rs) {
         P.m = S.m; P.nseg = S.nseg; P.nsep = S.nsep; P.sep_begin = S.sep_begin;
         P.cell = D.plg_cell; P.a21_ptr = a21_ptr; P.a21_col = a21_col; P.a21_val = a21v;
         P.seg_start = seg_start; P.inv_off = inv_off; P.inv = inv; P.f_off = f_off; P.F = F;
         P.fcols_ptr = fcols_ptr; P.fcols = fcols; P.sinv = sinv; P.sb_ptr = sb_ptr; P.sb_col = sb_col;
-        P.sb_val = sbv; P.y = y; P.xs = xs; P.max_seg = max_seg;
+        P.sb_val = sbv; P.y = y; P.xs = xs; P.t = t; P.rs = rs; P.max_seg = max_seg;
     };
     fill(D.P64, h->upload(aval), h->upload(S.inv), h->upload(S.F), h->upload(S.sinv), h->upload(S.sb_val),
-         h->alloc<double>(S.m), h->alloc<double>(S.nsep));
+         h->alloc<double>(S.m), h->alloc<double>(S.nsep), h->alloc<double>(S.m), h->alloc<double>(S.nsep));
     fill(D.P32, h->upload_f32<float>(aval), h->upload_f32<float>(S.inv), h->upload_f32<float>(S.F),
-         h->upload_f32<float>(S.sinv), h->upload_f32<float>(S.sb_val), h->alloc<float>(S.m), h->alloc<float>(S.nsep));
+         h->upload_f32<float>(S.sinv), h->upload_f32<float>(S.sb_val), h->alloc<float>(S.m), h->alloc<float>(S.nsep),
+         h->alloc<float>(S.m), h->alloc<float>(S.nsep));
     // transfers to the next level
     if (!last) {
         const Level &C = *h->levels[l + 1];
@@ -425,6 +430,50 @@ double residual_norm(mg_handle h, int l, const double *u, const double *b, float
     launch_plg_residual<double>(D.m, D.plg_cell, D.full_ptr, D.full_col, D.full_val64, b, u, D.rplg64, st);
     int nb = launch_residual_norm(D.args, u, b, D.mask, D.plgidx, D.rplg64, r32, r64, h->partial, st);
     return device_absmax_finish(h, nb, st);
+}
+
+// ||b - A u||_inf of the finest level into *h->host_scalar (no synchronisation)
+void enqueue_residual(mg_handle h, bool mixed, hipStream_t st) {
+    DevLevel &D = h->dev[0];
+    launch_plg_residual<double>(D.m, D.plg_cell, D.full_ptr, D.full_col, D.full_val64, D.b64, D.u64[0], D.rplg64, st);
+    int nb = launch_residual_norm(D.args, D.u64[0], D.b64, D.mask, D.plgidx, D.rplg64, mixed ? D.b32 : nullptr,
+                                  nullptr, h->partial, st);
+    launch_absmax(nb, h->partial, nullptr, h->partial + h->npartial - 1, 1, st);
+    HIPCHECK(hipMemcpyAsync(h->host_scalar, h->partial + h->npartial - 1, sizeof(double), hipMemcpyDeviceToHost, st));
+}
+
+// one outer iteration on the handle's own buffers: a V-cycle (FP64), or an
+// FP32 V-cycle on the FP32 residual added in FP64 (mixed); then the residual
+void enqueue_iteration(mg_handle h, bool mixed, hipStream_t st) {
+    DevLevel &D = h->dev[0];
+    if (mixed) {
+        launch_fill_zero(D.ncells, D.u32[0], st);
+        D.cur = 0;
+        vcycle<float>(h, 0, st);
+        launch_add_correction(D.ncells, D.mask, D.u32[D.cur], D.u64[0], st);
+    } else {
+        D.cur = 0;
+        vcycle<double>(h, 0, st);
+        if (D.cur != 0) HIPCHECK(hipMemcpyAsync(D.u64[0], D.u64[1], D.ncells * 8, hipMemcpyDeviceToDevice, st));
+    }
+    D.cur = 0;
+    enqueue_residual(h, mixed, st);
+}
+
+void run_iteration(mg_handle h, bool mixed, hipStream_t st) {
+    const int p = mixed ? 1 : 0;
+    if (h->timing) {                     // eager launches (events around the sweeps)
+        enqueue_iteration(h, mixed, st);
+        return;
+    }
+    if (!h->iter_exec[p]) {
+        if (!h->cap_stream) HIPCHECK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+        HIPCHECK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+        enqueue_iteration(h, mixed, h->cap_stream);
+        HIPCHECK(hipStreamEndCapture(h->cap_stream, &h->iter_graph[p]));
+        HIPCHECK(hipGraphInstantiate(&h->iter_exec[p], h->iter_graph[p], nullptr, nullptr, 0));
+    }
+    HIPCHECK(hipGraphLaunch(h->iter_exec[p], st));
 }
 
 thread_local std::string g_last_error;
@@ -631,34 +680,27 @@ mg_status mg_solve(mg_handle h, const double *f_dev, const double *g_dev, double
         double bnorm = device_absmax_finish(h, nb, st);
         if (bnorm == 0.0) bnorm = 1.0;
         const bool mixed = h->opt.precision == MG_MIXED;
-        double *keep_u = D.u64[0];
-        D.u64[0] = u_dev;
+        // iterate on the handle's own finest-level buffer (fixed addresses,
+        // so the captured iteration can be replayed)
+        HIPCHECK(hipMemcpyAsync(D.u64[0], u_dev, D.ncells * 8, hipMemcpyDeviceToDevice, st));
+        enqueue_residual(h, mixed, st);
+        HIPCHECK(hipStreamSynchronize(st));
         int it = 0, grow = 0;
-        double rel = residual_norm(h, 0, u_dev, D.b64, mixed ? D.b32 : nullptr, nullptr, st) / bnorm;
+        double rel = *h->host_scalar / bnorm;
         double prev = rel;
         while (rel > tol && it < h->opt.max_iters) {
-            if (mixed) {
-                HIPCHECK(hipMemsetAsync(D.u32[0], 0, D.ncells * sizeof(float), st));
-                D.cur = 0;
-                vcycle<float>(h, 0, st);
-                launch_add_correction(D.ncells, D.mask, D.u32[D.cur], u_dev, st);
-                D.cur = 0;
-            } else {
-                D.cur = 0;
-                vcycle<double>(h, 0, st);
-                if (D.cur != 0) HIPCHECK(hipMemcpyAsync(u_dev, D.u64[1], D.ncells * 8, hipMemcpyDeviceToDevice, st));
-                D.cur = 0;
-            }
+            run_iteration(h, mixed, st);
+            HIPCHECK(hipStreamSynchronize(st));
             ++it;
-            rel = residual_norm(h, 0, u_dev, D.b64, mixed ? D.b32 : nullptr, nullptr, st) / bnorm;
+            rel = *h->host_scalar / bnorm;
             if (std::isnan(rel)) { result = MG_ERR_DIVERGED; break; }
             grow = rel > prev ? grow + 1 : 0;
             if (grow >= 3) { result = MG_ERR_DIVERGED; break; }
             prev = rel;
         }
+        HIPCHECK(hipMemcpyAsync(u_dev, D.u64[0], D.ncells * 8, hipMemcpyDeviceToDevice, st));
         launch_zero_inactive(D.ncells, D.mask, u_dev, st);
         HIPCHECK(hipStreamSynchronize(st));
-        D.u64[0] = keep_u;
         if (result == MG_OK && rel > tol) result = MG_ERR_NO_CONVERGENCE;
         if (iters) *iters = it;
         if (rel_residual) *rel_residual = rel;
@@ -875,6 +917,11 @@ mg_status mg_kernel_timing(mg_handle h, int enable, int *launches, double *avg_m
 mg_status mg_destroy(mg_handle h) {
     if (!h) return MG_OK;
     for (auto &e : h->ev) (void)hipEventDestroy(e);
+    for (int p = 0; p < 2; ++p) {
+        if (h->iter_exec[p]) (void)hipGraphExecDestroy(h->iter_exec[p]);
+        if (h->iter_graph[p]) (void)hipGraphDestroy(h->iter_graph[p]);
+    }
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     for (void *p : h->allocs) (void)hipFree(p);
     if (h->host_scalar) (void)hipHostFree(h->host_scalar);
     delete h;

@@ -88,20 +88,80 @@ __device__ __forceinline__ T apply_sfv(const LevelArgs &L, F at) {
     return s;
 }
 
-constexpr int TX = 64, TY = 16, HX = TX + 4, HY = TY + 4, NT = 256;
+constexpr int TX = 64, TY = 32, HX = TX + 4, HY = TY + 4, NT = 256;
+
+// Ghost value at (qi, qj) outside the box from a tile held in LDS; the tile
+// origin (i0 - 2, j0 - 2) must contain the 4 interior cells next to the box
+// edge in each direction the position lies beyond.
+template <typename T>
+__device__ __forceinline__ T ghost_lds(const T (*s)[HX], const LevelArgs &L, int i0, int j0, int qi, int qj) {
+    auto at = [&](int i, int j) { return (double)s[j - j0 + 2][i - i0 + 2]; };
+    const bool ox = qi < 0 || qi >= L.nx, oy = qj < 0 || qj >= L.ny;
+    if (ox && oy) {
+        const int xside = qi < 0 ? 3 : 1, yside = qj < 0 ? 0 : 2;
+        const int m = qi < 0 ? -qi : qi - L.nx + 1, k = qj < 0 ? -qj : qj - L.ny + 1;
+        const double *gx = c_gw[L.bc[xside]][m - 1];
+        const double *gy = c_gw[L.bc[yside]][k - 1];
+        double sum = 0.0;
+        for (int p = 0; p < 4; ++p) {
+            const int col = xside == 3 ? p : L.nx - 1 - p;
+            double t = 0.0;
+            for (int q = 0; q < 4; ++q) t += gy[q] * at(col, yside == 0 ? q : L.ny - 1 - q);
+            sum += gx[p] * t;
+        }
+        return (T)sum;
+    }
+    int side, depth;
+    if (qj < 0) { side = 0; depth = -qj; }
+    else if (qj >= L.ny) { side = 2; depth = qj - L.ny + 1; }
+    else if (qi < 0) { side = 3; depth = -qi; }
+    else { side = 1; depth = qi - L.nx + 1; }
+    const double *w = c_gw[L.bc[side]][depth - 1];
+    double sum = 0.0;
+    for (int k = 0; k < 4; ++k) {
+        if (side == 0) sum += w[k] * at(qi, k);
+        else if (side == 2) sum += w[k] * at(qi, L.ny - 1 - k);
+        else if (side == 3) sum += w[k] * at(k, qj);
+        else sum += w[k] * at(L.nx - 1 - k, qj);
+    }
+    return (T)sum;
+}
 
 // Loads the (TY+4) x (TX+4) tile with halo into LDS; halo positions outside
-// the box are filled with ghost values (only blocks touching the box edge).
+// the box are ghost values.  A block at the box edge first loads the interior
+// cells, then fills the ghosts from LDS when the 4 cells inward from each
+// edge it touches lie in the tile (always so when nx, ny are multiples of 4
+// and at least 4 cells remain in the last tile), else from global memory.
 template <typename T>
 __device__ __forceinline__ void load_tile(T (*s)[HX], const T *__restrict__ u, const LevelArgs &L, int i0, int j0) {
     const bool edge = i0 < 2 || j0 < 2 || i0 + TX + 2 > L.nx || j0 + TY + 2 > L.ny;
+    // all global loads of a thread are issued before any LDS store
+    constexpr int NL = (HX * HY + NT - 1) / NT;
+    T v[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int t = threadIdx.x + k * NT;
+        const int ly = t / HX, lx = t - ly * HX;
+        const int qi = i0 - 2 + lx, qj = j0 - 2 + ly;
+        v[k] = (t < HX * HY && qi >= 0 && qi < L.nx && qj >= 0 && qj < L.ny) ? u[pidx(L, qi, qj)] : (T)0;
+    }
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int t = threadIdx.x + k * NT;
+        if (t < HX * HY) s[t / HX][t % HX] = v[k];
+    }
+    if (!edge) return;
+    // the tile holds cells [i0 - 2, i0 + TX + 2) x [j0 - 2, j0 + TY + 2);
+    // the left and bottom edges (i0 = 0, j0 = 0) always have their 4 inward
+    // cells in it, the right and top edges when nx - 4 >= i0 - 2 (ny - 4 >= j0 - 2)
+    const bool lds_ok = (i0 + TX + 2 <= L.nx || L.nx - 4 >= i0 - 2) && (j0 + TY + 2 <= L.ny || L.ny - 4 >= j0 - 2);
+    __syncthreads();
     for (int t = threadIdx.x; t < HX * HY; t += NT) {
         const int ly = t / HX, lx = t - ly * HX;
         const int qi = i0 - 2 + lx, qj = j0 - 2 + ly;
-        T v = 0;
-        if (qi >= 0 && qi < L.nx && qj >= 0 && qj < L.ny) v = u[pidx(L, qi, qj)];
-        else if (edge && qi >= -2 && qi < L.nx + 2 && qj >= -2 && qj < L.ny + 2) v = ghost_value(u, L, qi, qj);
-        s[ly][lx] = v;
+        const bool inside = qi >= 0 && qi < L.nx && qj >= 0 && qj < L.ny;
+        if (!inside && qi >= -2 && qi < L.nx + 2 && qj >= -2 && qj < L.ny + 2)
+            s[ly][lx] = lds_ok ? ghost_lds<T>(s, L, i0, j0, qi, qj) : ghost_value(u, L, qi, qj);
     }
 }
 
@@ -111,82 +171,153 @@ template <typename T, bool MIXED>
 __global__ __launch_bounds__(NT) void k_jacobi(LevelArgs L, const T *__restrict__ uold, const T *__restrict__ b,
                                                T *__restrict__ unew, const uint8_t *__restrict__ mask) {
     __shared__ T s[HY][HX];
+    constexpr int R = TY / (NT / TX);            // rows per thread
     const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int i = i0 + tx;
+    // issue the per-cell loads before the tile barrier so that their latency
+    // overlaps the tile load
+    uint8_t mk[R];
+    T bv[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int j = j0 + ty + k * (NT / TX);
+        const bool in = i < L.nx && j < L.ny;
+        const size_t id = pidx(L, in ? i : 0, in ? j : 0);
+        mk[k] = in ? mask[id] : 0;
+        bv[k] = b[id];
+    }
     load_tile<T>(s, uold, L, i0, j0);
     __syncthreads();
-    const int tx = threadIdx.x % TX;
     const T wod = (T)L.omega_over_d;
-    for (int r = threadIdx.x / TX; r < TY; r += NT / TX) {
-        const int i = i0 + tx, j = j0 + r;
-        if (i >= L.nx || j >= L.ny) continue;
-        const size_t id = pidx(L, i, j);
-        if (mask[id] != 1) continue;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        if (mk[k] != 1) continue;
+        const int r = ty + k * (NT / TX);
         const int lx = tx + 2, ly = r + 2;
         T au = apply_sfv<T, MIXED>(L, [&](int dx, int dy) { return s[ly + dy][lx + dx]; });
-        unew[id] = s[ly][lx] + wod * (b[id] - au);
+        unew[pidx(L, i, j0 + r)] = s[ly][lx] + wod * (bv[k] - au);
     }
 }
 
 // ---------------------------------------------------------------------------
 // PLG rows: t = b2 - A21 u1 (eq. (5.6)), then u2 = A22^{-1} t via the
 // segment / separator decomposition.
-// P1: one block per segment: t_j, y_j = B_j^{-1} t_j (u2 = y_j if no separators)
+// Dense row-major blocks are applied one wavefront per row: the 64 lanes
+// read consecutive columns (coalesced) and the partial sums are reduced
+// across the wavefront.
 template <typename T>
-__global__ __launch_bounds__(256) void k_plg_seg(PlgDev<T> P, const T *__restrict__ b, T *__restrict__ u) {
+__device__ __forceinline__ T wave_sum(T v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+constexpr int PLG_ROWS = 32;     // rows per block in the PLG kernels (8 per wavefront)
+
+// t = b2 - A21 u1 for all PLG rows (solve order): 32 lanes per row gather the
+// row's SFV couplings in parallel.
+template <typename T>
+__global__ __launch_bounds__(256) void k_plg_gather(PlgDev<T> P, const T *__restrict__ b, const T *__restrict__ u,
+                                                    T *__restrict__ t) {
+    const int q = blockIdx.x * 8 + (threadIdx.x >> 5);
+    const int lane = threadIdx.x & 31;
+    if (q >= P.m) return;
+    const int e0 = P.a21_ptr[q], e1 = P.a21_ptr[q + 1];
+    T v = 0;
+    for (int e = e0 + lane; e < e1; e += 32) v += P.a21_val[e] * u[P.a21_col[e]];
+    for (int off = 16; off > 0; off >>= 1) v += __shfl_down(v, off, 32);
+    if (lane == 0) t[q] = b[P.cell[q]] - v;
+}
+
+// P1: block (j, rb): rows [rb * PLG_ROWS, ...) of y_j = B_j^{-1} t_j
+// (u2 = y_j if there are no separators)
+template <typename T>
+__global__ __launch_bounds__(256) void k_plg_seg(PlgDev<T> P, const T *__restrict__ tg, T *__restrict__ u) {
     extern __shared__ unsigned char smem_raw[];
     T *t = reinterpret_cast<T *>(smem_raw);
     const int j = blockIdx.x;
     const int s0 = P.seg_start[j], Lj = P.seg_start[j + 1] - s0;
-    for (int r = threadIdx.x; r < Lj; r += blockDim.x) {
-        const int q = s0 + r;
-        T v = b[P.cell[q]];
-        for (int e = P.a21_ptr[q]; e < P.a21_ptr[q + 1]; ++e) v -= P.a21_val[e] * u[P.a21_col[e]];
-        t[r] = v;
-    }
+    const int r0 = blockIdx.y * PLG_ROWS;
+    if (r0 >= Lj) return;
+    for (int r = threadIdx.x; r < Lj; r += blockDim.x) t[r] = tg[s0 + r];
     __syncthreads();
     const T *inv = P.inv + P.inv_off[j];
-    for (int r = threadIdx.x; r < Lj; r += blockDim.x) {
-        T acc = 0;
-        for (int c = 0; c < Lj; ++c) acc += inv[(size_t)c * Lj + r] * t[c];
-        if (P.nsep == 0) u[P.cell[s0 + r]] = acc;
-        else P.y[s0 + r] = acc;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int rw = r0 + wave * (PLG_ROWS / 4);
+    T acc[PLG_ROWS / 4];
+#pragma unroll
+    for (int k = 0; k < PLG_ROWS / 4; ++k) acc[k] = 0;
+    for (int c = lane; c < Lj; c += 64) {
+        const T x = t[c];
+#pragma unroll
+        for (int k = 0; k < PLG_ROWS / 4; ++k)
+            if (rw + k < Lj) acc[k] += inv[(size_t)(rw + k) * Lj + c] * x;
+    }
+#pragma unroll
+    for (int k = 0; k < PLG_ROWS / 4; ++k) {
+        const T a = wave_sum(acc[k]);
+        if (lane == 0 && rw + k < Lj) {
+            if (P.nsep == 0) u[P.cell[s0 + rw + k]] = a;
+            else P.y[s0 + rw + k] = a;
+        }
     }
 }
 
-// P2: separators: r_S = t_S - A_SB y, x_S = S'^{-1} r_S (each block recomputes r_S)
+// P2a: separator right-hand side r_S = t_S - A_SB y, 32 lanes per row
 template <typename T>
-__global__ __launch_bounds__(256) void k_plg_sep(PlgDev<T> P, const T *__restrict__ b, T *__restrict__ u) {
+__global__ __launch_bounds__(256) void k_plg_sep_rhs(PlgDev<T> P, const T *__restrict__ tg) {
+    const int s = blockIdx.x * 8 + (threadIdx.x >> 5);
+    const int lane = threadIdx.x & 31;
+    if (s >= P.nsep) return;
+    T v = 0;
+    for (int e = P.sb_ptr[s] + lane; e < P.sb_ptr[s + 1]; e += 32) v += P.sb_val[e] * P.y[P.sb_col[e]];
+    for (int off = 16; off > 0; off >>= 1) v += __shfl_down(v, off, 32);
+    if (lane == 0) P.rs[s] = tg[P.sep_begin + s] - v;
+}
+
+// P2b: x_S = S'^{-1} r_S for the block's rows
+template <typename T>
+__global__ __launch_bounds__(256) void k_plg_sep(PlgDev<T> P, T *__restrict__ u) {
     extern __shared__ unsigned char smem_raw[];
     T *rs = reinterpret_cast<T *>(smem_raw);
     const int ns = P.nsep;
-    for (int s = threadIdx.x; s < ns; s += blockDim.x) {
-        const int q = P.sep_begin + s;
-        T v = b[P.cell[q]];
-        for (int e = P.a21_ptr[q]; e < P.a21_ptr[q + 1]; ++e) v -= P.a21_val[e] * u[P.a21_col[e]];
-        for (int e = P.sb_ptr[s]; e < P.sb_ptr[s + 1]; ++e) v -= P.sb_val[e] * P.y[P.sb_col[e]];
-        rs[s] = v;
-    }
+    for (int s = threadIdx.x; s < ns; s += blockDim.x) rs[s] = P.rs[s];
     __syncthreads();
-    const int row = blockIdx.x * blockDim.x + threadIdx.x;
-    if (row < ns) {
-        T acc = 0;
-        for (int c = 0; c < ns; ++c) acc += P.sinv[(size_t)c * ns + row] * rs[c];
-        P.xs[row] = acc;
-        u[P.cell[P.sep_begin + row]] = acc;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r0 = blockIdx.x * PLG_ROWS + wave * (PLG_ROWS / 4);
+    T acc[PLG_ROWS / 4];
+#pragma unroll
+    for (int k = 0; k < PLG_ROWS / 4; ++k) acc[k] = 0;
+    for (int c = lane; c < ns; c += 64) {
+        const T x = rs[c];
+#pragma unroll
+        for (int k = 0; k < PLG_ROWS / 4; ++k)
+            if (r0 + k < ns) acc[k] += P.sinv[(size_t)(r0 + k) * ns + c] * x;
+    }
+#pragma unroll
+    for (int k = 0; k < PLG_ROWS / 4; ++k) {
+        const T a = wave_sum(acc[k]);
+        if (lane == 0 && r0 + k < ns) {
+            P.xs[r0 + k] = a;
+            u[P.cell[P.sep_begin + r0 + k]] = a;
+        }
     }
 }
 
-// P3: x_j = y_j - F_j x_S
+// P3: x_j = y_j - F_j x_S (F_j row-major, L_j x k_j)
 template <typename T>
 __global__ __launch_bounds__(256) void k_plg_fix(PlgDev<T> P, T *__restrict__ u) {
     const int j = blockIdx.x;
     const int s0 = P.seg_start[j], Lj = P.seg_start[j + 1] - s0;
     const int k0 = P.fcols_ptr[j], k = P.fcols_ptr[j + 1] - k0;
     const T *F = P.F + P.f_off[j];
-    for (int r = threadIdx.x; r < Lj; r += blockDim.x) {
-        T acc = P.y[s0 + r];
-        for (int kk = 0; kk < k; ++kk) acc -= F[(size_t)kk * Lj + r] * P.xs[P.fcols[k0 + kk]];
-        u[P.cell[s0 + r]] = acc;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r0 = blockIdx.y * PLG_ROWS;
+    for (int r = r0 + wave; r < min(r0 + PLG_ROWS, Lj); r += 4) {
+        T acc = 0;
+        for (int kk = lane; kk < k; kk += 64) acc += F[(size_t)r * k + kk] * P.xs[P.fcols[k0 + kk]];
+        acc = wave_sum(acc);
+        if (lane == 0) u[P.cell[s0 + r]] = P.y[s0 + r] - acc;
     }
 }
 
@@ -214,34 +345,48 @@ __global__ __launch_bounds__(NT) void k_restrict(LevelArgs L, LevelArgs C, const
                                                  T *__restrict__ uc) {
     __shared__ T s[HY][HX];
     const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+    constexpr int NC = (TX / 2) * (TY / 2) / NT;      // coarse cells per thread
+    uint8_t ck[NC], fk[NC][4];
+    T fb[NC][4];
+#pragma unroll
+    for (int n = 0; n < NC; ++n) {
+        const int t = threadIdx.x + n * NT;
+        const int ci = blockIdx.x * (TX / 2) + t % (TX / 2), cj = blockIdx.y * (TY / 2) + t / (TX / 2);
+        const bool cin = ci < C.nx && cj < C.ny;
+        ck[n] = cin ? cmask[pidx(C, ci, cj)] : 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int fi = 2 * ci + (q & 1), fj = 2 * cj + (q >> 1);
+            const bool fin = cin && fi < L.nx && fj < L.ny;
+            const size_t id = pidx(L, fin ? fi : 0, fin ? fj : 0);
+            fk[n][q] = fin ? mask[id] : 0;
+            fb[n][q] = b[id];
+        }
+    }
     load_tile<T>(s, u, L, i0, j0);
     __syncthreads();
-    const int ci = blockIdx.x * (TX / 2) + threadIdx.x % (TX / 2);
-    const int cj = blockIdx.y * (TY / 2) + threadIdx.x / (TX / 2);
-    if (ci >= C.nx || cj >= C.ny) return;
-    const size_t cid = pidx(C, ci, cj);
-    uc[cid] = 0;
-    if (!cmask[cid]) {
-        bc[cid] = 0;
-        return;
-    }
-    T sum = 0;
 #pragma unroll
-    for (int dj = 0; dj < 2; ++dj)
+    for (int n = 0; n < NC; ++n) {
+        const int t = threadIdx.x + n * NT;
+        const int ci = blockIdx.x * (TX / 2) + t % (TX / 2), cj = blockIdx.y * (TY / 2) + t / (TX / 2);
+        if (ci >= C.nx || cj >= C.ny) continue;
+        const size_t cid = pidx(C, ci, cj);
+        uc[cid] = 0;
+        T sum = 0;
+        if (ck[n]) {
 #pragma unroll
-        for (int di = 0; di < 2; ++di) {
-            const int i = 2 * ci + di, j = 2 * cj + dj;
-            if (i >= L.nx || j >= L.ny) continue;
-            const size_t id = pidx(L, i, j);
-            const uint8_t k = mask[id];
-            if (k == 1) {
-                const int lx = i - i0 + 2, ly = j - j0 + 2;
-                sum += b[id] - apply_sfv<T, MIXED>(L, [&](int dx, int dy) { return s[ly + dy][lx + dx]; });
-            } else if (k == 2) {
-                sum += rplg[plgidx[id]];
+            for (int q = 0; q < 4; ++q) {
+                const int fi = 2 * ci + (q & 1), fj = 2 * cj + (q >> 1);
+                if (fk[n][q] == 1) {
+                    const int lx = fi - i0 + 2, ly = fj - j0 + 2;
+                    sum += fb[n][q] - apply_sfv<T, MIXED>(L, [&](int dx, int dy) { return s[ly + dy][lx + dx]; });
+                } else if (fk[n][q] == 2) {
+                    sum += rplg[plgidx[pidx(L, fi, fj)]];
+                }
             }
         }
-    bc[cid] = (T)0.25 * sum;
+        bc[cid] = (T)0.25 * sum;
+    }
 }
 
 // fine cells whose coarse parent was merged away: add to the absorbing cell
@@ -284,26 +429,26 @@ __global__ void k_prolong_ex(int n, const int *__restrict__ fine, const int *__r
 }
 
 // ---------------------------------------------------------------------------
-// K6: bottom solve x = A_c^{-1} b (FP64 dense inverse, row-major); one
-// wavefront per row, the right-hand side staged in LDS.
+// K6: bottom solve x = A_c^{-1} b (FP64 dense inverse, row-major): one
+// wavefront per row, 16 wavefronts per block, the right-hand side staged in
+// LDS by every block.
+constexpr int BOT_WAVES = 16;
 template <typename TI, typename TO>
-__global__ __launch_bounds__(256) void k_bottom(int n, const int *__restrict__ cells, const double *__restrict__ ainv,
-                                                const TI *__restrict__ b, TO *__restrict__ x) {
+__global__ __launch_bounds__(64 * BOT_WAVES) void k_bottom(int n, const int *__restrict__ cells,
+                                                          const double *__restrict__ ainv, const TI *__restrict__ b,
+                                                          TO *__restrict__ x) {
     extern __shared__ unsigned char smem_raw[];
     double *bs = reinterpret_cast<double *>(smem_raw);
     for (int k = threadIdx.x; k < n; k += blockDim.x) bs[k] = (double)b[cells[k]];
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int rows_per_block = 16;
-    for (int rr = wave; rr < rows_per_block; rr += 4) {
-        const int row = blockIdx.x * rows_per_block + rr;
-        if (row >= n) break;
-        const double *a = ainv + (size_t)row * n;
-        double acc = 0.0;
-        for (int c = lane; c < n; c += 64) acc += a[c] * bs[c];
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-        if (lane == 0) x[cells[row]] = (TO)acc;
-    }
+    const int row = blockIdx.x * BOT_WAVES + wave;
+    if (row >= n) return;
+    const double *a = ainv + (size_t)row * n;
+    double acc = 0.0;
+    for (int c = lane; c < n; c += 64) acc += a[c] * bs[c];
+    acc = wave_sum(acc);
+    if (lane == 0) x[cells[row]] = (TO)acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -317,21 +462,34 @@ __global__ __launch_bounds__(NT) void k_residual_norm(LevelArgs L, const double 
                                                       double *__restrict__ partial) {
     __shared__ double s[HY][HX];
     __shared__ double red[NT];
+    constexpr int R = TY / (NT / TX);
     const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int i = i0 + tx;
+    uint8_t mk[R];
+    double bv[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int j = j0 + ty + k * (NT / TX);
+        const bool in = i < L.nx && j < L.ny;
+        const size_t id = pidx(L, in ? i : 0, in ? j : 0);
+        mk[k] = in ? mask[id] : 0;
+        bv[k] = b[id];
+    }
     load_tile<double>(s, u, L, i0, j0);
     __syncthreads();
-    const int tx = threadIdx.x % TX;
     double mx = 0.0;
-    for (int rr = threadIdx.x / TX; rr < TY; rr += NT / TX) {
-        const int i = i0 + tx, j = j0 + rr;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int rr = ty + k * (NT / TX);
+        const int j = j0 + rr;
         if (i >= L.nx || j >= L.ny) continue;
         const size_t id = pidx(L, i, j);
-        const uint8_t k = mask[id];
         double r = 0.0;
-        if (k == 1) {
+        if (mk[k] == 1) {
             const int lx = tx + 2, ly = rr + 2;
-            r = b[id] - apply_sfv<double, MIXED>(L, [&](int dx, int dy) { return s[ly + dy][lx + dx]; });
-        } else if (k == 2) {
+            r = bv[k] - apply_sfv<double, MIXED>(L, [&](int dx, int dy) { return s[ly + dy][lx + dx]; });
+        } else if (mk[k] == 2) {
             r = rplg[plgidx[id]];
         }
         if (WRITE32) r32[id] = (float)r;
@@ -384,6 +542,11 @@ __global__ void k_add_correction(size_t n, const uint8_t *__restrict__ mask, con
                                  double *__restrict__ u) {
     const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < n && mask[k]) u[k] += (double)e[k];
+}
+
+__global__ void k_fill_zero_f32(size_t n, float *__restrict__ u) {
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) u[k] = 0.0f;
 }
 
 __global__ void k_zero_inactive(size_t n, const uint8_t *__restrict__ mask, double *__restrict__ u) {
@@ -472,10 +635,14 @@ void launch_jacobi(const LevelArgs &L, const T *uold, const T *b, T *unew, const
 template <typename T>
 void launch_plg_solve(const PlgDev<T> &P, const T *b, T *u, hipStream_t st) {
     if (P.m == 0) return;
-    if (P.nseg) hipLaunchKernelGGL((k_plg_seg<T>), dim3(P.nseg), dim3(256), sizeof(T) * P.max_seg, st, P, b, u);
+    const unsigned rb = (P.max_seg + PLG_ROWS - 1) / PLG_ROWS;
+    hipLaunchKernelGGL((k_plg_gather<T>), dim3((P.m + 7) / 8), dim3(256), 0, st, P, b, u, P.t);
+    if (P.nseg) hipLaunchKernelGGL((k_plg_seg<T>), dim3(P.nseg, rb), dim3(256), sizeof(T) * P.max_seg, st, P, P.t, u);
     if (P.nsep) {
-        hipLaunchKernelGGL((k_plg_sep<T>), dim3((P.nsep + 255) / 256), dim3(256), sizeof(T) * P.nsep, st, P, b, u);
-        if (P.nseg) hipLaunchKernelGGL((k_plg_fix<T>), dim3(P.nseg), dim3(256), 0, st, P, u);
+        hipLaunchKernelGGL((k_plg_sep_rhs<T>), dim3((P.nsep + 7) / 8), dim3(256), 0, st, P, P.t);
+        hipLaunchKernelGGL((k_plg_sep<T>), dim3((P.nsep + PLG_ROWS - 1) / PLG_ROWS), dim3(256), sizeof(T) * P.nsep, st,
+                           P, u);
+        if (P.nseg) hipLaunchKernelGGL((k_plg_fix<T>), dim3(P.nseg, rb), dim3(256), 0, st, P, u);
     }
 }
 
@@ -515,7 +682,8 @@ void launch_prolong(const LevelArgs &L, const LevelArgs &C, const uint8_t *mask,
 
 template <typename TI, typename TO>
 void launch_bottom(int n, const int *cells, const double *ainv, const TI *b, TO *x, hipStream_t st) {
-    hipLaunchKernelGGL((k_bottom<TI, TO>), dim3((n + 15) / 16), dim3(256), sizeof(double) * n, st, n, cells, ainv, b, x);
+    hipLaunchKernelGGL((k_bottom<TI, TO>), dim3((n + BOT_WAVES - 1) / BOT_WAVES), dim3(64 * BOT_WAVES),
+                       sizeof(double) * n, st, n, cells, ainv, b, x);
 }
 
 int launch_residual_norm(const LevelArgs &L, const double *u, const double *b, const uint8_t *mask, const int *plgidx,
@@ -544,6 +712,10 @@ void launch_rhs(size_t n, const uint8_t *mask, const double *f, double *b, int n
 
 void launch_add_correction(size_t n, const uint8_t *mask, const float *e, double *u, hipStream_t st) {
     hipLaunchKernelGGL(k_add_correction, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, mask, e, u);
+}
+
+void launch_fill_zero(size_t n, float *u, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_zero_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, u);
 }
 
 void launch_zero_inactive(size_t n, const uint8_t *mask, double *u, hipStream_t st) {

@@ -36,15 +36,17 @@ struct PlgDev {
     const T *a21_val = nullptr;
     const int *seg_start = nullptr;     // [nseg+1]
     const long long *inv_off = nullptr; // [nseg]
-    const T *inv = nullptr;             // column-major segment inverses
+    const T *inv = nullptr;             // row-major segment inverses
     const long long *f_off = nullptr;
     const T *F = nullptr;
     const int *fcols_ptr = nullptr, *fcols = nullptr;
-    const T *sinv = nullptr;            // column-major
+    const T *sinv = nullptr;            // row-major
     const int *sb_ptr = nullptr, *sb_col = nullptr;   // separator rows -> segment positions
     const T *sb_val = nullptr;
+    T *t = nullptr;                     // [m] workspace: b2 - A21 u1
     T *y = nullptr;                     // [m] workspace
     T *xs = nullptr;                    // [nsep] workspace
+    T *rs = nullptr;                    // [nsep] workspace: separator right-hand side
     int max_seg = 0;
 };
 

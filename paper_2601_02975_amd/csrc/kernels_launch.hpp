@@ -32,6 +32,7 @@ void launch_rhs(size_t n, const uint8_t *mask, const double *f, double *b, int n
                 const int *gidx, const double *coef, const double *g, hipStream_t st);
 void launch_add_correction(size_t n, const uint8_t *mask, const float *e, double *u, hipStream_t st);
 void launch_zero_inactive(size_t n, const uint8_t *mask, double *u, hipStream_t st);
+void launch_fill_zero(size_t n, float *u, hipStream_t st);
 void launch_fit(int m, const double *M, const double *phi, const double *w, const int *ncol, double *work,
                 double *beta, int *status, hipStream_t st);
 

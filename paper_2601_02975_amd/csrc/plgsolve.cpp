@@ -244,10 +244,9 @@ void build_plg_solver(const Level &L, int seg_max, PlgSolver &S) {
             singular = true;
             continue;
         }
-        // stored column-major: inv[c * Lj + r] = B^{-1}[r][c]
+        // stored row-major
         double *dst = &S.inv[S.inv_off[j]];
-        for (int r = 0; r < Lj; ++r)
-            for (int c = 0; c < Lj; ++c) dst[(size_t)c * Lj + r] = B[(size_t)r * Lj + c];
+        for (size_t e = 0; e < (size_t)Lj * Lj; ++e) dst[e] = B[e];
         // F = B^{-1} A_{j,S}
         int k = (int)cols.size();
         std::vector<double> AS((size_t)Lj * k, 0.0);
@@ -277,9 +276,8 @@ void build_plg_solver(const Level &L, int seg_max, PlgSolver &S) {
     S.fcols.clear();
     for (int j = 0; j < nb; ++j) {
         int Lj = S.seg_start[j + 1] - S.seg_start[j], k = (int)fcols[j].size();
-        // column-major: F[kk * Lj + r]
-        for (int r = 0; r < Lj; ++r)
-            for (int kk = 0; kk < k; ++kk) S.F[S.f_off[j] + (size_t)kk * Lj + r] = Fj[j][(size_t)r * k + kk];
+        // row-major: F[r * k + kk]
+        for (size_t e = 0; e < (size_t)Lj * k; ++e) S.F[S.f_off[j] + e] = Fj[j][e];
         for (int c : fcols[j]) S.fcols.push_back(c);
         // Schur complement: S' -= A_{S,j} F_j
         int s0 = S.seg_start[j];
@@ -293,9 +291,7 @@ void build_plg_solver(const Level &L, int seg_max, PlgSolver &S) {
     }
     if (ns > 0) {
         if (!invert_dense(ns, Sp)) fail(MG_ERR_SINGULAR, "the PLG separator block is singular");
-        S.sinv.assign((size_t)ns * ns, 0.0);
-        for (int r = 0; r < ns; ++r)
-            for (int c = 0; c < ns; ++c) S.sinv[(size_t)c * ns + r] = Sp[(size_t)r * ns + c];
+        S.sinv = Sp;                                // row-major
     }
     // separator rows: couplings to segment unknowns (positions < sb)
     S.sb_ptr.assign(ns + 1, 0);

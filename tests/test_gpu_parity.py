@@ -103,10 +103,12 @@ def test_rhs_parity(name):
     assert S.info["n_face"] + S.info["n_irr"] == len(g)
     bd = torch.zeros_like(to_dev(L, f))
     S.rhs(to_dev(L, f), torch.tensor(g, device="cuda"), bd)
-    # both sides sum the same terms in different orders: the difference is
-    # bounded by a few units of roundoff of the summed magnitudes
-    mag = np.abs(f) + abs(L.N) @ np.abs(g)
-    assert np.abs(from_dev(L, bd) - b).max() <= 16 * np.finfo(float).eps * mag.max()
+    # the GPU applies its own N (box ghost weights, and fitted beta_b that
+    # match the oracle's to the setup-parity bound of 1e-12 relative) and sums
+    # in a different order: |db| <= 16 eps (|f| + |N||g|) + 1e-12 |N||g|
+    ng = abs(L.N) @ np.abs(g)
+    bound = 16 * np.finfo(float).eps * (np.abs(f) + ng) + 1e-12 * ng
+    assert np.all(np.abs(from_dev(L, bd) - b) <= bound + 1e-300)
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -212,3 +214,28 @@ def test_mixed_step_is_fp32_accurate(name):
     d = rel(from_dev(L, u32), from_dev(L, u64))
     print("one mixed step vs one FP64 V-cycle: rel diff %.2e" % d)
     assert 1e-12 < d < 1e-4
+
+
+@pytest.mark.parametrize("name", ["disk64", "three_disks128"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replays_match_eager(name, precision):
+    """The captured outer iteration (HIP graph) gives bitwise the same
+    solution as eager launches, over several solves in a row with eager work
+    of the same handle in between."""
+    torch = _torch()
+    import paper_2601_02975_amd as mg
+    P, H = oracle(name)
+    S = mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=precision)
+    f, g = S.project(P.solution)
+    ft, gt = torch.tensor(f, device="cuda"), torch.tensor(g, device="cuda")
+    S.kernel_timing(True)                       # eager launches
+    ue = torch.zeros_like(ft)
+    it_e, rel_e, _ = S.solve(ft, gt, ue, 1e-10)
+    S.kernel_timing(False)
+    for k in range(3):
+        ug = torch.zeros_like(ft)
+        it_g, rel_g, _ = S.solve(ft, gt, ug, 1e-10)
+        assert it_g == it_e and rel_g == rel_e
+        assert torch.equal(ug, ue), "replay %d differs" % k
+        scratch = ug.clone()
+        S.smooth(0, ft, scratch)                # eager work between replays
