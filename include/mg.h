@@ -94,6 +94,11 @@ typedef struct {
     int n_active[16];          /* cut cells in C^h_eps per level */
     int n_plg[16];             /* PLG cells per level (Definition 4.1) */
     int n_sep[16];             /* separator unknowns of the PLG block solve per level */
+    long long sweep_words[16]; /* algorithmic words moved by the first launch of one smoother
+                                  sweep per level: u, b read and u written on every SFV cell,
+                                  every PLG segment inverse read once, b read and u (or the
+                                  segment solution) written on every PLG row; times the word
+                                  size (8 FP64, 4 FP32), plus nx*ny bytes of the class mask */
     int n_face, n_irr;         /* boundary-data layout sizes (finest level) */
     long long nnz_plg;         /* nonzeros of the PLG rows, all levels */
     long long device_bytes;    /* device memory held by the handle */
@@ -166,8 +171,10 @@ mg_status mg_destroy(mg_handle h);
 const char *mg_error_string(mg_status s);
 
 /* Kernel timing for measurement: enable = 1 clears and starts recording a
- * pair of HIP events around every launch of the finest-level SFV sweep
- * (eq. (5.5), the dominant kernel) on the stream it is launched on;
+ * pair of HIP events around every finest-level launch of the smoother's
+ * first kernel (the SFV Jacobi sweep of eq. (5.5) fused with the PLG
+ * right-hand sides and segment solves of eq. (5.6); the dominant kernel) on
+ * the stream it is launched on, and makes mg_solve launch eagerly;
  * enable = 0 stops recording, synchronises, and returns the number of
  * recorded launches and their average duration in milliseconds.  At most
  * 8192 launches are recorded. */

@@ -52,7 +52,7 @@ class mg_options(ctypes.Structure):
 class mg_info(ctypes.Structure):
     _fields_ = [("n_levels", ctypes.c_int), ("nx", ctypes.c_int * 16), ("ny", ctypes.c_int * 16),
                 ("n_active", ctypes.c_int * 16), ("n_plg", ctypes.c_int * 16), ("n_sep", ctypes.c_int * 16),
-                ("n_face", ctypes.c_int), ("n_irr", ctypes.c_int), ("nnz_plg", ctypes.c_longlong),
+                ("sweep_words", ctypes.c_longlong * 16), ("n_face", ctypes.c_int), ("n_irr", ctypes.c_int), ("nnz_plg", ctypes.c_longlong),
                 ("device_bytes", ctypes.c_longlong), ("setup_seconds", ctypes.c_double)]
 
 
@@ -214,7 +214,8 @@ class Solver:
         _check(lib().mg_query(self.h, ctypes.byref(inf)), "mg_query")
         n = inf.n_levels
         return {"n_levels": n, "nx": list(inf.nx[:n]), "ny": list(inf.ny[:n]), "n_active": list(inf.n_active[:n]),
-                "n_plg": list(inf.n_plg[:n]), "n_sep": list(inf.n_sep[:n]), "n_face": inf.n_face,
+                "n_plg": list(inf.n_plg[:n]), "n_sep": list(inf.n_sep[:n]),
+                "sweep_words": list(inf.sweep_words[:n]), "n_face": inf.n_face,
                 "n_irr": inf.n_irr, "nnz_plg": inf.nnz_plg, "device_bytes": inf.device_bytes,
                 "setup_seconds": inf.setup_seconds}
 

@@ -39,18 +39,22 @@ struct DevLevel {
     float *u32[2] = {nullptr, nullptr}, *b32 = nullptr, *rplg32 = nullptr;
     int m = 0;
     int *plg_cell = nullptr, *full_ptr = nullptr, *full_col = nullptr;
+    int *fe_col = nullptr;                  // PLG rows, fixed width (ELL_W), padded cell index
+    double *fe_val = nullptr;
     double *full_val64 = nullptr;
     float *full_val32 = nullptr;
     PlgDev<double> P64;
     PlgDev<float> P32;
-    int ex_nt = 0;
-    int *ex_ptr = nullptr, *ex_target = nullptr, *ex_child = nullptr;   // restriction to the next level
+    int ex_nt = 0;                                                      // restriction to the next level:
+    int *ex_ptr = nullptr, *ex_target = nullptr, *ex_child = nullptr;   // coarse cells with extra children
+    uint8_t *rmask = nullptr;                                           // next level: 0 off, 1 tile, 2 extra list
     int pex_n = 0;
     int *pex_fine = nullptr, *pex_coarse = nullptr;                     // prolongation from the next level
     int nbot = 0;
     int *bot_cells = nullptr;
     double *ainv = nullptr;
     int cur = 0;
+    long long sweep_words = 0;    // words moved by one smoother launch A (algorithmic)
 };
 
 }  // namespace
@@ -74,8 +78,9 @@ struct mg_handle_s {
     std::string last_error;
     // captured outer iteration per precision (0 FP64, 1 mixed)
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t iter_exec[2] = {nullptr, nullptr};
-    hipGraph_t iter_graph[2] = {nullptr, nullptr};
+    hipGraphExec_t iter_exec[3] = {nullptr, nullptr, nullptr};
+    hipGraph_t iter_graph[3] = {nullptr, nullptr, nullptr};
+    int upar = 0;                 // mixed precision: which FP64 buffer holds the iterate
     // timing of the finest-level SFV sweep
     bool timing = false;
     std::vector<hipEvent_t> ev;
@@ -221,23 +226,29 @@ void upload_level(mg_handle h, int l, bool last, hipStream_t st) {
     D.b32 = h->alloc<float>(D.ncells);
     // PLG rows in solve order
     D.m = S.m;
-    std::vector<int> cell(S.m), fptr(S.m + 1, 0), fcol, aptr(S.m + 1, 0), acol;
-    std::vector<double> fval, aval;
+    std::vector<int> cell(S.m), fptr(S.m + 1, 0), fcol;
+    std::vector<double> fval;
     for (int q = 0; q < S.m; ++q) {
         int r = S.order[q];
         cell[q] = (int)padded_index(nx, L.plg_cells[r]);
         for (int e = L.row_ptr[r]; e < L.row_ptr[r + 1]; ++e) {
-            int c = L.col[e];
-            fcol.push_back((int)padded_index(nx, c));
+            fcol.push_back((int)padded_index(nx, L.col[e]));
             fval.push_back(L.val[e]);
-            if (L.kind[c] == 1) {
-                acol.push_back((int)padded_index(nx, c));
-                aval.push_back(L.val[e]);
-            }
         }
         fptr[q + 1] = (int)fcol.size();
-        aptr[q + 1] = (int)acol.size();
     }
+    std::vector<int> fe_col((size_t)S.m * ELL_W);
+    std::vector<double> fe_val((size_t)S.m * ELL_W, 0.0);
+    for (int q = 0; q < S.m; ++q) {
+        if (fptr[q + 1] - fptr[q] > ELL_W) fail(MG_ERR_UNSUPPORTED, "a PLG row is wider than the row width");
+        for (int k = 0; k < ELL_W; ++k) {
+            const int e = fptr[q] + k;
+            fe_col[(size_t)q * ELL_W + k] = e < fptr[q + 1] ? fcol[e] : cell[q];
+            if (e < fptr[q + 1]) fe_val[(size_t)q * ELL_W + k] = fval[e];
+        }
+    }
+    D.fe_col = h->upload(fe_col);
+    D.fe_val = h->upload(fe_val);
     D.plg_cell = h->upload(cell);
     D.full_ptr = h->upload(fptr);
     D.full_col = h->upload(fcol);
@@ -245,31 +256,47 @@ void upload_level(mg_handle h, int l, bool last, hipStream_t st) {
     D.full_val32 = h->upload_f32<float>(fval);
     D.rplg64 = h->alloc<double>(S.m);
     D.rplg32 = h->alloc<float>(S.m);
-    int *a21_ptr = h->upload(aptr), *a21_col = h->upload(acol);
+    PlgPlan G;
+    build_plg_plan(L, S, nx, PLG_SLICE, PLG_LMAX, PLG_SEP_ROWS, G);
+    if (G.hmax > PLG_HMAX || G.lmax > PLG_LMAX || G.kmax > PLG_KMAX || S.nsep > PLG_SMAX)
+        fail(MG_ERR_UNSUPPORTED, "PLG block partition exceeds the LDS staging limits");
+    int *grp_start = h->upload(G.grp_start), *hptr = h->upload(G.hptr), *hcell = h->upload(G.hcell);
+    int *a21_loc = h->upload(G.a21_loc);
+    int *blk1 = h->upload(G.blk1), *blk2 = h->upload(G.blk2);
     int *seg_start = h->upload(S.seg_start);
-    long long *inv_off = h->upload(S.inv_off), *f_off = h->upload(S.f_off);
-    int *fcols_ptr = h->upload(S.fcols_ptr), *fcols = h->upload(S.fcols);
-    int *sb_ptr = h->upload(S.sb_ptr), *sb_col = h->upload(S.sb_col);
-    int max_seg = 0;
-    for (int j = 0; j < S.nseg; ++j) max_seg = std::max(max_seg, S.seg_start[j + 1] - S.seg_start[j]);
-    // the segment and separator right-hand sides are staged in LDS (FP64)
-    if ((size_t)max_seg * 8 > 65536 || (size_t)S.nsep * 8 > 65536)
-        fail(MG_ERR_UNSUPPORTED, "PLG block partition exceeds the LDS budget");
-    auto fill = [&](auto &P, auto *a21v, auto *inv, auto *F, auto *sinv, auto *sbv, auto *y, auto *xs, auto *t, auto *rs) {
+    long long *inv_off = h->upload(G.inv_off), *ft_off = h->upload(G.ft_off), *sj_off = h->upload(G.sj_off);
+    int *fcols_ptr = h->upload(S.fcols_ptr);
+    int *ce_ptr = h->upload(G.ce_ptr), *ce_row = h->upload(G.ce_row), *ce_slot = h->upload(G.ce_slot);
+    auto fill = [&](auto &P, auto *a21v, auto *inv, auto *cev, auto *FT, auto *SJ, auto *sinv, auto *t, auto *y,
+                    auto *contrib) {
         P.m = S.m; P.nseg = S.nseg; P.nsep = S.nsep; P.sep_begin = S.sep_begin;
-        P.cell = D.plg_cell; P.a21_ptr = a21_ptr; P.a21_col = a21_col; P.a21_val = a21v;
-        P.seg_start = seg_start; P.inv_off = inv_off; P.inv = inv; P.f_off = f_off; P.F = F;
-        P.fcols_ptr = fcols_ptr; P.fcols = fcols; P.sinv = sinv; P.sb_ptr = sb_ptr; P.sb_col = sb_col;
-        P.sb_val = sbv; P.y = y; P.xs = xs; P.t = t; P.rs = rs; P.max_seg = max_seg;
+        P.cell = D.plg_cell;
+        P.grp_start = grp_start; P.hptr = hptr; P.hcell = hcell;
+        P.a21_loc = a21_loc; P.a21_val = a21v;
+        P.nblk1 = (int)G.blk1.size() / 4; P.blk1 = reinterpret_cast<const int4 *>(blk1);
+        P.seg_start = seg_start; P.inv_off = inv_off; P.inv = inv;
+        P.ce_ptr = ce_ptr; P.ce_row = ce_row; P.ce_slot = ce_slot; P.ce_val = cev;
+        P.nblk2 = (int)G.blk2.size() / 4; P.blk2 = reinterpret_cast<const int4 *>(blk2);
+        P.ft_off = ft_off; P.FT = FT; P.fcols_ptr = fcols_ptr; P.sj_off = sj_off; P.SJ = SJ; P.sinv = sinv;
+        P.t = t; P.y = y; P.contrib = contrib;
     };
-    fill(D.P64, h->upload(aval), h->upload(S.inv), h->upload(S.F), h->upload(S.sinv), h->upload(S.sb_val),
-         h->alloc<double>(S.m), h->alloc<double>(S.nsep), h->alloc<double>(S.m), h->alloc<double>(S.nsep));
-    fill(D.P32, h->upload_f32<float>(aval), h->upload_f32<float>(S.inv), h->upload_f32<float>(S.F),
-         h->upload_f32<float>(S.sinv), h->upload_f32<float>(S.sb_val), h->alloc<float>(S.m), h->alloc<float>(S.nsep),
-         h->alloc<float>(S.m), h->alloc<float>(S.nsep));
+    const size_t nslot = (size_t)S.nsep * ELL_W;
+    fill(D.P64, h->upload(G.a21_val), h->upload(G.INV), h->upload(G.ce_val), h->upload(G.FT), h->upload(G.SJ),
+         h->upload(G.SINV), h->alloc<double>(S.m), h->alloc<double>(S.m), h->alloc<double>(nslot));
+    fill(D.P32, h->upload_f32<float>(G.a21_val), h->upload_f32<float>(G.INV), h->upload_f32<float>(G.ce_val),
+         h->upload_f32<float>(G.FT), h->upload_f32<float>(G.SJ), h->upload_f32<float>(G.SINV), h->alloc<float>(S.m),
+         h->alloc<float>(S.m), h->alloc<float>(nslot));
+    // algorithmic words of launch A: u, b read and u written on every SFV
+    // cell, each segment inverse read once, b read and u (or y) written on
+    // every PLG row
+    long long nsfv = 0;
+    for (int cl = 0; cl < nx * ny; ++cl) nsfv += L.kind[cl] == 1;
+    D.sweep_words = 3 * nsfv + (long long)S.inv.size() + 2LL * S.m;
     // transfers to the next level
     if (!last) {
         const Level &C = *h->levels[l + 1];
+        // fine cells whose coarse parent was merged away go to the cell that
+        // absorbed it (restriction and prolongation)
         std::vector<std::pair<int, int>> ex;        // (coarse target cell, fine cell)
         for (int cellf = 0; cellf < nx * ny; ++cellf) {
             if (!L.cg.active[cellf]) continue;
@@ -280,22 +307,37 @@ void upload_level(mg_handle h, int l, bool last, hipStream_t st) {
             if (own < 0) fail(MG_ERR_GEOMETRY, "fine cell without a coarse parent");
             ex.push_back({own, cellf});
         }
-        std::sort(ex.begin(), ex.end());
-        std::vector<int> ptr{0}, tgt, child, pf, pc;
-        for (size_t k = 0; k < ex.size(); ++k) {
-            if (k == 0 || ex[k].first != ex[k - 1].first) {
-                if (k) ptr.push_back((int)k);
-                tgt.push_back((int)padded_index(C.g.nx, ex[k].first));
-            }
-            child.push_back((int)padded_index(nx, ex[k].second));
-            pf.push_back((int)padded_index(nx, ex[k].second));
-            pc.push_back((int)padded_index(C.g.nx, ex[k].first));
+        std::vector<int> pf, pc;
+        for (auto &e : ex) {
+            pf.push_back((int)padded_index(nx, e.second));
+            pc.push_back((int)padded_index(C.g.nx, e.first));
         }
-        if (!ex.empty()) ptr.push_back((int)ex.size());
+        // restriction: coarse cells with extra children take all their
+        // children from a list (own active children first)
+        std::vector<int> tg;
+        for (auto &e : ex) tg.push_back(e.first);
+        std::sort(tg.begin(), tg.end());
+        tg.erase(std::unique(tg.begin(), tg.end()), tg.end());
+        std::vector<uint8_t> rmask((size_t)(C.g.nx + 4) * (C.g.ny + 4), 0);
+        for (int cc = 0; cc < C.g.nx * C.g.ny; ++cc) rmask[padded_index(C.g.nx, cc)] = C.cg.active[cc] ? 1 : 0;
+        std::vector<int> ptr{0}, tgt, child;
+        for (int t : tg) {
+            rmask[padded_index(C.g.nx, t)] = 2;
+            tgt.push_back((int)padded_index(C.g.nx, t));
+            const int ci = t % C.g.nx, cj = t / C.g.nx;
+            for (int q = 0; q < 4; ++q) {
+                const int fi = 2 * ci + (q & 1), fj = 2 * cj + (q >> 1);
+                if (fi < nx && fj < ny && L.cg.active[fj * nx + fi]) child.push_back((int)padded_index(nx, fj * nx + fi));
+            }
+            for (auto &e : ex)
+                if (e.first == t) child.push_back((int)padded_index(nx, e.second));
+            ptr.push_back((int)child.size());
+        }
         D.ex_nt = (int)tgt.size();
         D.ex_ptr = h->upload(ptr);
         D.ex_target = h->upload(tgt);
         D.ex_child = h->upload(child);
+        D.rmask = h->upload(rmask);
         D.pex_n = (int)pf.size();
         D.pex_fine = h->upload(pf);
         D.pex_coarse = h->upload(pc);
@@ -381,41 +423,52 @@ struct Prec<float> {
     static PlgDev<float> &P(DevLevel &D) { return D.P32; }
 };
 
+// one block-smoother sweep on level l (the iterate ping-pongs between the
+// level's two buffers); uzero: the current iterate is known to be zero
 template <typename T>
-void smooth(mg_handle h, int l, hipStream_t st) {
+void smooth(mg_handle h, int l, bool uzero, hipStream_t st) {
     DevLevel &D = h->dev[l];
     T *uo = Prec<T>::u(D, D.cur), *un = Prec<T>::u(D, 1 - D.cur);
     const bool rec = h->timing && l == 0 && 2 * h->nrec + 1 < (int)h->ev.size();
     if (rec) HIPCHECK(hipEventRecord(h->ev[2 * h->nrec], st));
-    launch_jacobi<T>(D.args, uo, Prec<T>::b(D), un, D.mask, st);
+    launch_smooth_a<T>(D.args, uo, Prec<T>::b(D), un, D.mask, uzero, Prec<T>::P(D), st);
     if (rec) {
         HIPCHECK(hipEventRecord(h->ev[2 * h->nrec + 1], st));
         ++h->nrec;
     }
-    launch_plg_solve<T>(Prec<T>::P(D), Prec<T>::b(D), un, st);
+    launch_smooth_b<T>(Prec<T>::P(D), un, st);
     D.cur = 1 - D.cur;
 }
 
+// Algorithm 3 on level l; uzero: the iterate on entry is zero (the coarse
+// levels, and the FP32 cycle of the mixed-precision iteration)
 template <typename T>
-void vcycle(mg_handle h, int l, hipStream_t st) {
+void vcycle(mg_handle h, int l, bool uzero, hipStream_t st) {
     DevLevel &D = h->dev[l];
     const int last = (int)h->dev.size() - 1;
     if (l == last) {
         launch_bottom<T, T>(D.nbot, D.bot_cells, D.ainv, Prec<T>::b(D), Prec<T>::u(D, D.cur), st);
         return;
     }
-    for (int k = 0; k < h->opt.nu1; ++k) smooth<T>(h, l, st);
+    const int nu1 = h->opt.nu1;
+    if (nu1 == 0 && uzero) launch_fill_zero<T>(D.ncells, Prec<T>::u(D, D.cur), st);
+    for (int k = 0; k < nu1; ++k) smooth<T>(h, l, uzero && k == 0, st);
     DevLevel &C = h->dev[l + 1];
     T *u = Prec<T>::u(D, D.cur);
-    launch_plg_residual<T>(D.m, D.plg_cell, D.full_ptr, D.full_col, Prec<T>::fval(D), Prec<T>::b(D), u,
-                           Prec<T>::rplg(D), st);
-    launch_restrict<T>(D.args, C.args, u, Prec<T>::b(D), D.mask, D.plgidx, Prec<T>::rplg(D), C.mask, Prec<T>::b(C),
-                       Prec<T>::u(C, 0), D.ex_nt, D.ex_ptr, D.ex_target, D.ex_child, st);
+    // after a block-smoother sweep the PLG residuals are zero; without
+    // pre-smoothing they are computed
+    T *rplg = nullptr;
+    if (nu1 == 0) {
+        rplg = Prec<T>::rplg(D);
+        launch_plg_residual<T>(D.m, D.plg_cell, D.full_ptr, D.full_col, Prec<T>::fval(D), Prec<T>::b(D), u, rplg, st);
+    }
     C.cur = 0;
-    vcycle<T>(h, l + 1, st);
+    launch_restrict<T>(D.args, C.args, u, Prec<T>::b(D), D.mask, D.plgidx, rplg, D.rmask, Prec<T>::b(C),
+                       nu1 == 0 ? Prec<T>::u(C, 0) : nullptr, D.ex_nt, D.ex_ptr, D.ex_target, D.ex_child, st);
+    vcycle<T>(h, l + 1, true, st);
     launch_prolong<T>(D.args, C.args, D.mask, C.mask, Prec<T>::u(C, C.cur), Prec<T>::u(D, D.cur), D.pex_n, D.pex_fine,
                       D.pex_coarse, st);
-    for (int k = 0; k < h->opt.nu2; ++k) smooth<T>(h, l, st);
+    for (int k = 0; k < h->opt.nu2; ++k) smooth<T>(h, l, false, st);
 }
 
 double device_absmax_finish(mg_handle h, int nblocks, hipStream_t st) {
@@ -425,55 +478,59 @@ double device_absmax_finish(mg_handle h, int nblocks, hipStream_t st) {
     return *h->host_scalar;
 }
 
-double residual_norm(mg_handle h, int l, const double *u, const double *b, float *r32, double *r64, hipStream_t st) {
+double residual_norm(mg_handle h, int l, const double *u, const double *b, double *r64, hipStream_t st) {
     DevLevel &D = h->dev[l];
-    launch_plg_residual<double>(D.m, D.plg_cell, D.full_ptr, D.full_col, D.full_val64, b, u, D.rplg64, st);
-    int nb = launch_residual_norm(D.args, u, b, D.mask, D.plgidx, D.rplg64, r32, r64, h->partial, st);
+    int nb = launch_residual_norm(D.args, u, nullptr, nullptr, b, D.mask, D.m, D.plg_cell, D.fe_col, D.fe_val,
+                                  nullptr, r64, h->partial, st);
     return device_absmax_finish(h, nb, st);
 }
 
-// ||b - A u||_inf of the finest level into *h->host_scalar (no synchronisation)
-void enqueue_residual(mg_handle h, bool mixed, hipStream_t st) {
+// ||b - A u||_inf of the finest level into *h->host_scalar (no
+// synchronisation); u is u64[src] (+ e, written to u64[1 - src], when e is
+// given); mixed: the residual also goes to b32 in FP32
+void enqueue_residual(mg_handle h, bool mixed, int src, const float *e, hipStream_t st) {
     DevLevel &D = h->dev[0];
-    launch_plg_residual<double>(D.m, D.plg_cell, D.full_ptr, D.full_col, D.full_val64, D.b64, D.u64[0], D.rplg64, st);
-    int nb = launch_residual_norm(D.args, D.u64[0], D.b64, D.mask, D.plgidx, D.rplg64, mixed ? D.b32 : nullptr,
-                                  nullptr, h->partial, st);
+    int nb = launch_residual_norm(D.args, D.u64[src], e, e ? D.u64[1 - src] : nullptr, D.b64, D.mask, D.m,
+                                  D.plg_cell, D.fe_col, D.fe_val, mixed ? D.b32 : nullptr, nullptr, h->partial, st);
     launch_absmax(nb, h->partial, nullptr, h->partial + h->npartial - 1, 1, st);
     HIPCHECK(hipMemcpyAsync(h->host_scalar, h->partial + h->npartial - 1, sizeof(double), hipMemcpyDeviceToHost, st));
 }
 
 // one outer iteration on the handle's own buffers: a V-cycle (FP64), or an
-// FP32 V-cycle on the FP32 residual added in FP64 (mixed); then the residual
-void enqueue_iteration(mg_handle h, bool mixed, hipStream_t st) {
+// FP32 V-cycle from zero on the FP32 residual whose result corrects the FP64
+// iterate u64[par] into u64[1 - par] (mixed); then the residual
+void enqueue_iteration(mg_handle h, bool mixed, int par, hipStream_t st) {
     DevLevel &D = h->dev[0];
-    if (mixed) {
-        launch_fill_zero(D.ncells, D.u32[0], st);
-        D.cur = 0;
-        vcycle<float>(h, 0, st);
-        launch_add_correction(D.ncells, D.mask, D.u32[D.cur], D.u64[0], st);
-    } else {
-        D.cur = 0;
-        vcycle<double>(h, 0, st);
-        if (D.cur != 0) HIPCHECK(hipMemcpyAsync(D.u64[0], D.u64[1], D.ncells * 8, hipMemcpyDeviceToDevice, st));
-    }
     D.cur = 0;
-    enqueue_residual(h, mixed, st);
+    if (mixed) {
+        vcycle<float>(h, 0, true, st);
+        const float *e = D.u32[D.cur];
+        D.cur = 0;
+        enqueue_residual(h, true, par, e, st);
+    } else {
+        vcycle<double>(h, 0, false, st);
+        if (D.cur != 0) HIPCHECK(hipMemcpyAsync(D.u64[0], D.u64[1], D.ncells * 8, hipMemcpyDeviceToDevice, st));
+        D.cur = 0;
+        enqueue_residual(h, false, 0, nullptr, st);
+    }
 }
 
 void run_iteration(mg_handle h, bool mixed, hipStream_t st) {
-    const int p = mixed ? 1 : 0;
+    const int par = mixed ? h->upar : 0;
+    const int p = mixed ? 1 + par : 0;
     if (h->timing) {                     // eager launches (events around the sweeps)
-        enqueue_iteration(h, mixed, st);
-        return;
+        enqueue_iteration(h, mixed, par, st);
+    } else {
+        if (!h->iter_exec[p]) {
+            if (!h->cap_stream) HIPCHECK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+            HIPCHECK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+            enqueue_iteration(h, mixed, par, h->cap_stream);
+            HIPCHECK(hipStreamEndCapture(h->cap_stream, &h->iter_graph[p]));
+            HIPCHECK(hipGraphInstantiate(&h->iter_exec[p], h->iter_graph[p], nullptr, nullptr, 0));
+        }
+        HIPCHECK(hipGraphLaunch(h->iter_exec[p], st));
     }
-    if (!h->iter_exec[p]) {
-        if (!h->cap_stream) HIPCHECK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
-        HIPCHECK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-        enqueue_iteration(h, mixed, h->cap_stream);
-        HIPCHECK(hipStreamEndCapture(h->cap_stream, &h->iter_graph[p]));
-        HIPCHECK(hipGraphInstantiate(&h->iter_exec[p], h->iter_graph[p], nullptr, nullptr, 0));
-    }
-    HIPCHECK(hipGraphLaunch(h->iter_exec[p], st));
+    if (mixed) h->upar = 1 - h->upar;
 }
 
 thread_local std::string g_last_error;
@@ -602,9 +659,10 @@ mg_status mg_setup(const mg_grid *grid, int n_curves, const mg_curve *curves, do
         h->dev.resize(nl);
         for (int l = 0; l < nl; ++l) upload_level(h.get(), l, l == nl - 1, st);
         upload_rhs(h.get());
-        int maxtiles = 1;
-        for (auto &D : h->dev) maxtiles = std::max(maxtiles, ((D.args.nx + 63) / 64) * ((D.args.ny + 15) / 16));
-        h->npartial = std::max(maxtiles, 1024) + 1;
+        int maxblk = 1;
+        for (auto &D : h->dev)
+            maxblk = std::max(maxblk, ((D.args.nx + 63) / 64) * ((D.args.ny + 31) / 32) + (D.m + 255) / 256);
+        h->npartial = std::max(maxblk, 1024) + 1;
         h->partial = h->alloc<double>(h->npartial);
         HIPCHECK(hipHostMalloc((void **)&h->host_scalar, sizeof(double)));
         HIPCHECK(hipDeviceSynchronize());
@@ -637,7 +695,7 @@ mg_status mg_vcycle(mg_handle h, const double *b_dev, double *u_dev, void *strea
         D.u64[0] = u_dev;
         D.b64 = const_cast<double *>(b_dev);
         D.cur = 0;
-        vcycle<double>(h, 0, st);
+        vcycle<double>(h, 0, false, st);
         if (D.cur != 0) HIPCHECK(hipMemcpyAsync(u_dev, D.u64[1], D.ncells * 8, hipMemcpyDeviceToDevice, st));
         D.u64[0] = keep_u;
         D.b64 = keep_b;
@@ -651,8 +709,8 @@ mg_status mg_smooth(mg_handle h, int level, const double *b_dev, double *u_dev, 
     return guard(h, [&]() {
         hipStream_t st = (hipStream_t)stream;
         DevLevel &D = h->dev[level];
-        launch_jacobi<double>(D.args, u_dev, b_dev, D.u64[1], D.mask, st);
-        launch_plg_solve<double>(D.P64, b_dev, D.u64[1], st);
+        launch_smooth_a<double>(D.args, u_dev, b_dev, D.u64[1], D.mask, false, D.P64, st);
+        launch_smooth_b<double>(D.P64, D.u64[1], st);
         HIPCHECK(hipMemcpyAsync(u_dev, D.u64[1], D.ncells * 8, hipMemcpyDeviceToDevice, st));
         HIPCHECK(hipGetLastError());
     });
@@ -662,7 +720,7 @@ mg_status mg_residual(mg_handle h, int level, const double *b_dev, const double 
                       void *stream) {
     if (!h || !b_dev || !u_dev || level < 0 || level >= (int)h->dev.size()) return MG_ERR_INVALID_ARG;
     return guard(h, [&]() {
-        double v = residual_norm(h, level, u_dev, b_dev, nullptr, r_dev, (hipStream_t)stream);
+        double v = residual_norm(h, level, u_dev, b_dev, r_dev, (hipStream_t)stream);
         if (rnorm) *rnorm = v;
     });
 }
@@ -683,7 +741,8 @@ mg_status mg_solve(mg_handle h, const double *f_dev, const double *g_dev, double
         // iterate on the handle's own finest-level buffer (fixed addresses,
         // so the captured iteration can be replayed)
         HIPCHECK(hipMemcpyAsync(D.u64[0], u_dev, D.ncells * 8, hipMemcpyDeviceToDevice, st));
-        enqueue_residual(h, mixed, st);
+        h->upar = 0;
+        enqueue_residual(h, mixed, 0, nullptr, st);
         HIPCHECK(hipStreamSynchronize(st));
         int it = 0, grow = 0;
         double rel = *h->host_scalar / bnorm;
@@ -698,7 +757,7 @@ mg_status mg_solve(mg_handle h, const double *f_dev, const double *g_dev, double
             if (grow >= 3) { result = MG_ERR_DIVERGED; break; }
             prev = rel;
         }
-        HIPCHECK(hipMemcpyAsync(u_dev, D.u64[0], D.ncells * 8, hipMemcpyDeviceToDevice, st));
+        HIPCHECK(hipMemcpyAsync(u_dev, D.u64[mixed ? h->upar : 0], D.ncells * 8, hipMemcpyDeviceToDevice, st));
         launch_zero_inactive(D.ncells, D.mask, u_dev, st);
         HIPCHECK(hipStreamSynchronize(st));
         if (result == MG_OK && rel > tol) result = MG_ERR_NO_CONVERGENCE;
@@ -719,6 +778,7 @@ mg_status mg_query(mg_handle h, mg_info *info) {
         info->n_active[l] = L.n_active;
         info->n_plg[l] = (int)L.plg_cells.size();
         info->n_sep[l] = h->solvers[l].nsep;
+        info->sweep_words[l] = h->dev[l].sweep_words;
         info->nnz_plg += (long long)L.col.size();
     }
     info->n_face = h->levels[0]->n_face;
@@ -917,7 +977,7 @@ mg_status mg_kernel_timing(mg_handle h, int enable, int *launches, double *avg_m
 mg_status mg_destroy(mg_handle h) {
     if (!h) return MG_OK;
     for (auto &e : h->ev) (void)hipEventDestroy(e);
-    for (int p = 0; p < 2; ++p) {
+    for (int p = 0; p < 3; ++p) {
         if (h->iter_exec[p]) (void)hipGraphExecDestroy(h->iter_exec[p]);
         if (h->iter_graph[p]) (void)hipGraphDestroy(h->iter_graph[p]);
     }

@@ -3,6 +3,15 @@
 // Cell arrays are row-major with a halo of 2: cell (i, j) at
 // (j + 2) * pitch + (i + 2), pitch = nx + 4.  The halo is never read as data:
 // ghost values are synthesised from interior cells (Section 4.1).
+//
+// One block smoothing sweep (Definition 5.6) is two launches:
+//   A: omega-Jacobi on the SFV cells (eq. (5.5)) in 64 x 32 tiles, and in the
+//      same launch, per group of PLG rows, t = b2 - A21 u1 (eq. (5.6)) from
+//      Jacobi-updated values of the SFV cells those rows couple to
+//      (recomputed from the old iterate, so that the launch needs no grid-wide
+//      ordering), followed by the segment solves y = B^{-1} t;
+//   B: the separator Schur-complement solve and the segment corrections
+//      (only on levels with separators).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -22,25 +31,40 @@ __device__ __forceinline__ size_t pidx(const LevelArgs &L, int i, int j) {
     return (size_t)(j + 2) * L.pitch + (size_t)(i + 2);
 }
 
-// Ghost value at (qi, qj) outside the box, from the interior cells of the
-// current iterate (homogeneous part; face data live in the right-hand side).
-template <typename T>
-__device__ T ghost_value(const T *__restrict__ u, const LevelArgs &L, int qi, int qj) {
+// boundary condition of a box side without indexing the argument struct at
+// run time (that would place it in scratch memory)
+__device__ __forceinline__ int side_bc(const LevelArgs &L, int side) {
+    return side == 0 ? L.bc[0] : side == 1 ? L.bc[1] : side == 2 ? L.bc[2] : L.bc[3];
+}
+
+// ghost weights from the constant table
+struct GhostW {
+    const LevelArgs &L;
+    __device__ double operator()(int side, int depth, int k) const { return c_gw[side_bc(L, side)][depth - 1][k]; }
+};
+
+// ghost weights staged in LDS: w[side][depth - 1][k]
+struct GhostWLds {
+    const double *w;
+    __device__ double operator()(int side, int depth, int k) const { return w[(side * 2 + depth - 1) * 4 + k]; }
+};
+
+// Ghost value at (qi, qj) outside the box (homogeneous part; face data live
+// in the right-hand side), from in-box values at(i, j) and ghost weights
+// W(side, depth, k).  Corner positions apply the x and y face formulas in
+// turn.
+template <typename T, typename At, typename Wt>
+__device__ T ghost_at(const At &at, const Wt &W, const LevelArgs &L, int qi, int qj) {
     const bool ox = qi < 0 || qi >= L.nx, oy = qj < 0 || qj >= L.ny;
     if (ox && oy) {
         const int xside = qi < 0 ? 3 : 1, yside = qj < 0 ? 0 : 2;
         const int m = qi < 0 ? -qi : qi - L.nx + 1, k = qj < 0 ? -qj : qj - L.ny + 1;
-        const double *gx = c_gw[L.bc[xside]][m - 1];
-        const double *gy = c_gw[L.bc[yside]][k - 1];
         double s = 0.0;
         for (int p = 0; p < 4; ++p) {
             const int col = xside == 3 ? p : L.nx - 1 - p;
             double t = 0.0;
-            for (int q = 0; q < 4; ++q) {
-                const int row = yside == 0 ? q : L.ny - 1 - q;
-                t += gy[q] * (double)u[pidx(L, col, row)];
-            }
-            s += gx[p] * t;
+            for (int q = 0; q < 4; ++q) t += W(yside, k, q) * (double)at(col, yside == 0 ? q : L.ny - 1 - q);
+            s += W(xside, m, p) * t;
         }
         return (T)s;
     }
@@ -49,23 +73,24 @@ __device__ T ghost_value(const T *__restrict__ u, const LevelArgs &L, int qi, in
     else if (qj >= L.ny) { side = 2; depth = qj - L.ny + 1; }
     else if (qi < 0) { side = 3; depth = -qi; }
     else { side = 1; depth = qi - L.nx + 1; }
-    const double *w = c_gw[L.bc[side]][depth - 1];
     double s = 0.0;
     for (int k = 0; k < 4; ++k) {
-        int ci, cj;
-        if (side == 0) { ci = qi; cj = k; }
-        else if (side == 2) { ci = qi; cj = L.ny - 1 - k; }
-        else if (side == 3) { ci = k; cj = qj; }
-        else { ci = L.nx - 1 - k; cj = qj; }
-        s += w[k] * (double)u[pidx(L, ci, cj)];
+        double v;
+        if (side == 0) v = (double)at(qi, k);
+        else if (side == 2) v = (double)at(qi, L.ny - 1 - k);
+        else if (side == 3) v = (double)at(k, qj);
+        else v = (double)at(L.nx - 1 - k, qj);
+        s += W(side, depth, k) * v;
     }
     return (T)s;
 }
 
+// value at (i, j), in the box or a ghost, read from global memory
 template <typename T>
 __device__ __forceinline__ T fetch(const T *__restrict__ u, const LevelArgs &L, int i, int j) {
-    if (i >= 0 && i < L.nx && j >= 0 && j < L.ny) return u[pidx(L, i, j)];
-    return ghost_value(u, L, i, j);
+    auto at = [&](int a, int c) { return u[pidx(L, a, c)]; };
+    if (i >= 0 && i < L.nx && j >= 0 && j < L.ny) return at(i, j);
+    return ghost_at<T>(at, GhostW{L}, L, i, j);
 }
 
 // (A u) at an SFV cell from a 2D accessor (eq. (4.7) and the mixed term)
@@ -88,53 +113,34 @@ __device__ __forceinline__ T apply_sfv(const LevelArgs &L, F at) {
     return s;
 }
 
-constexpr int TX = 64, TY = 32, HX = TX + 4, HY = TY + 4, NT = 256;
-
-// Ghost value at (qi, qj) outside the box from a tile held in LDS; the tile
-// origin (i0 - 2, j0 - 2) must contain the 4 interior cells next to the box
-// edge in each direction the position lies beyond.
-template <typename T>
-__device__ __forceinline__ T ghost_lds(const T (*s)[HX], const LevelArgs &L, int i0, int j0, int qi, int qj) {
-    auto at = [&](int i, int j) { return (double)s[j - j0 + 2][i - i0 + 2]; };
-    const bool ox = qi < 0 || qi >= L.nx, oy = qj < 0 || qj >= L.ny;
-    if (ox && oy) {
-        const int xside = qi < 0 ? 3 : 1, yside = qj < 0 ? 0 : 2;
-        const int m = qi < 0 ? -qi : qi - L.nx + 1, k = qj < 0 ? -qj : qj - L.ny + 1;
-        const double *gx = c_gw[L.bc[xside]][m - 1];
-        const double *gy = c_gw[L.bc[yside]][k - 1];
-        double sum = 0.0;
-        for (int p = 0; p < 4; ++p) {
-            const int col = xside == 3 ? p : L.nx - 1 - p;
-            double t = 0.0;
-            for (int q = 0; q < 4; ++q) t += gy[q] * at(col, yside == 0 ? q : L.ny - 1 - q);
-            sum += gx[p] * t;
-        }
-        return (T)sum;
+// (A u) at the SFV cell (i, j) from global memory: direct loads when its
+// 5 x 5 box lies in the grid (all loads issue together), else through fetch
+template <typename T, bool MIXED>
+__device__ __forceinline__ T sfv_global(const LevelArgs &L, const T *__restrict__ u, int i, int j) {
+    if (i >= 2 && i < L.nx - 2 && j >= 2 && j < L.ny - 2) {
+        const T *p = u + pidx(L, i, j);
+        const int pt = L.pitch;
+        return apply_sfv<T, MIXED>(L, [&](int dx, int dy) { return p[dy * pt + dx]; });
     }
-    int side, depth;
-    if (qj < 0) { side = 0; depth = -qj; }
-    else if (qj >= L.ny) { side = 2; depth = qj - L.ny + 1; }
-    else if (qi < 0) { side = 3; depth = -qi; }
-    else { side = 1; depth = qi - L.nx + 1; }
-    const double *w = c_gw[L.bc[side]][depth - 1];
-    double sum = 0.0;
-    for (int k = 0; k < 4; ++k) {
-        if (side == 0) sum += w[k] * at(qi, k);
-        else if (side == 2) sum += w[k] * at(qi, L.ny - 1 - k);
-        else if (side == 3) sum += w[k] * at(k, qj);
-        else sum += w[k] * at(L.nx - 1 - k, qj);
-    }
-    return (T)sum;
+    return apply_sfv<T, MIXED>(L, [&](int dx, int dy) { return fetch(u, L, i + dx, j + dy); });
 }
 
-// Loads the (TY+4) x (TX+4) tile with halo into LDS; halo positions outside
-// the box are ghost values.  A block at the box edge first loads the interior
-// cells, then fills the ghosts from LDS when the 4 cells inward from each
-// edge it touches lie in the tile (always so when nx, ny are multiples of 4
-// and at least 4 cells remain in the last tile), else from global memory.
-template <typename T>
-__device__ __forceinline__ void load_tile(T (*s)[HX], const T *__restrict__ u, const LevelArgs &L, int i0, int j0) {
+constexpr int TX = 64, TY = 32, HX = TX + 4, HY = TY + 4, NT = 256;
+
+// Loads the (TY+4) x (TX+4) tile with halo into LDS from in-box values
+// at(i, j); halo positions outside the box get ghost values.  A block at the
+// box edge first loads the interior cells and the ghost weights, then
+// computes the ghosts of its part of the 2-cell band around the box from
+// LDS when the 4 cells inward from each edge it touches lie in the tile
+// (always so when at least 2 cells of the box remain in the last tile), else
+// from the accessor.  gws: 32 doubles of LDS for the weights.
+template <typename T, typename At>
+__device__ __forceinline__ void load_tile(T (*s)[HX], double *gws, const At &at, const LevelArgs &L, int i0, int j0) {
     const bool edge = i0 < 2 || j0 < 2 || i0 + TX + 2 > L.nx || j0 + TY + 2 > L.ny;
+    if (edge && threadIdx.x < 32) {
+        const int side = threadIdx.x >> 3, d = (threadIdx.x >> 2) & 1, k = threadIdx.x & 3;
+        gws[threadIdx.x] = c_gw[side_bc(L, side)][d][k];
+    }
     // all global loads of a thread are issued before any LDS store
     constexpr int NL = (HX * HY + NT - 1) / NT;
     T v[NL];
@@ -143,7 +149,7 @@ __device__ __forceinline__ void load_tile(T (*s)[HX], const T *__restrict__ u, c
         const int t = threadIdx.x + k * NT;
         const int ly = t / HX, lx = t - ly * HX;
         const int qi = i0 - 2 + lx, qj = j0 - 2 + ly;
-        v[k] = (t < HX * HY && qi >= 0 && qi < L.nx && qj >= 0 && qj < L.ny) ? u[pidx(L, qi, qj)] : (T)0;
+        v[k] = (t < HX * HY && qi >= 0 && qi < L.nx && qj >= 0 && qj < L.ny) ? at(qi, qj) : (T)0;
     }
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
@@ -151,32 +157,120 @@ __device__ __forceinline__ void load_tile(T (*s)[HX], const T *__restrict__ u, c
         if (t < HX * HY) s[t / HX][t % HX] = v[k];
     }
     if (!edge) return;
-    // the tile holds cells [i0 - 2, i0 + TX + 2) x [j0 - 2, j0 + TY + 2);
-    // the left and bottom edges (i0 = 0, j0 = 0) always have their 4 inward
-    // cells in it, the right and top edges when nx - 4 >= i0 - 2 (ny - 4 >= j0 - 2)
+    // the tile holds cells [i0 - 2, i0 + TX + 2) x [j0 - 2, j0 + TY + 2)
     const bool lds_ok = (i0 + TX + 2 <= L.nx || L.nx - 4 >= i0 - 2) && (j0 + TY + 2 <= L.ny || L.ny - 4 >= j0 - 2);
+    auto lat = [&](int i, int j) { return s[j - j0 + 2][i - i0 + 2]; };
+    const GhostWLds W{gws};
     __syncthreads();
-    for (int t = threadIdx.x; t < HX * HY; t += NT) {
-        const int ly = t / HX, lx = t - ly * HX;
-        const int qi = i0 - 2 + lx, qj = j0 - 2 + ly;
-        const bool inside = qi >= 0 && qi < L.nx && qj >= 0 && qj < L.ny;
-        if (!inside && qi >= -2 && qi < L.nx + 2 && qj >= -2 && qj < L.ny + 2)
-            s[ly][lx] = lds_ok ? ghost_lds<T>(s, L, i0, j0, qi, qj) : ghost_value(u, L, qi, qj);
+    // the ghost band: columns -2, -1, nx, nx+1 over rows -2 .. ny+1, then
+    // rows -2, -1, ny, ny+1 over columns 0 .. nx-1; positions outside the
+    // tile are skipped
+    constexpr int NV = 2 * (HY), NH = 2 * (HX);
+    for (int t = threadIdx.x; t < 2 * NV + 2 * NH; t += NT) {
+        int qi, qj;
+        bool ok;
+        if (t < 2 * NV) {
+            const int band = t / NV, r = t - band * NV;          // band 0 left, 1 right
+            const int c = r / HY;
+            qi = band == 0 ? -2 + c : L.nx + c;
+            qj = j0 - 2 + (r - c * HY);
+            ok = qj >= -2 && qj < L.ny + 2;
+        } else {
+            const int t2 = t - 2 * NV;
+            const int band = t2 / NH, r = t2 - band * NH;        // band 0 bottom, 1 top
+            const int c = r / HX;
+            qj = band == 0 ? -2 + c : L.ny + c;
+            qi = i0 - 2 + (r - c * HX);
+            ok = qi >= 0 && qi < L.nx;
+        }
+        const int lx = qi - i0 + 2, ly = qj - j0 + 2;
+        if (ok && lx >= 0 && lx < HX && ly >= 0 && ly < HY)
+            s[ly][lx] = lds_ok ? ghost_at<T>(lat, W, L, qi, qj) : ghost_at<T>(at, W, L, qi, qj);
     }
 }
 
+// 16-byte vector of T
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+    using V = float4;
+    static constexpr int N = 4;
+    __device__ static float at(const V &v, int k) { return k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : v.w; }
+};
+template <>
+struct Vec16<double> {
+    using V = double2;
+    static constexpr int N = 2;
+    __device__ static double at(const V &v, int k) { return k == 0 ? v.x : v.y; }
+};
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Rows [0, nr) (nr <= 8) of a row-major block A with row stride lda (a
+// multiple of 4) times x (LDS, zero beyond the last column up to lda), one
+// wavefront: each lane loads 16 bytes of every row per step, U steps per
+// pass so that a row of up to 64 * U * (16 / sizeof(T)) columns is read by
+// loads issued together.  Lane 0 receives the 8 results.
+template <typename T, int U>
+__device__ __forceinline__ void wave_rows8(const T *__restrict__ A, int lda, int nr, const T *x, int lane, T out[8]) {
+    using VT = Vec16<T>;
+    using V = typename VT::V;
+    constexpr int VN = VT::N;
+    T acc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = 0;
+    for (int base = lane * VN; base < lda; base += 64 * VN * U) {
+        V a[U][8];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int c = base + u * 64 * VN;
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (k < nr && c < lda) a[u][k] = *reinterpret_cast<const V *>(A + (size_t)k * lda + c);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int c = base + u * 64 * VN;
+            if (c < lda) {
+                T xv[VN];
+#pragma unroll
+                for (int v = 0; v < VN; ++v) xv[v] = x[c + v];
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    if (k < nr)
+#pragma unroll
+                        for (int v = 0; v < VN; ++v) acc[k] += VT::at(a[u][k], v) * xv[v];
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) out[k] = wave_sum(acc[k]);
+}
+
+// steps per pass of wave_rows8: rows of up to PLG_LMAX columns in one pass
+template <typename T>
+constexpr int rows_unroll() {
+    return (PLG_LMAX + 64 * Vec16<T>::N - 1) / (64 * Vec16<T>::N);
+}
+
 // ---------------------------------------------------------------------------
-// K1: weighted Jacobi on the SFV cells, eq. (5.5), D = -5(a+c)/(2h^2).
+// Launch A, tile role: weighted Jacobi on the SFV cells, eq. (5.5),
+// D = -5(a+c)/(2h^2).  uzero: the old iterate is zero (first sweep of a
+// residual equation), so it is not read.
 template <typename T, bool MIXED>
-__global__ __launch_bounds__(NT) void k_jacobi(LevelArgs L, const T *__restrict__ uold, const T *__restrict__ b,
-                                               T *__restrict__ unew, const uint8_t *__restrict__ mask) {
-    __shared__ T s[HY][HX];
+__device__ __forceinline__ void jacobi_tile(const LevelArgs &L, const T *__restrict__ uold, const T *__restrict__ b,
+                                            T *__restrict__ unew, const uint8_t *__restrict__ mask, bool uzero,
+                                            int i0, int j0, T (*s)[HX], double *gws) {
     constexpr int R = TY / (NT / TX);            // rows per thread
-    const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     const int i = i0 + tx;
-    // issue the per-cell loads before the tile barrier so that their latency
-    // overlaps the tile load
+    // the per-cell loads are issued before the tile barrier so that their
+    // latency overlaps the tile load
     uint8_t mk[R];
     T bv[R];
 #pragma unroll
@@ -187,9 +281,15 @@ __global__ __launch_bounds__(NT) void k_jacobi(LevelArgs L, const T *__restrict_
         mk[k] = in ? mask[id] : 0;
         bv[k] = b[id];
     }
-    load_tile<T>(s, uold, L, i0, j0);
-    __syncthreads();
     const T wod = (T)L.omega_over_d;
+    if (uzero) {
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if (mk[k] == 1) unew[pidx(L, i, j0 + ty + k * (NT / TX))] = wod * bv[k];
+        return;
+    }
+    load_tile<T>(s, gws, [&](int a, int c) { return uold[pidx(L, a, c)]; }, L, i0, j0);
+    __syncthreads();
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         if (mk[k] != 1) continue;
@@ -200,124 +300,164 @@ __global__ __launch_bounds__(NT) void k_jacobi(LevelArgs L, const T *__restrict_
     }
 }
 
-// ---------------------------------------------------------------------------
-// PLG rows: t = b2 - A21 u1 (eq. (5.6)), then u2 = A22^{-1} t via the
-// segment / separator decomposition.
-// Dense row-major blocks are applied one wavefront per row: the 64 lanes
-// read consecutive columns (coalesced) and the partial sums are reduced
-// across the wavefront.
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    return v;
-}
-
-constexpr int PLG_ROWS = 32;     // rows per block in the PLG kernels (8 per wavefront)
-
-// t = b2 - A21 u1 for all PLG rows (solve order): 32 lanes per row gather the
-// row's SFV couplings in parallel.
-template <typename T>
-__global__ __launch_bounds__(256) void k_plg_gather(PlgDev<T> P, const T *__restrict__ b, const T *__restrict__ u,
-                                                    T *__restrict__ t) {
-    const int q = blockIdx.x * 8 + (threadIdx.x >> 5);
-    const int lane = threadIdx.x & 31;
-    if (q >= P.m) return;
-    const int e0 = P.a21_ptr[q], e1 = P.a21_ptr[q + 1];
-    T v = 0;
-    for (int e = e0 + lane; e < e1; e += 32) v += P.a21_val[e] * u[P.a21_col[e]];
-    for (int off = 16; off > 0; off >>= 1) v += __shfl_down(v, off, 32);
-    if (lane == 0) t[q] = b[P.cell[q]] - v;
-}
-
-// P1: block (j, rb): rows [rb * PLG_ROWS, ...) of y_j = B_j^{-1} t_j
-// (u2 = y_j if there are no separators)
-template <typename T>
-__global__ __launch_bounds__(256) void k_plg_seg(PlgDev<T> P, const T *__restrict__ tg, T *__restrict__ u) {
-    extern __shared__ unsigned char smem_raw[];
-    T *t = reinterpret_cast<T *>(smem_raw);
-    const int j = blockIdx.x;
-    const int s0 = P.seg_start[j], Lj = P.seg_start[j + 1] - s0;
-    const int r0 = blockIdx.y * PLG_ROWS;
-    if (r0 >= Lj) return;
-    for (int r = threadIdx.x; r < Lj; r += blockDim.x) t[r] = tg[s0 + r];
-    __syncthreads();
-    const T *inv = P.inv + P.inv_off[j];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int rw = r0 + wave * (PLG_ROWS / 4);
-    T acc[PLG_ROWS / 4];
+// Launch A, PLG role: one group of PLG rows (a segment slice, or a run of
+// separator rows).  Dense row-major blocks are applied one wavefront per
+// row, 8 rows at a time: the 64 lanes read consecutive columns and the
+// partial sums are reduced across the wavefront.
+template <typename T, bool MIXED>
+__device__ __forceinline__ void plg_group(const LevelArgs &L, const T *__restrict__ uold, const T *__restrict__ b,
+                                          T *__restrict__ unew, bool uzero, const PlgDev<T> &P, int bi, T *lds) {
+    const int4 bk = P.blk1[bi];
+    const int g = bk.x, r0 = bk.y, r1 = bk.z;
+    const int gs = P.grp_start[g], n = P.grp_start[g + 1] - gs;
+    const int h0 = P.hptr[g], nh = P.hptr[g + 1] - h0;
+    T *hv = lds, *tt = lds + PLG_HMAX, *yy = tt + PLG_LMAX;
+    const T wod = (T)L.omega_over_d;
+    // b2 of this thread's rows, loaded before the gather
+    constexpr int RPT = (PLG_LMAX + NT - 1) / NT;
+    T brow[RPT];
 #pragma unroll
-    for (int k = 0; k < PLG_ROWS / 4; ++k) acc[k] = 0;
-    for (int c = lane; c < Lj; c += 64) {
-        const T x = t[c];
-#pragma unroll
-        for (int k = 0; k < PLG_ROWS / 4; ++k)
-            if (rw + k < Lj) acc[k] += inv[(size_t)(rw + k) * Lj + c] * x;
+    for (int k = 0; k < RPT; ++k) {
+        const int q = threadIdx.x + k * NT;
+        brow[k] = q < n ? b[P.cell[gs + q]] : (T)0;
     }
+    // u1 after the Jacobi sweep on the SFV cells the group couples to
+    for (int k = threadIdx.x; k < nh; k += NT) {
+        const int id = P.hcell[h0 + k];
+        T v;
+        if (uzero) {
+            v = wod * b[id];
+        } else {
+            const int j = id / L.pitch - 2, i = id - (j + 2) * L.pitch - 2;
+            v = uold[id] + wod * (b[id] - sfv_global<T, MIXED>(L, uold, i, j));
+        }
+        hv[k] = v;
+    }
+    if (nh == 0 && threadIdx.x == 0) hv[0] = 0;   // target of the zero padding
+    __syncthreads();
+    // t = b2 - A21 u1
 #pragma unroll
-    for (int k = 0; k < PLG_ROWS / 4; ++k) {
-        const T a = wave_sum(acc[k]);
-        if (lane == 0 && rw + k < Lj) {
-            if (P.nsep == 0) u[P.cell[s0 + rw + k]] = a;
-            else P.y[s0 + rw + k] = a;
+    for (int k = 0; k < RPT; ++k) {
+        const int q = threadIdx.x + k * NT;
+        if (q < n) {
+            const size_t e0 = (size_t)(gs + q) * ELL_W;
+            T v = 0;
+#pragma unroll
+            for (int e = 0; e < ELL_W; ++e) v += P.a21_val[e0 + e] * hv[P.a21_loc[e0 + e]];
+            tt[q] = brow[k] - v;
         }
     }
+    const int npad = (n + 3) & ~3;
+    if (threadIdx.x < npad - n) tt[n + threadIdx.x] = 0;
+    __syncthreads();
+    if (g >= P.nseg) {                           // separator rows: right-hand side only
+        for (int q = threadIdx.x; q < n; q += NT) P.t[gs + q] = tt[q];
+        return;
+    }
+    // y = B^{-1} t on rows [r0, r1) (row stride npad)
+    const T *inv = P.inv + P.inv_off[g];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nr = r1 - r0, lr0 = r0 - gs;
+    for (int rb = wave * 8; rb < nr; rb += 32) {
+        T out[8];
+        wave_rows8<T, rows_unroll<T>()>(inv + (size_t)(lr0 + rb) * npad, npad, min(8, nr - rb), tt, lane, out);
+        if (lane == 0)
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (rb + k < nr) yy[rb + k] = out[k];
+    }
+    __syncthreads();
+    if (P.nsep == 0) {
+        for (int q = threadIdx.x; q < nr; q += NT) unew[P.cell[r0 + q]] = yy[q];
+        return;
+    }
+    for (int q = threadIdx.x; q < nr; q += NT) P.y[r0 + q] = yy[q];
+    // entries of A_SB y on these rows (summed per separator row in launch B)
+    for (int k = P.ce_ptr[g] + threadIdx.x; k < P.ce_ptr[g + 1]; k += NT) {
+        const int row = P.ce_row[k];
+        if (row >= r0 && row < r1) P.contrib[P.ce_slot[k]] = P.ce_val[k] * yy[row - r0];
+    }
 }
 
-// P2a: separator right-hand side r_S = t_S - A_SB y, 32 lanes per row
 template <typename T>
-__global__ __launch_bounds__(256) void k_plg_sep_rhs(PlgDev<T> P, const T *__restrict__ tg) {
-    const int s = blockIdx.x * 8 + (threadIdx.x >> 5);
-    const int lane = threadIdx.x & 31;
-    if (s >= P.nsep) return;
-    T v = 0;
-    for (int e = P.sb_ptr[s] + lane; e < P.sb_ptr[s + 1]; e += 32) v += P.sb_val[e] * P.y[P.sb_col[e]];
-    for (int off = 16; off > 0; off >>= 1) v += __shfl_down(v, off, 32);
-    if (lane == 0) P.rs[s] = tg[P.sep_begin + s] - v;
+constexpr size_t smooth_a_lds() {
+    return sizeof(T) * ((size_t)HY * HX > (size_t)(PLG_HMAX + 2 * PLG_LMAX) ? (size_t)HY * HX
+                                                                           : (size_t)(PLG_HMAX + 2 * PLG_LMAX));
 }
 
-// P2b: x_S = S'^{-1} r_S for the block's rows
+template <typename T, bool MIXED>
+__global__ __launch_bounds__(NT) void k_smooth_a(LevelArgs L, const T *__restrict__ uold, const T *__restrict__ b,
+                                                 T *__restrict__ unew, const uint8_t *__restrict__ mask, int tiles_x,
+                                                 int ntile, int uzero, PlgDev<T> P) {
+    __shared__ __align__(16) unsigned char smem[smooth_a_lds<T>()];
+    __shared__ double gws[32];
+    const int bid = blockIdx.x;
+    if (bid < ntile) {
+        jacobi_tile<T, MIXED>(L, uold, b, unew, mask, uzero != 0, (bid % tiles_x) * TX, (bid / tiles_x) * TY,
+                              reinterpret_cast<T(*)[HX]>(smem), gws);
+        return;
+    }
+    plg_group<T, MIXED>(L, uold, b, unew, uzero != 0, P, bid - ntile, reinterpret_cast<T *>(smem));
+}
+
+// Launch B: r_S = t_S - A_SB y (every block forms all of it in LDS), then
+// either x_S = S'^{-1} r_S on a run of separator rows, or, for a segment
+// slice, x_S on the segment's separator columns and x_B = y - F_j x_S.
 template <typename T>
-__global__ __launch_bounds__(256) void k_plg_sep(PlgDev<T> P, T *__restrict__ u) {
-    extern __shared__ unsigned char smem_raw[];
+__global__ __launch_bounds__(NT) void k_smooth_b(PlgDev<T> P, T *__restrict__ u) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int ns = P.nsep, nsp = (ns + 3) & ~3;          // dense rows have stride nsp
     T *rs = reinterpret_cast<T *>(smem_raw);
-    const int ns = P.nsep;
-    for (int s = threadIdx.x; s < ns; s += blockDim.x) rs[s] = P.rs[s];
+    T *xk = rs + nsp;
+    const int4 bk = P.blk2[blockIdx.x];
+    for (int s = threadIdx.x; s < nsp; s += NT) {
+        T v = 0;
+        if (s < ns) {
+            v = P.t[P.sep_begin + s];
+#pragma unroll
+            for (int k = 0; k < ELL_W; ++k) v -= P.contrib[(size_t)s * ELL_W + k];
+        }
+        rs[s] = v;
+    }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int r0 = blockIdx.x * PLG_ROWS + wave * (PLG_ROWS / 4);
-    T acc[PLG_ROWS / 4];
+    const bool seprows = bk.x == 1;
+    // dense rows times r_S: rows of S'^{-1} (separator block), or the rows
+    // of S'^{-1} at the segment's separator columns
+    const T *A = seprows ? P.sinv + (size_t)bk.z * nsp : P.SJ + P.sj_off[bk.y];
+    const int nr = seprows ? bk.w - bk.z : P.fcols_ptr[bk.y + 1] - P.fcols_ptr[bk.y];
+    for (int rb = wave * 8; rb < nr; rb += 32) {
+        T out[8];
+        wave_rows8<T, rows_unroll<T>()>(A + (size_t)rb * nsp, nsp, min(8, nr - rb), rs, lane, out);
+        if (lane == 0)
 #pragma unroll
-    for (int k = 0; k < PLG_ROWS / 4; ++k) acc[k] = 0;
-    for (int c = lane; c < ns; c += 64) {
-        const T x = rs[c];
-#pragma unroll
-        for (int k = 0; k < PLG_ROWS / 4; ++k)
-            if (r0 + k < ns) acc[k] += P.sinv[(size_t)(r0 + k) * ns + c] * x;
+            for (int k = 0; k < 8; ++k)
+                if (rb + k < nr) {
+                    if (seprows) u[P.cell[P.sep_begin + bk.z + rb + k]] = out[k];
+                    else xk[rb + k] = out[k];
+                }
     }
-#pragma unroll
-    for (int k = 0; k < PLG_ROWS / 4; ++k) {
-        const T a = wave_sum(acc[k]);
-        if (lane == 0 && r0 + k < ns) {
-            P.xs[r0 + k] = a;
-            u[P.cell[P.sep_begin + r0 + k]] = a;
-        }
-    }
-}
-
-// P3: x_j = y_j - F_j x_S (F_j row-major, L_j x k_j)
-template <typename T>
-__global__ __launch_bounds__(256) void k_plg_fix(PlgDev<T> P, T *__restrict__ u) {
-    const int j = blockIdx.x;
+    if (seprows) return;
+    __syncthreads();
+    const int j = bk.y, r0 = bk.z, r1 = bk.w, kj = nr;
     const int s0 = P.seg_start[j], Lj = P.seg_start[j + 1] - s0;
-    const int k0 = P.fcols_ptr[j], k = P.fcols_ptr[j + 1] - k0;
-    const T *F = P.F + P.f_off[j];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int r0 = blockIdx.y * PLG_ROWS;
-    for (int r = r0 + wave; r < min(r0 + PLG_ROWS, Lj); r += 4) {
-        T acc = 0;
-        for (int kk = lane; kk < k; kk += 64) acc += F[(size_t)r * k + kk] * P.xs[P.fcols[k0 + kk]];
-        acc = wave_sum(acc);
-        if (lane == 0) u[P.cell[s0 + r]] = P.y[s0 + r] - acc;
+    const T *FT = P.FT + P.ft_off[j];
+    constexpr int KU = 32;                               // columns of F_j unrolled
+    for (int r = r0 + threadIdx.x; r < r1; r += NT) {
+        const T *f = FT + (r - s0);
+        T fv[KU];
+#pragma unroll
+        for (int kk = 0; kk < KU; ++kk) fv[kk] = kk < kj ? f[(size_t)kk * Lj] : (T)0;
+        T v0 = 0, v1 = 0, v2 = 0, v3 = 0;
+#pragma unroll
+        for (int kk = 0; kk < KU; kk += 4) {
+            if (kk < kj) v0 += fv[kk] * xk[kk];
+            if (kk + 1 < kj) v1 += fv[kk + 1] * xk[kk + 1];
+            if (kk + 2 < kj) v2 += fv[kk + 2] * xk[kk + 2];
+            if (kk + 3 < kj) v3 += fv[kk + 3] * xk[kk + 3];
+        }
+        for (int kk = KU; kk < kj; ++kk) v0 += f[(size_t)kk * Lj] * xk[kk];
+        u[P.cell[r]] = P.y[r] - ((v0 + v1) + (v2 + v3));
     }
 }
 
@@ -334,26 +474,51 @@ __global__ void k_plg_residual(int m, const int *__restrict__ cell, const int *_
     r[q] = v;
 }
 
-// K2: residual of the fine level fused with the restriction of eq. (5.8):
-// one thread per coarse cell, children summed with weight 1/4; zero the
-// coarse initial guess.
+// Residual of the fine level fused with the restriction of eq. (5.8): one
+// thread per coarse cell, children summed with weight 1/4.  Fine PLG cells
+// contribute rplg, or 0 when rplg is null (after a block-smoother sweep the
+// PLG rows are solved exactly, Definition 5.6).  rmask (coarse level): 0
+// inactive (b = 0), 1 regular, 2 a cell that also absorbs fine cells of a
+// merged-away coarse cell, computed by the extra blocks after the tiles,
+// one thread per such cell over its list of children.  uc (optional) is the
+// coarse iterate, set to zero.
 template <typename T, bool MIXED>
-__global__ __launch_bounds__(NT) void k_restrict(LevelArgs L, LevelArgs C, const T *__restrict__ u,
-                                                 const T *__restrict__ b, const uint8_t *__restrict__ mask,
-                                                 const int *__restrict__ plgidx, const T *__restrict__ rplg,
-                                                 const uint8_t *__restrict__ cmask, T *__restrict__ bc,
-                                                 T *__restrict__ uc) {
+__global__ __launch_bounds__(NT) void k_restrict(LevelArgs L, LevelArgs C, int tiles_x, int ntile,
+                                                 const T *__restrict__ u, const T *__restrict__ b,
+                                                 const uint8_t *__restrict__ mask, const int *__restrict__ plgidx,
+                                                 const T *__restrict__ rplg, const uint8_t *__restrict__ rmask,
+                                                 T *__restrict__ bc, T *__restrict__ uc, int nt,
+                                                 const int *__restrict__ ex_ptr, const int *__restrict__ ex_target,
+                                                 const int *__restrict__ ex_child) {
     __shared__ T s[HY][HX];
-    const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+    __shared__ double gws[32];
+    if ((int)blockIdx.x >= ntile) {
+        const int t = (blockIdx.x - ntile) * NT + threadIdx.x;
+        if (t >= nt) return;
+        T sum = 0;
+        for (int e = ex_ptr[t]; e < ex_ptr[t + 1]; ++e) {
+            const int id = ex_child[e];
+            const int j = id / L.pitch - 2, i = id - (j + 2) * L.pitch - 2;
+            if (mask[id] == 1)
+                sum += b[id] - sfv_global<T, MIXED>(L, u, i, j);
+            else if (mask[id] == 2 && rplg)
+                sum += rplg[plgidx[id]];
+        }
+        bc[ex_target[t]] = (T)0.25 * sum;
+        if (uc) uc[ex_target[t]] = 0;
+        return;
+    }
+    const int bx = blockIdx.x % tiles_x, by = blockIdx.x / tiles_x;
+    const int i0 = bx * TX, j0 = by * TY;
     constexpr int NC = (TX / 2) * (TY / 2) / NT;      // coarse cells per thread
     uint8_t ck[NC], fk[NC][4];
     T fb[NC][4];
 #pragma unroll
     for (int n = 0; n < NC; ++n) {
         const int t = threadIdx.x + n * NT;
-        const int ci = blockIdx.x * (TX / 2) + t % (TX / 2), cj = blockIdx.y * (TY / 2) + t / (TX / 2);
+        const int ci = bx * (TX / 2) + t % (TX / 2), cj = by * (TY / 2) + t / (TX / 2);
         const bool cin = ci < C.nx && cj < C.ny;
-        ck[n] = cin ? cmask[pidx(C, ci, cj)] : 0;
+        ck[n] = cin ? rmask[pidx(C, ci, cj)] : 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int fi = 2 * ci + (q & 1), fj = 2 * cj + (q >> 1);
@@ -363,15 +528,15 @@ __global__ __launch_bounds__(NT) void k_restrict(LevelArgs L, LevelArgs C, const
             fb[n][q] = b[id];
         }
     }
-    load_tile<T>(s, u, L, i0, j0);
+    load_tile<T>(s, gws, [&](int a, int c) { return u[pidx(L, a, c)]; }, L, i0, j0);
     __syncthreads();
 #pragma unroll
     for (int n = 0; n < NC; ++n) {
         const int t = threadIdx.x + n * NT;
-        const int ci = blockIdx.x * (TX / 2) + t % (TX / 2), cj = blockIdx.y * (TY / 2) + t / (TX / 2);
-        if (ci >= C.nx || cj >= C.ny) continue;
+        const int ci = bx * (TX / 2) + t % (TX / 2), cj = by * (TY / 2) + t / (TX / 2);
+        if (ci >= C.nx || cj >= C.ny || ck[n] == 2) continue;
         const size_t cid = pidx(C, ci, cj);
-        uc[cid] = 0;
+        if (uc) uc[cid] = 0;
         T sum = 0;
         if (ck[n]) {
 #pragma unroll
@@ -380,7 +545,7 @@ __global__ __launch_bounds__(NT) void k_restrict(LevelArgs L, LevelArgs C, const
                 if (fk[n][q] == 1) {
                     const int lx = fi - i0 + 2, ly = fj - j0 + 2;
                     sum += fb[n][q] - apply_sfv<T, MIXED>(L, [&](int dx, int dy) { return s[ly + dy][lx + dx]; });
-                } else if (fk[n][q] == 2) {
+                } else if (fk[n][q] == 2 && rplg) {
                     sum += rplg[plgidx[pidx(L, fi, fj)]];
                 }
             }
@@ -389,55 +554,36 @@ __global__ __launch_bounds__(NT) void k_restrict(LevelArgs L, LevelArgs C, const
     }
 }
 
-// fine cells whose coarse parent was merged away: add to the absorbing cell
-template <typename T, bool MIXED>
-__global__ void k_restrict_ex(LevelArgs L, LevelArgs C, int nt, const int *__restrict__ ptr,
-                              const int *__restrict__ target, const int *__restrict__ child,
-                              const T *__restrict__ u, const T *__restrict__ b, const uint8_t *__restrict__ mask,
-                              const int *__restrict__ plgidx, const T *__restrict__ rplg, T *__restrict__ bc) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nt) return;
-    T sum = 0;
-    for (int e = ptr[t]; e < ptr[t + 1]; ++e) {
-        const int id = child[e];
-        const int i = id % L.pitch - 2, j = id / L.pitch - 2;
-        if (mask[id] == 1) {
-            sum += b[id] - apply_sfv<T, MIXED>(L, [&](int dx, int dy) { return fetch(u, L, i + dx, j + dy); });
-        } else if (mask[id] == 2) {
-            sum += rplg[plgidx[id]];
-        }
-    }
-    bc[target[t]] += (T)0.25 * sum;
-}
-
-// K3: piecewise-constant interpolation and correction, eq. (5.9)
+// Piecewise-constant interpolation and correction, eq. (5.9): blocks
+// [0, nmain) cover the fine rows; the rest handle the fine cells whose coarse
+// parent was merged away (they take the value of the absorbing cell).
 template <typename T>
-__global__ void k_prolong(LevelArgs L, LevelArgs C, const uint8_t *__restrict__ mask,
-                          const uint8_t *__restrict__ cmask, const T *__restrict__ ec, T *__restrict__ u) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+__global__ void k_prolong(LevelArgs L, LevelArgs C, int bx_per_row, int nmain, const uint8_t *__restrict__ mask,
+                          const uint8_t *__restrict__ cmask, const T *__restrict__ ec, T *__restrict__ u, int nex,
+                          const int *__restrict__ ex_fine, const int *__restrict__ ex_coarse) {
+    if ((int)blockIdx.x >= nmain) {
+        const int k = (blockIdx.x - nmain) * blockDim.x + threadIdx.x;
+        if (k < nex) u[ex_fine[k]] += ec[ex_coarse[k]];
+        return;
+    }
+    const int j = blockIdx.x / bx_per_row;
+    const int i = (blockIdx.x - j * bx_per_row) * blockDim.x + threadIdx.x;
     if (i >= L.nx) return;
     const size_t id = pidx(L, i, j);
     const size_t cid = pidx(C, i >> 1, j >> 1);
     if (mask[id] && cmask[cid]) u[id] += ec[cid];
 }
 
-template <typename T>
-__global__ void k_prolong_ex(int n, const int *__restrict__ fine, const int *__restrict__ coarse,
-                             const T *__restrict__ ec, T *__restrict__ u) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) u[fine[k]] += ec[coarse[k]];
-}
-
 // ---------------------------------------------------------------------------
-// K6: bottom solve x = A_c^{-1} b (FP64 dense inverse, row-major): one
-// wavefront per row, 16 wavefronts per block, the right-hand side staged in
-// LDS by every block.
+// Bottom solve x = A_c^{-1} b (FP64 dense inverse, row-major): one wavefront
+// per row, 16 wavefronts per block, the right-hand side staged in LDS by
+// every block; 4 independent partial sums per lane keep more loads in flight.
 constexpr int BOT_WAVES = 16;
 template <typename TI, typename TO>
 __global__ __launch_bounds__(64 * BOT_WAVES) void k_bottom(int n, const int *__restrict__ cells,
                                                           const double *__restrict__ ainv, const TI *__restrict__ b,
                                                           TO *__restrict__ x) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     double *bs = reinterpret_cast<double *>(smem_raw);
     for (int k = threadIdx.x; k < n; k += blockDim.x) bs[k] = (double)b[cells[k]];
     __syncthreads();
@@ -445,64 +591,94 @@ __global__ __launch_bounds__(64 * BOT_WAVES) void k_bottom(int n, const int *__r
     const int row = blockIdx.x * BOT_WAVES + wave;
     if (row >= n) return;
     const double *a = ainv + (size_t)row * n;
-    double acc = 0.0;
-    for (int c = lane; c < n; c += 64) acc += a[c] * bs[c];
-    acc = wave_sum(acc);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int c = lane;
+    for (; c + 192 < n; c += 256) {
+        a0 += a[c] * bs[c];
+        a1 += a[c + 64] * bs[c + 64];
+        a2 += a[c + 128] * bs[c + 128];
+        a3 += a[c + 192] * bs[c + 192];
+    }
+    for (; c < n; c += 64) a0 += a[c] * bs[c];
+    const double acc = wave_sum((a0 + a1) + (a2 + a3));
     if (lane == 0) x[cells[row]] = (TO)acc;
 }
 
 // ---------------------------------------------------------------------------
-// K7: residual max-norm over active cells (SFV by the stencil, PLG from
-// rplg); optionally writes r as FP32 (mixed-precision defect correction).
-template <bool MIXED, bool WRITE32>
-__global__ __launch_bounds__(NT) void k_residual_norm(LevelArgs L, const double *__restrict__ u,
+// Residual max-norm over the active cells, FP64: tiles compute the SFV rows
+// by the stencil; blocks after the tiles compute the PLG rows from their
+// fixed-width rows (one thread per row).  CORRECT: the iterate is u + e (e
+// the FP32 V-cycle correction) and the tiles write it to uout (a different
+// buffer); WRITE32: the residual is also written in FP32 (the next FP32
+// V-cycle's right-hand side).  One partial maximum per block.
+template <bool MIXED, bool WRITE32, bool CORRECT>
+__global__ __launch_bounds__(NT) void k_residual_norm(LevelArgs L, int tiles_x, int ntile, const double *__restrict__ u,
+                                                      const float *__restrict__ e, double *__restrict__ uout,
                                                       const double *__restrict__ b, const uint8_t *__restrict__ mask,
-                                                      const int *__restrict__ plgidx, const double *__restrict__ rplg,
-                                                      float *__restrict__ r32, double *__restrict__ r64,
-                                                      double *__restrict__ partial) {
+                                                      int m, const int *__restrict__ pcell,
+                                                      const int *__restrict__ fe_col,
+                                                      const double *__restrict__ fe_val, float *__restrict__ r32,
+                                                      double *__restrict__ r64, double *__restrict__ partial) {
     __shared__ double s[HY][HX];
-    __shared__ double red[NT];
-    constexpr int R = TY / (NT / TX);
-    const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
-    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-    const int i = i0 + tx;
-    uint8_t mk[R];
-    double bv[R];
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-        const int j = j0 + ty + k * (NT / TX);
-        const bool in = i < L.nx && j < L.ny;
-        const size_t id = pidx(L, in ? i : 0, in ? j : 0);
-        mk[k] = in ? mask[id] : 0;
-        bv[k] = b[id];
-    }
-    load_tile<double>(s, u, L, i0, j0);
-    __syncthreads();
+    __shared__ double gws[32];
+    __shared__ double red[NT / 64];
+    auto uat = [&](size_t id) { return CORRECT ? u[id] + (double)e[id] : u[id]; };
     double mx = 0.0;
+    if ((int)blockIdx.x >= ntile) {
+        const int q = (blockIdx.x - ntile) * NT + threadIdx.x;
+        if (q < m) {
+            const int id = pcell[q];
+            const size_t e0 = (size_t)q * ELL_W;
+            double r = b[id];
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
-        const int rr = ty + k * (NT / TX);
-        const int j = j0 + rr;
-        if (i >= L.nx || j >= L.ny) continue;
-        const size_t id = pidx(L, i, j);
-        double r = 0.0;
-        if (mk[k] == 1) {
-            const int lx = tx + 2, ly = rr + 2;
-            r = bv[k] - apply_sfv<double, MIXED>(L, [&](int dx, int dy) { return s[ly + dy][lx + dx]; });
-        } else if (mk[k] == 2) {
-            r = rplg[plgidx[id]];
+            for (int f = 0; f < ELL_W; ++f) r -= fe_val[e0 + f] * uat(fe_col[e0 + f]);
+            if (WRITE32) r32[id] = (float)r;
+            if (r64) r64[id] = r;
+            mx = fabs(r);
         }
-        if (WRITE32) r32[id] = (float)r;
-        if (r64) r64[id] = r;
-        mx = fmax(mx, fabs(r));
-    }
-    red[threadIdx.x] = mx;
-    __syncthreads();
-    for (int off = NT / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+    } else {
+        constexpr int R = TY / (NT / TX);
+        const int i0 = (blockIdx.x % tiles_x) * TX, j0 = (blockIdx.x / tiles_x) * TY;
+        const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+        const int i = i0 + tx;
+        uint8_t mk[R];
+        double bv[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int j = j0 + ty + k * (NT / TX);
+            const bool in = i < L.nx && j < L.ny;
+            const size_t id = pidx(L, in ? i : 0, in ? j : 0);
+            mk[k] = in ? mask[id] : 0;
+            bv[k] = b[id];
+        }
+        load_tile<double>(s, gws, [&](int a, int c) { return uat(pidx(L, a, c)); }, L, i0, j0);
         __syncthreads();
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int rr = ty + k * (NT / TX);
+            const int j = j0 + rr;
+            if (i >= L.nx || j >= L.ny) continue;
+            const size_t id = pidx(L, i, j);
+            if (CORRECT) uout[id] = mk[k] ? s[rr + 2][tx + 2] : 0.0;
+            if (mk[k] == 2) continue;                 // PLG rows: the blocks after the tiles
+            double r = 0.0;
+            if (mk[k] == 1) {
+                const int lx = tx + 2, ly = rr + 2;
+                r = bv[k] - apply_sfv<double, MIXED>(L, [&](int dx, int dy) { return s[ly + dy][lx + dx]; });
+            }
+            if (WRITE32) r32[id] = (float)r;
+            if (r64) r64[id] = r;
+            mx = fmax(mx, fabs(r));
+        }
     }
-    if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_down(mx, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v = red[0];
+        for (int w = 1; w < NT / 64; ++w) v = fmax(v, red[w]);
+        partial[blockIdx.x] = v;
+    }
 }
 
 __global__ void k_absmax(int n, const double *__restrict__ v, const uint8_t *__restrict__ mask,
@@ -520,7 +696,7 @@ __global__ void k_absmax(int n, const double *__restrict__ v, const uint8_t *__r
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-// K8: b = f - N g (eq. (4.19)) on the finest level
+// b = f - N g (eq. (4.19)) on the finest level
 __global__ void k_copy_active(size_t n, const uint8_t *__restrict__ mask, const double *__restrict__ src,
                               double *__restrict__ dst) {
     const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -535,18 +711,6 @@ __global__ void k_rhs_rows(int nrows, const int *__restrict__ ptr, const int *__
     double s = 0.0;
     for (int e = ptr[r]; e < ptr[r + 1]; ++e) s += coef[e] * g[gidx[e]];
     b[cell[r]] -= s;
-}
-
-// K9: u64 += e32 over active cells; zero inactive cells
-__global__ void k_add_correction(size_t n, const uint8_t *__restrict__ mask, const float *__restrict__ e,
-                                 double *__restrict__ u) {
-    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n && mask[k]) u[k] += (double)e[k];
-}
-
-__global__ void k_fill_zero_f32(size_t n, float *__restrict__ u) {
-    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) u[k] = 0.0f;
 }
 
 __global__ void k_zero_inactive(size_t n, const uint8_t *__restrict__ mask, double *__restrict__ u) {
@@ -627,24 +791,38 @@ inline dim3 tile_grid(const LevelArgs &L) { return dim3((L.nx + TX - 1) / TX, (L
 }  // namespace
 
 template <typename T>
-void launch_jacobi(const LevelArgs &L, const T *uold, const T *b, T *unew, const uint8_t *mask, hipStream_t st) {
-    if (L.mixed) hipLaunchKernelGGL((k_jacobi<T, true>), tile_grid(L), dim3(NT), 0, st, L, uold, b, unew, mask);
-    else hipLaunchKernelGGL((k_jacobi<T, false>), tile_grid(L), dim3(NT), 0, st, L, uold, b, unew, mask);
+void launch_smooth_a(const LevelArgs &L, const T *uold, const T *b, T *unew, const uint8_t *mask, bool uzero,
+                     const PlgDev<T> &P, hipStream_t st) {
+    const dim3 tg = tile_grid(L);
+    const int ntile = (int)(tg.x * tg.y);
+    const dim3 grid(ntile + P.nblk1);
+    if (L.mixed)
+        hipLaunchKernelGGL((k_smooth_a<T, true>), grid, dim3(NT), 0, st, L, uold, b, unew, mask, (int)tg.x, ntile,
+                           uzero ? 1 : 0, P);
+    else
+        hipLaunchKernelGGL((k_smooth_a<T, false>), grid, dim3(NT), 0, st, L, uold, b, unew, mask, (int)tg.x, ntile,
+                           uzero ? 1 : 0, P);
 }
 
 template <typename T>
-void launch_plg_solve(const PlgDev<T> &P, const T *b, T *u, hipStream_t st) {
-    if (P.m == 0) return;
-    const unsigned rb = (P.max_seg + PLG_ROWS - 1) / PLG_ROWS;
-    hipLaunchKernelGGL((k_plg_gather<T>), dim3((P.m + 7) / 8), dim3(256), 0, st, P, b, u, P.t);
-    if (P.nseg) hipLaunchKernelGGL((k_plg_seg<T>), dim3(P.nseg, rb), dim3(256), sizeof(T) * P.max_seg, st, P, P.t, u);
-    if (P.nsep) {
-        hipLaunchKernelGGL((k_plg_sep_rhs<T>), dim3((P.nsep + 7) / 8), dim3(256), 0, st, P, P.t);
-        hipLaunchKernelGGL((k_plg_sep<T>), dim3((P.nsep + PLG_ROWS - 1) / PLG_ROWS), dim3(256), sizeof(T) * P.nsep, st,
-                           P, u);
-        if (P.nseg) hipLaunchKernelGGL((k_plg_fix<T>), dim3(P.nseg, rb), dim3(256), 0, st, P, u);
-    }
+void launch_smooth_b(const PlgDev<T> &P, T *unew, hipStream_t st) {
+    if (P.nblk2)
+        hipLaunchKernelGGL((k_smooth_b<T>), dim3(P.nblk2), dim3(NT), sizeof(T) * (((P.nsep + 3) & ~3) + PLG_KMAX), st,
+                           P, unew);
 }
+
+template <typename T>
+__global__ void k_fill_zero(size_t n, T *__restrict__ u) {
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) u[k] = (T)0;
+}
+
+template <typename T>
+void launch_fill_zero(size_t n, T *u, hipStream_t st) {
+    hipLaunchKernelGGL((k_fill_zero<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, u);
+}
+
+size_t smooth_lds_bytes(bool fp64) { return fp64 ? smooth_a_lds<double>() : smooth_a_lds<float>(); }
 
 template <typename T>
 void launch_plg_residual(int m, const int *cell, const int *ptr, const int *col, const T *val, const T *b,
@@ -655,29 +833,25 @@ void launch_plg_residual(int m, const int *cell, const int *ptr, const int *col,
 
 template <typename T>
 void launch_restrict(const LevelArgs &L, const LevelArgs &C, const T *u, const T *b, const uint8_t *mask,
-                     const int *plgidx, const T *rplg, const uint8_t *cmask, T *bc, T *uc, int nt, const int *ex_ptr,
+                     const int *plgidx, const T *rplg, const uint8_t *rmask, T *bc, T *uc, int nt, const int *ex_ptr,
                      const int *ex_target, const int *ex_child, hipStream_t st) {
-    dim3 grid((C.nx + TX / 2 - 1) / (TX / 2), (C.ny + TY / 2 - 1) / (TY / 2));
+    const int tx = (C.nx + TX / 2 - 1) / (TX / 2), ty = (C.ny + TY / 2 - 1) / (TY / 2);
+    const int ntile = tx * ty;
+    const dim3 grid(ntile + (nt + NT - 1) / NT);
     if (L.mixed)
-        hipLaunchKernelGGL((k_restrict<T, true>), grid, dim3(NT), 0, st, L, C, u, b, mask, plgidx, rplg, cmask, bc, uc);
+        hipLaunchKernelGGL((k_restrict<T, true>), grid, dim3(NT), 0, st, L, C, tx, ntile, u, b, mask, plgidx, rplg,
+                           rmask, bc, uc, nt, ex_ptr, ex_target, ex_child);
     else
-        hipLaunchKernelGGL((k_restrict<T, false>), grid, dim3(NT), 0, st, L, C, u, b, mask, plgidx, rplg, cmask, bc, uc);
-    if (nt) {
-        if (L.mixed)
-            hipLaunchKernelGGL((k_restrict_ex<T, true>), dim3((nt + 63) / 64), dim3(64), 0, st, L, C, nt, ex_ptr,
-                               ex_target, ex_child, u, b, mask, plgidx, rplg, bc);
-        else
-            hipLaunchKernelGGL((k_restrict_ex<T, false>), dim3((nt + 63) / 64), dim3(64), 0, st, L, C, nt, ex_ptr,
-                               ex_target, ex_child, u, b, mask, plgidx, rplg, bc);
-    }
+        hipLaunchKernelGGL((k_restrict<T, false>), grid, dim3(NT), 0, st, L, C, tx, ntile, u, b, mask, plgidx, rplg,
+                           rmask, bc, uc, nt, ex_ptr, ex_target, ex_child);
 }
 
 template <typename T>
 void launch_prolong(const LevelArgs &L, const LevelArgs &C, const uint8_t *mask, const uint8_t *cmask, const T *ec,
                     T *u, int nex, const int *ex_fine, const int *ex_coarse, hipStream_t st) {
-    hipLaunchKernelGGL((k_prolong<T>), dim3((L.nx + 255) / 256, L.ny), dim3(256), 0, st, L, C, mask, cmask, ec, u);
-    if (nex)
-        hipLaunchKernelGGL((k_prolong_ex<T>), dim3((nex + 255) / 256), dim3(256), 0, st, nex, ex_fine, ex_coarse, ec, u);
+    const int bxr = (L.nx + 255) / 256, nmain = bxr * L.ny;
+    hipLaunchKernelGGL((k_prolong<T>), dim3(nmain + (nex + 255) / 256), dim3(256), 0, st, L, C, bxr, nmain, mask, cmask,
+                       ec, u, nex, ex_fine, ex_coarse);
 }
 
 template <typename TI, typename TO>
@@ -686,17 +860,24 @@ void launch_bottom(int n, const int *cells, const double *ainv, const TI *b, TO 
                        sizeof(double) * n, st, n, cells, ainv, b, x);
 }
 
-int launch_residual_norm(const LevelArgs &L, const double *u, const double *b, const uint8_t *mask, const int *plgidx,
-                         const double *rplg, float *r32, double *r64, double *partial, hipStream_t st) {
-    dim3 g = tile_grid(L);
-    if (r32) {
-        if (L.mixed) hipLaunchKernelGGL((k_residual_norm<true, true>), g, dim3(NT), 0, st, L, u, b, mask, plgidx, rplg, r32, r64, partial);
-        else hipLaunchKernelGGL((k_residual_norm<false, true>), g, dim3(NT), 0, st, L, u, b, mask, plgidx, rplg, r32, r64, partial);
+int launch_residual_norm(const LevelArgs &L, const double *u, const float *e, double *uout, const double *b,
+                         const uint8_t *mask, int m, const int *pcell, const int *fe_col, const double *fe_val,
+                         float *r32, double *r64, double *partial, hipStream_t st) {
+    const dim3 tg = tile_grid(L);
+    const int ntile = (int)(tg.x * tg.y), nblk = ntile + (m + NT - 1) / NT;
+#define MG_RES(MX, W32, CORR)                                                                                         \
+    hipLaunchKernelGGL((k_residual_norm<MX, W32, CORR>), dim3(nblk), dim3(NT), 0, st, L, (int)tg.x, ntile, u, e, uout, \
+                       b, mask, m, pcell, fe_col, fe_val, r32, r64, partial)
+    const bool w32 = r32 != nullptr, corr = e != nullptr;
+    if (L.mixed) {
+        if (corr) { if (w32) MG_RES(true, true, true); else MG_RES(true, false, true); }
+        else { if (w32) MG_RES(true, true, false); else MG_RES(true, false, false); }
     } else {
-        if (L.mixed) hipLaunchKernelGGL((k_residual_norm<true, false>), g, dim3(NT), 0, st, L, u, b, mask, plgidx, rplg, r32, r64, partial);
-        else hipLaunchKernelGGL((k_residual_norm<false, false>), g, dim3(NT), 0, st, L, u, b, mask, plgidx, rplg, r32, r64, partial);
+        if (corr) { if (w32) MG_RES(false, true, true); else MG_RES(false, false, true); }
+        else { if (w32) MG_RES(false, true, false); else MG_RES(false, false, false); }
     }
-    return (int)(g.x * g.y);
+#undef MG_RES
+    return nblk;
 }
 
 void launch_absmax(int n, const double *v, const uint8_t *mask, double *partial, int nblocks, hipStream_t st) {
@@ -710,14 +891,6 @@ void launch_rhs(size_t n, const uint8_t *mask, const double *f, double *b, int n
         hipLaunchKernelGGL(k_rhs_rows, dim3((nrows + 255) / 256), dim3(256), 0, st, nrows, ptr, cell, gidx, coef, g, b);
 }
 
-void launch_add_correction(size_t n, const uint8_t *mask, const float *e, double *u, hipStream_t st) {
-    hipLaunchKernelGGL(k_add_correction, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, mask, e, u);
-}
-
-void launch_fill_zero(size_t n, float *u, hipStream_t st) {
-    hipLaunchKernelGGL(k_fill_zero_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, u);
-}
-
 void launch_zero_inactive(size_t n, const uint8_t *mask, double *u, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_inactive, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, mask, u);
 }
@@ -727,10 +900,14 @@ void launch_fit(int m, const double *M, const double *phi, const double *w, cons
     hipLaunchKernelGGL(k_fit, dim3((m + 63) / 64), dim3(64), 0, st, m, M, phi, w, ncol, work, beta, status);
 }
 
-template void launch_jacobi<double>(const LevelArgs &, const double *, const double *, double *, const uint8_t *, hipStream_t);
-template void launch_jacobi<float>(const LevelArgs &, const float *, const float *, float *, const uint8_t *, hipStream_t);
-template void launch_plg_solve<double>(const PlgDev<double> &, const double *, double *, hipStream_t);
-template void launch_plg_solve<float>(const PlgDev<float> &, const float *, float *, hipStream_t);
+template void launch_smooth_a<double>(const LevelArgs &, const double *, const double *, double *, const uint8_t *,
+                                      bool, const PlgDev<double> &, hipStream_t);
+template void launch_smooth_a<float>(const LevelArgs &, const float *, const float *, float *, const uint8_t *, bool,
+                                     const PlgDev<float> &, hipStream_t);
+template void launch_smooth_b<double>(const PlgDev<double> &, double *, hipStream_t);
+template void launch_smooth_b<float>(const PlgDev<float> &, float *, hipStream_t);
+template void launch_fill_zero<double>(size_t, double *, hipStream_t);
+template void launch_fill_zero<float>(size_t, float *, hipStream_t);
 template void launch_plg_residual<double>(int, const int *, const int *, const int *, const double *, const double *, const double *, double *, hipStream_t);
 template void launch_plg_residual<float>(int, const int *, const int *, const int *, const float *, const float *, const float *, float *, hipStream_t);
 template void launch_restrict<double>(const LevelArgs &, const LevelArgs &, const double *, const double *, const uint8_t *, const int *, const double *, const uint8_t *, double *, double *, int, const int *, const int *, const int *, hipStream_t);

@@ -26,28 +26,48 @@ struct LevelArgs {
     int mixed;                  // b != 0
 };
 
-// PLG block solve data of one level (device pointers)
+// PLG block solve data of one level (device pointers).  Rows are numbered
+// in solve order: the segments (consecutive runs), then the separators.
+// Row-wise sparse data have a fixed width of ELL_W entries (zero padding).
 template <typename T>
 struct PlgDev {
     int m = 0, nseg = 0, nsep = 0, sep_begin = 0;
-    const int *cell = nullptr;          // [m] padded cell index, solve order
-    const int *a21_ptr = nullptr;       // [m+1] SFV couplings of each PLG row (solve order)
-    const int *a21_col = nullptr;       // padded cell index
+    const int *cell = nullptr;          // [m] padded cell index
+    // gather groups (launch A)
+    const int *grp_start = nullptr;     // [ngroup + 1]
+    const int *hptr = nullptr, *hcell = nullptr;   // SFV cells coupled to each group
+    const int *a21_loc = nullptr;       // [m * ELL_W] index into the group's H
     const T *a21_val = nullptr;
-    const int *seg_start = nullptr;     // [nseg+1]
-    const long long *inv_off = nullptr; // [nseg]
-    const T *inv = nullptr;             // row-major segment inverses
-    const long long *f_off = nullptr;
-    const T *F = nullptr;
-    const int *fcols_ptr = nullptr, *fcols = nullptr;
-    const T *sinv = nullptr;            // row-major
-    const int *sb_ptr = nullptr, *sb_col = nullptr;   // separator rows -> segment positions
-    const T *sb_val = nullptr;
-    T *t = nullptr;                     // [m] workspace: b2 - A21 u1
-    T *y = nullptr;                     // [m] workspace
-    T *xs = nullptr;                    // [nsep] workspace
-    T *rs = nullptr;                    // [nsep] workspace: separator right-hand side
-    int max_seg = 0;
+    int nblk1 = 0;
+    const int4 *blk1 = nullptr;         // (group, r0, r1, -)
+    // segments
+    const int *seg_start = nullptr;     // [nseg + 1]
+    const long long *inv_off = nullptr; // row-major segment inverses
+    const T *inv = nullptr;
+    const int *ce_ptr = nullptr, *ce_row = nullptr, *ce_slot = nullptr;   // A_SB entries on each segment's rows
+    const T *ce_val = nullptr;
+    // separators (launch B)
+    int nblk2 = 0;
+    const int4 *blk2 = nullptr;         // (0 segment slice | 1 separator rows, j, r0, r1)
+    const long long *ft_off = nullptr;  // F_j^T = (B_j^{-1} A_{j,S})^T, row-major k_j x L_j
+    const T *FT = nullptr;
+    const int *fcols_ptr = nullptr;     // k_j = fcols_ptr[j + 1] - fcols_ptr[j]
+    const long long *sj_off = nullptr;  // rows of S'^{-1} at segment j's separator columns, k_j x nsep
+    const T *SJ = nullptr;
+    const T *sinv = nullptr;            // row-major nsep x nsep
+    T *t = nullptr;                     // [m] separator right-hand sides b2 - A21 u1
+    T *y = nullptr;                     // [m] segment solutions B^{-1} t
+    T *contrib = nullptr;               // [nsep * ELL_W] entries of A_SB times y
 };
+
+constexpr int ELL_W = 16;               // width of the row-wise sparse data
+
+// Limits of the LDS staging (checked at setup).
+constexpr int PLG_HMAX = 1536;          // SFV cells coupled to one group
+constexpr int PLG_LMAX = 320;           // rows of one group (segments reach 1.25x the nominal 256)
+constexpr int PLG_KMAX = 256;           // separator columns of one segment
+constexpr int PLG_SMAX = 4096;          // separator rows of one level
+constexpr int PLG_SLICE = 32;           // segment rows per block
+constexpr int PLG_SEP_ROWS = 32;        // separator rows per block of launch B
 
 }  // namespace mgc

@@ -9,30 +9,38 @@ namespace mgc {
 
 hipError_t upload_ghost_table(const double gw[2][2][4]);
 
+// one block-smoother sweep (Definition 5.6), uold -> unew: launch A (SFV
+// tiles, PLG gathers and segment solves), then launch B (separators and
+// segment corrections; nothing on levels without separators)
 template <typename T>
-void launch_jacobi(const LevelArgs &L, const T *uold, const T *b, T *unew, const uint8_t *mask, hipStream_t st);
+void launch_smooth_a(const LevelArgs &L, const T *uold, const T *b, T *unew, const uint8_t *mask, bool uzero,
+                     const PlgDev<T> &P, hipStream_t st);
 template <typename T>
-void launch_plg_solve(const PlgDev<T> &P, const T *b, T *u, hipStream_t st);
+void launch_smooth_b(const PlgDev<T> &P, T *unew, hipStream_t st);
+template <typename T>
+void launch_fill_zero(size_t n, T *u, hipStream_t st);
+size_t smooth_lds_bytes(bool fp64);
 template <typename T>
 void launch_plg_residual(int m, const int *cell, const int *ptr, const int *col, const T *val, const T *b,
                          const T *u, T *r, hipStream_t st);
 template <typename T>
 void launch_restrict(const LevelArgs &L, const LevelArgs &C, const T *u, const T *b, const uint8_t *mask,
-                     const int *plgidx, const T *rplg, const uint8_t *cmask, T *bc, T *uc, int nt, const int *ex_ptr,
+                     const int *plgidx, const T *rplg, const uint8_t *rmask, T *bc, T *uc, int nt, const int *ex_ptr,
                      const int *ex_target, const int *ex_child, hipStream_t st);
 template <typename T>
 void launch_prolong(const LevelArgs &L, const LevelArgs &C, const uint8_t *mask, const uint8_t *cmask, const T *ec,
                     T *u, int nex, const int *ex_fine, const int *ex_coarse, hipStream_t st);
 template <typename TI, typename TO>
 void launch_bottom(int n, const int *cells, const double *ainv, const TI *b, TO *x, hipStream_t st);
-int launch_residual_norm(const LevelArgs &L, const double *u, const double *b, const uint8_t *mask, const int *plgidx,
-                         const double *rplg, float *r32, double *r64, double *partial, hipStream_t st);
+// residual b - A u (u + e when e is given, written to uout) with partial
+// max-norms per block; returns the number of blocks
+int launch_residual_norm(const LevelArgs &L, const double *u, const float *e, double *uout, const double *b,
+                         const uint8_t *mask, int m, const int *pcell, const int *fe_col, const double *fe_val,
+                         float *r32, double *r64, double *partial, hipStream_t st);
 void launch_absmax(int n, const double *v, const uint8_t *mask, double *partial, int nblocks, hipStream_t st);
 void launch_rhs(size_t n, const uint8_t *mask, const double *f, double *b, int nrows, const int *ptr, const int *cell,
                 const int *gidx, const double *coef, const double *g, hipStream_t st);
-void launch_add_correction(size_t n, const uint8_t *mask, const float *e, double *u, hipStream_t st);
 void launch_zero_inactive(size_t n, const uint8_t *mask, double *u, hipStream_t st);
-void launch_fill_zero(size_t n, float *u, hipStream_t st);
 void launch_fit(int m, const double *M, const double *phi, const double *w, const int *ncol, double *work,
                 double *beta, int *status, hipStream_t st);
 

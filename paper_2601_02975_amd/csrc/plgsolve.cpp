@@ -13,6 +13,7 @@
 // where S' = A_SS - A_SB B^{-1} A_BS.  B^{-1} (per segment), B^{-1} A_BS and
 // S'^{-1} are dense and precomputed, so a solve is three parallel passes.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <numeric>
 
@@ -302,6 +303,116 @@ void build_plg_solver(const Level &L, int seg_max, PlgSolver &S) {
                 S.sb_val.push_back(e.second);
             }
         S.sb_ptr[r - sb + 1] = (int)S.sb_col.size();
+    }
+}
+
+}  // namespace mgc
+
+namespace mgc {
+
+void build_plg_plan(const Level &L, const PlgSolver &S, int nx, int slice, int sep_group, int sep_rows,
+                    PlgPlan &P) {
+    P = PlgPlan();
+    const int m = S.m;
+    auto padded = [nx](int cell) { return (cell / nx + 2) * (nx + 4) + (cell % nx + 2); };
+    // groups: the segments, then the separators in runs of sep_group rows
+    P.grp_start.push_back(0);
+    for (int j = 0; j < S.nseg; ++j) P.grp_start.push_back(S.seg_start[j + 1]);
+    for (int s = S.sep_begin; s < m; s += sep_group) P.grp_start.push_back(std::min(m, s + sep_group));
+    P.ngroup = (int)P.grp_start.size() - 1;
+    // H of each group and the A21 rows in group-local numbering
+    P.hptr.push_back(0);
+    P.a21_loc.assign((size_t)m * ELL_W, 0);
+    P.a21_val.assign((size_t)m * ELL_W, 0.0);
+    for (int g = 0; g < P.ngroup; ++g) {
+        std::vector<int> seen;                         // cells of H, first-appearance order
+        for (int q = P.grp_start[g]; q < P.grp_start[g + 1]; ++q) {
+            const int r = S.order[q];
+            int k = 0;
+            for (int e = L.row_ptr[r]; e < L.row_ptr[r + 1]; ++e) {
+                const int c = L.col[e];
+                if (L.kind[c] != 1) continue;
+                int loc = (int)(std::find(seen.begin(), seen.end(), c) - seen.begin());
+                if (loc == (int)seen.size()) seen.push_back(c);
+                if (k == ELL_W) fail(MG_ERR_UNSUPPORTED, "a PLG row has more SFV couplings than the row width");
+                P.a21_loc[(size_t)q * ELL_W + k] = loc;
+                P.a21_val[(size_t)q * ELL_W + k] = L.val[e];
+                ++k;
+            }
+        }
+        for (int c : seen) P.hcell.push_back(padded(c));
+        P.hptr.push_back((int)P.hcell.size());
+        P.hmax = std::max(P.hmax, (int)seen.size());
+        P.lmax = std::max(P.lmax, P.grp_start[g + 1] - P.grp_start[g]);
+    }
+    // padded segment inverses
+    auto pad4 = [](int n) { return (n + 3) & ~3; };
+    P.inv_off.assign(S.nseg + 1, 0);
+    for (int j = 0; j < S.nseg; ++j) {
+        const int Lj = S.seg_start[j + 1] - S.seg_start[j], Lp = pad4(Lj);
+        P.inv_off[j + 1] = P.inv_off[j] + (long long)Lj * Lp;
+    }
+    P.INV.assign(P.inv_off[S.nseg], 0.0);
+    for (int j = 0; j < S.nseg; ++j) {
+        const int Lj = S.seg_start[j + 1] - S.seg_start[j], Lp = pad4(Lj);
+        for (int r = 0; r < Lj; ++r)
+            for (int c = 0; c < Lj; ++c)
+                P.INV[P.inv_off[j] + (size_t)r * Lp + c] = S.inv[S.inv_off[j] + (size_t)r * Lj + c];
+    }
+    // launch A blocks: segment slices, then one block per separator group
+    for (int g = 0; g < P.ngroup; ++g) {
+        const int g0 = P.grp_start[g], g1 = P.grp_start[g + 1];
+        const int step = g < S.nseg ? slice : g1 - g0;
+        for (int r = g0; r < g1; r += step) P.blk1.insert(P.blk1.end(), {g, r, std::min(g1, r + step), 0});
+    }
+    if (S.nsep == 0) return;
+    // launch B blocks: the same segment slices, then separator rows in runs
+    for (int j = 0; j < S.nseg; ++j)
+        for (int r = S.seg_start[j]; r < S.seg_start[j + 1]; r += slice)
+            P.blk2.insert(P.blk2.end(), {0, j, r, std::min(S.seg_start[j + 1], r + slice)});
+    for (int s = 0; s < S.nsep; s += sep_rows) P.blk2.insert(P.blk2.end(), {1, 0, s, std::min(S.nsep, s + sep_rows)});
+    // A_SB entries owned by each segment, in ELL slots of the separator rows
+    std::vector<int> seg_of(S.sep_begin);
+    for (int j = 0, q = 0; q < S.sep_begin; ++q) {
+        while (q >= S.seg_start[j + 1]) ++j;
+        seg_of[q] = j;
+    }
+    std::vector<std::vector<std::array<int, 2>>> own(S.nseg);   // (slot, entry)
+    for (int s = 0; s < S.nsep; ++s) {
+        if (S.sb_ptr[s + 1] - S.sb_ptr[s] > ELL_W)
+            fail(MG_ERR_UNSUPPORTED, "a separator row has more segment couplings than the row width");
+        for (int e = S.sb_ptr[s]; e < S.sb_ptr[s + 1]; ++e)
+            own[seg_of[S.sb_col[e]]].push_back({s * ELL_W + (e - S.sb_ptr[s]), e});
+    }
+    P.ce_ptr.push_back(0);
+    for (int j = 0; j < S.nseg; ++j) {
+        for (auto &se : own[j]) {
+            P.ce_row.push_back(S.sb_col[se[1]]);
+            P.ce_slot.push_back(se[0]);
+            P.ce_val.push_back(S.sb_val[se[1]]);
+        }
+        P.ce_ptr.push_back((int)P.ce_row.size());
+    }
+    // S'^{-1}, F_j^T and the rows of S'^{-1} that segment j needs
+    const int nsp = pad4(S.nsep);
+    P.SINV.assign((size_t)S.nsep * nsp, 0.0);
+    for (int r = 0; r < S.nsep; ++r)
+        for (int c = 0; c < S.nsep; ++c) P.SINV[(size_t)r * nsp + c] = S.sinv[(size_t)r * S.nsep + c];
+    P.ft_off.assign(S.nseg + 1, 0);
+    P.sj_off.assign(S.nseg + 1, 0);
+    P.FT.assign(S.F.size(), 0.0);
+    for (int j = 0; j < S.nseg; ++j) {
+        const int Lj = S.seg_start[j + 1] - S.seg_start[j], k = S.fcols_ptr[j + 1] - S.fcols_ptr[j];
+        P.ft_off[j + 1] = P.ft_off[j] + (long long)Lj * k;
+        P.sj_off[j + 1] = P.sj_off[j] + (long long)k * nsp;
+        for (int r = 0; r < Lj; ++r)
+            for (int kk = 0; kk < k; ++kk)
+                P.FT[P.ft_off[j] + (size_t)kk * Lj + r] = S.F[S.f_off[j] + (size_t)r * k + kk];
+        for (int kk = 0; kk < k; ++kk) {
+            const int row = S.fcols[S.fcols_ptr[j] + kk];
+            P.SJ.insert(P.SJ.end(), P.SINV.begin() + (size_t)row * nsp, P.SINV.begin() + (size_t)(row + 1) * nsp);
+        }
+        P.kmax = std::max(P.kmax, k);
     }
 }
 
