@@ -31,9 +31,10 @@ def kernel_source_hash():
 
 
 def load_traffic(precision):
-    """HBM bytes per launch of the finest-level sweep from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "traffic_sfv_sweep_three_disks1024.json")
+    """HBM bytes per launch of the finest-level smoother launch A from the
+    committed rocprofv3 counter summary, if it was taken on the current kernel
+    source."""
+    path = os.path.join(ROOT, "profiles", "traffic_smooth_a_three_disks1024.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -143,7 +144,10 @@ def main():
     diff = float((u32 - u64).abs().max() / u64.abs().max())
 
     n_cells = P.grid.nx * P.grid.ny
-    alg_bytes = 3 * 4 * n_cells                     # FP32 sweep: read u, b; write u
+    # FP32 launch A on the finest level: u, b read and u written on the SFV
+    # cells, the PLG segment inverses read once, b read and u/y written on
+    # the PLG rows (words of 4 bytes), plus one byte of class mask per cell
+    alg_bytes = 4 * S32.info["sweep_words"][0] + n_cells
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None
     traffic = load_traffic("fp32")
     out = {
@@ -165,7 +169,7 @@ def main():
         "fp64": {"value": args.steps / dt64, "unit": "solves/s", "iterations": it64[-1], "rel_residual": rel64},
         "mixed": {"iterations": it32[-1], "rel_residual": rel32, "max_rel_diff_vs_fp64": diff},
         "speedup_mixed_over_fp64": dt64 / dt32,
-        "roofline": {"bound": "hbm", "kernel": "k_jacobi<float> (finest-level SFV sweep)",
+        "roofline": {"bound": "hbm", "kernel": "k_smooth_a<float> (finest level: SFV Jacobi tiles + PLG segment solves)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
                      "launches_timed": nl, "avg_launch_ms": avg_ms,
