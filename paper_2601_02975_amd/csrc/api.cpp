@@ -28,6 +28,8 @@ namespace {
     } while (0)
 
 constexpr int SEG_MAX = 256;       // longest PLG segment (dense inverse per segment)
+constexpr int SEG_WHOLE = 768;     // a level whose hole chains fit in segments this long needs no separators
+constexpr int ITER_CHUNK = 8;      // most outer iterations per launch (chunks of 1, 2, 4, 8)
 constexpr int BOTTOM_MAX = 8192;   // largest dense bottom inverse (right-hand side staged in 64 KiB of LDS)
 
 struct DevLevel {
@@ -78,8 +80,9 @@ struct mg_handle_s {
     std::string last_error;
     // captured outer iteration per precision (0 FP64, 1 mixed)
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t iter_exec[3] = {nullptr, nullptr, nullptr};
-    hipGraph_t iter_graph[3] = {nullptr, nullptr, nullptr};
+    // [FP64 | mixed from u64[0] | mixed from u64[1]] x [1, 2, 4, 8 iterations]
+    hipGraphExec_t iter_exec[3][4] = {};
+    hipGraph_t iter_graph[3][4] = {};
     int upar = 0;                 // mixed precision: which FP64 buffer holds the iterate
     // timing of the finest-level SFV sweep
     bool timing = false;
@@ -262,7 +265,8 @@ void upload_level(mg_handle h, int l, bool last, hipStream_t st) {
         fail(MG_ERR_UNSUPPORTED, "PLG block partition exceeds the LDS staging limits");
     int *grp_start = h->upload(G.grp_start), *hptr = h->upload(G.hptr), *hcell = h->upload(G.hcell);
     int *a21_loc = h->upload(G.a21_loc);
-    int *blk1 = h->upload(G.blk1), *blk2 = h->upload(G.blk2);
+    const PlgBlkA *blk1 = h->upload(G.blk1);
+    const PlgBlkB *blk2 = h->upload(G.blk2);
     int *seg_start = h->upload(S.seg_start);
     long long *inv_off = h->upload(G.inv_off), *ft_off = h->upload(G.ft_off), *sj_off = h->upload(G.sj_off);
     int *fcols_ptr = h->upload(S.fcols_ptr);
@@ -273,10 +277,10 @@ void upload_level(mg_handle h, int l, bool last, hipStream_t st) {
         P.cell = D.plg_cell;
         P.grp_start = grp_start; P.hptr = hptr; P.hcell = hcell;
         P.a21_loc = a21_loc; P.a21_val = a21v;
-        P.nblk1 = (int)G.blk1.size() / 4; P.blk1 = reinterpret_cast<const int4 *>(blk1);
+        P.nblk1 = (int)G.blk1.size(); P.blk1 = blk1;
         P.seg_start = seg_start; P.inv_off = inv_off; P.inv = inv;
         P.ce_ptr = ce_ptr; P.ce_row = ce_row; P.ce_slot = ce_slot; P.ce_val = cev;
-        P.nblk2 = (int)G.blk2.size() / 4; P.blk2 = reinterpret_cast<const int4 *>(blk2);
+        P.nblk2 = (int)G.blk2.size(); P.blk2 = blk2;
         P.ft_off = ft_off; P.FT = FT; P.fcols_ptr = fcols_ptr; P.sj_off = sj_off; P.SJ = SJ; P.sinv = sinv;
         P.t = t; P.y = y; P.contrib = contrib;
     };
@@ -485,52 +489,58 @@ double residual_norm(mg_handle h, int l, const double *u, const double *b, doubl
     return device_absmax_finish(h, nb, st);
 }
 
-// ||b - A u||_inf of the finest level into *h->host_scalar (no
+// ||b - A u||_inf of the finest level into h->host_scalar[slot] (no
 // synchronisation); u is u64[src] (+ e, written to u64[1 - src], when e is
 // given); mixed: the residual also goes to b32 in FP32
-void enqueue_residual(mg_handle h, bool mixed, int src, const float *e, hipStream_t st) {
+void enqueue_residual(mg_handle h, bool mixed, int src, const float *e, int slot, hipStream_t st) {
     DevLevel &D = h->dev[0];
     int nb = launch_residual_norm(D.args, D.u64[src], e, e ? D.u64[1 - src] : nullptr, D.b64, D.mask, D.m,
                                   D.plg_cell, D.fe_col, D.fe_val, mixed ? D.b32 : nullptr, nullptr, h->partial, st);
     launch_absmax(nb, h->partial, nullptr, h->partial + h->npartial - 1, 1, st);
-    HIPCHECK(hipMemcpyAsync(h->host_scalar, h->partial + h->npartial - 1, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipMemcpyAsync(h->host_scalar + slot, h->partial + h->npartial - 1, sizeof(double),
+                            hipMemcpyDeviceToHost, st));
 }
 
 // one outer iteration on the handle's own buffers: a V-cycle (FP64), or an
 // FP32 V-cycle from zero on the FP32 residual whose result corrects the FP64
 // iterate u64[par] into u64[1 - par] (mixed); then the residual
-void enqueue_iteration(mg_handle h, bool mixed, int par, hipStream_t st) {
+void enqueue_iteration(mg_handle h, bool mixed, int par, int slot, hipStream_t st) {
     DevLevel &D = h->dev[0];
     D.cur = 0;
     if (mixed) {
         vcycle<float>(h, 0, true, st);
         const float *e = D.u32[D.cur];
         D.cur = 0;
-        enqueue_residual(h, true, par, e, st);
+        enqueue_residual(h, true, par, e, slot, st);
     } else {
         vcycle<double>(h, 0, false, st);
         if (D.cur != 0) HIPCHECK(hipMemcpyAsync(D.u64[0], D.u64[1], D.ncells * 8, hipMemcpyDeviceToDevice, st));
         D.cur = 0;
-        enqueue_residual(h, false, 0, nullptr, st);
+        enqueue_residual(h, false, 0, nullptr, slot, st);
     }
 }
 
-void run_iteration(mg_handle h, bool mixed, hipStream_t st) {
+// k outer iterations (k = 1, 2, 4 or 8); residual norms in
+// h->host_scalar[0, k)
+void run_iterations(mg_handle h, bool mixed, int k, hipStream_t st) {
     const int par = mixed ? h->upar : 0;
-    const int p = mixed ? 1 + par : 0;
+    const int p = mixed ? 1 + par : 0, c = k == 1 ? 0 : k == 2 ? 1 : k == 4 ? 2 : 3;
+    auto enqueue = [&](hipStream_t s) {
+        for (int i = 0; i < k; ++i) enqueue_iteration(h, mixed, mixed ? (par + i) & 1 : 0, i, s);
+    };
     if (h->timing) {                     // eager launches (events around the sweeps)
-        enqueue_iteration(h, mixed, par, st);
+        enqueue(st);
     } else {
-        if (!h->iter_exec[p]) {
+        if (!h->iter_exec[p][c]) {
             if (!h->cap_stream) HIPCHECK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
             HIPCHECK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-            enqueue_iteration(h, mixed, par, h->cap_stream);
-            HIPCHECK(hipStreamEndCapture(h->cap_stream, &h->iter_graph[p]));
-            HIPCHECK(hipGraphInstantiate(&h->iter_exec[p], h->iter_graph[p], nullptr, nullptr, 0));
+            enqueue(h->cap_stream);
+            HIPCHECK(hipStreamEndCapture(h->cap_stream, &h->iter_graph[p][c]));
+            HIPCHECK(hipGraphInstantiate(&h->iter_exec[p][c], h->iter_graph[p][c], nullptr, nullptr, 0));
         }
-        HIPCHECK(hipGraphLaunch(h->iter_exec[p], st));
+        HIPCHECK(hipGraphLaunch(h->iter_exec[p][c], st));
     }
-    if (mixed) h->upar = 1 - h->upar;
+    if (mixed && (k & 1)) h->upar = 1 - h->upar;
 }
 
 thread_local std::string g_last_error;
@@ -655,7 +665,12 @@ mg_status mg_setup(const mg_grid *grid, int n_curves, const mg_curve *curves, do
         }
         const int nl = (int)h->levels.size();
         h->solvers.resize(nl);
-        for (int l = 0; l < nl; ++l) build_plg_solver(*h->levels[l], SEG_MAX, h->solvers[l]);
+        for (int l = 0; l < nl; ++l) {
+            // whole chains as segments when that leaves no separators (one
+            // smoother launch per sweep), else short segments
+            build_plg_solver(*h->levels[l], SEG_WHOLE, h->solvers[l]);
+            if (h->solvers[l].nsep > 0) build_plg_solver(*h->levels[l], SEG_MAX, h->solvers[l]);
+        }
         h->dev.resize(nl);
         for (int l = 0; l < nl; ++l) upload_level(h.get(), l, l == nl - 1, st);
         upload_rhs(h.get());
@@ -664,7 +679,7 @@ mg_status mg_setup(const mg_grid *grid, int n_curves, const mg_curve *curves, do
             maxblk = std::max(maxblk, ((D.args.nx + 63) / 64) * ((D.args.ny + 31) / 32) + (D.m + 255) / 256);
         h->npartial = std::max(maxblk, 1024) + 1;
         h->partial = h->alloc<double>(h->npartial);
-        HIPCHECK(hipHostMalloc((void **)&h->host_scalar, sizeof(double)));
+        HIPCHECK(hipHostMalloc((void **)&h->host_scalar, sizeof(double) * ITER_CHUNK));
         HIPCHECK(hipDeviceSynchronize());
         h->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     });
@@ -742,20 +757,37 @@ mg_status mg_solve(mg_handle h, const double *f_dev, const double *g_dev, double
         // so the captured iteration can be replayed)
         HIPCHECK(hipMemcpyAsync(D.u64[0], u_dev, D.ncells * 8, hipMemcpyDeviceToDevice, st));
         h->upar = 0;
-        enqueue_residual(h, mixed, 0, nullptr, st);
+        enqueue_residual(h, mixed, 0, nullptr, 0, st);
         HIPCHECK(hipStreamSynchronize(st));
         int it = 0, grow = 0;
-        double rel = *h->host_scalar / bnorm;
-        double prev = rel;
-        while (rel > tol && it < h->opt.max_iters) {
-            run_iteration(h, mixed, st);
+        double rel = h->host_scalar[0] / bnorm;
+        double prev = rel, rmin = 1.0;
+        int nratio = 0;
+        bool stop = false;
+        while (!stop && rel > tol && it < h->opt.max_iters) {
+            // several iterations per launch (one host round trip) while the
+            // tolerance cannot be reached within them even at 1.5 times the
+            // fastest logarithmic rate seen so far
+            int k = 1;
+            if (nratio >= 2 && rmin > 0.0 && rmin < 1.0) {
+                const double need = std::log(tol / rel) / (1.5 * std::log(rmin));
+                while (k < ITER_CHUNK && need >= 2 * k + 1 && it + 2 * k <= h->opt.max_iters) k *= 2;
+            }
+            run_iterations(h, mixed, k, st);
             HIPCHECK(hipStreamSynchronize(st));
-            ++it;
-            rel = *h->host_scalar / bnorm;
-            if (std::isnan(rel)) { result = MG_ERR_DIVERGED; break; }
-            grow = rel > prev ? grow + 1 : 0;
-            if (grow >= 3) { result = MG_ERR_DIVERGED; break; }
-            prev = rel;
+            for (int i = 0; i < k && !stop; ++i) {
+                ++it;
+                rel = h->host_scalar[i] / bnorm;
+                if (std::isnan(rel)) { result = MG_ERR_DIVERGED; stop = true; break; }
+                grow = rel > prev ? grow + 1 : 0;
+                if (grow >= 3) { result = MG_ERR_DIVERGED; stop = true; break; }
+                if (prev > 0.0) {
+                    const double q = rel / prev;
+                    rmin = nratio == 0 ? q : std::min(rmin, q);
+                    ++nratio;
+                }
+                prev = rel;
+            }
         }
         HIPCHECK(hipMemcpyAsync(u_dev, D.u64[mixed ? h->upar : 0], D.ncells * 8, hipMemcpyDeviceToDevice, st));
         launch_zero_inactive(D.ncells, D.mask, u_dev, st);
@@ -977,10 +1009,11 @@ mg_status mg_kernel_timing(mg_handle h, int enable, int *launches, double *avg_m
 mg_status mg_destroy(mg_handle h) {
     if (!h) return MG_OK;
     for (auto &e : h->ev) (void)hipEventDestroy(e);
-    for (int p = 0; p < 3; ++p) {
-        if (h->iter_exec[p]) (void)hipGraphExecDestroy(h->iter_exec[p]);
-        if (h->iter_graph[p]) (void)hipGraphDestroy(h->iter_graph[p]);
-    }
+    for (int p = 0; p < 3; ++p)
+        for (int c = 0; c < 4; ++c) {
+            if (h->iter_exec[p][c]) (void)hipGraphExecDestroy(h->iter_exec[p][c]);
+            if (h->iter_graph[p][c]) (void)hipGraphDestroy(h->iter_graph[p][c]);
+        }
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     for (void *p : h->allocs) (void)hipFree(p);
     if (h->host_scalar) (void)hipHostFree(h->host_scalar);

@@ -126,6 +126,7 @@ __device__ __forceinline__ T sfv_global(const LevelArgs &L, const T *__restrict_
 }
 
 constexpr int TX = 64, TY = 32, HX = TX + 4, HY = TY + 4, NT = 256;
+static_assert(PLG_SLICE <= NT, "launch B holds one segment row per thread");
 
 // Loads the (TY+4) x (TX+4) tile with halo into LDS from in-box values
 // at(i, j); halo positions outside the box get ghost values.  A block at the
@@ -134,46 +135,47 @@ constexpr int TX = 64, TY = 32, HX = TX + 4, HY = TY + 4, NT = 256;
 // LDS when the 4 cells inward from each edge it touches lie in the tile
 // (always so when at least 2 cells of the box remain in the last tile), else
 // from the accessor.  gws: 32 doubles of LDS for the weights.
-template <typename T, typename At>
+template <typename T, typename At, int TYv = TY>
 __device__ __forceinline__ void load_tile(T (*s)[HX], double *gws, const At &at, const LevelArgs &L, int i0, int j0) {
-    const bool edge = i0 < 2 || j0 < 2 || i0 + TX + 2 > L.nx || j0 + TY + 2 > L.ny;
+    constexpr int HYv = TYv + 4;
+    const bool edge = i0 < 2 || j0 < 2 || i0 + TX + 2 > L.nx || j0 + TYv + 2 > L.ny;
     if (edge && threadIdx.x < 32) {
         const int side = threadIdx.x >> 3, d = (threadIdx.x >> 2) & 1, k = threadIdx.x & 3;
         gws[threadIdx.x] = c_gw[side_bc(L, side)][d][k];
     }
     // all global loads of a thread are issued before any LDS store
-    constexpr int NL = (HX * HY + NT - 1) / NT;
+    constexpr int NL = (HX * HYv + NT - 1) / NT;
     T v[NL];
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
         const int t = threadIdx.x + k * NT;
         const int ly = t / HX, lx = t - ly * HX;
         const int qi = i0 - 2 + lx, qj = j0 - 2 + ly;
-        v[k] = (t < HX * HY && qi >= 0 && qi < L.nx && qj >= 0 && qj < L.ny) ? at(qi, qj) : (T)0;
+        v[k] = (t < HX * HYv && qi >= 0 && qi < L.nx && qj >= 0 && qj < L.ny) ? at(qi, qj) : (T)0;
     }
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
         const int t = threadIdx.x + k * NT;
-        if (t < HX * HY) s[t / HX][t % HX] = v[k];
+        if (t < HX * HYv) s[t / HX][t % HX] = v[k];
     }
     if (!edge) return;
     // the tile holds cells [i0 - 2, i0 + TX + 2) x [j0 - 2, j0 + TY + 2)
-    const bool lds_ok = (i0 + TX + 2 <= L.nx || L.nx - 4 >= i0 - 2) && (j0 + TY + 2 <= L.ny || L.ny - 4 >= j0 - 2);
+    const bool lds_ok = (i0 + TX + 2 <= L.nx || L.nx - 4 >= i0 - 2) && (j0 + TYv + 2 <= L.ny || L.ny - 4 >= j0 - 2);
     auto lat = [&](int i, int j) { return s[j - j0 + 2][i - i0 + 2]; };
     const GhostWLds W{gws};
     __syncthreads();
     // the ghost band: columns -2, -1, nx, nx+1 over rows -2 .. ny+1, then
     // rows -2, -1, ny, ny+1 over columns 0 .. nx-1; positions outside the
     // tile are skipped
-    constexpr int NV = 2 * (HY), NH = 2 * (HX);
+    constexpr int NV = 2 * (HYv), NH = 2 * (HX);
     for (int t = threadIdx.x; t < 2 * NV + 2 * NH; t += NT) {
         int qi, qj;
         bool ok;
         if (t < 2 * NV) {
             const int band = t / NV, r = t - band * NV;          // band 0 left, 1 right
-            const int c = r / HY;
+            const int c = r / HYv;
             qi = band == 0 ? -2 + c : L.nx + c;
-            qj = j0 - 2 + (r - c * HY);
+            qj = j0 - 2 + (r - c * HYv);
             ok = qj >= -2 && qj < L.ny + 2;
         } else {
             const int t2 = t - 2 * NV;
@@ -184,7 +186,7 @@ __device__ __forceinline__ void load_tile(T (*s)[HX], double *gws, const At &at,
             ok = qi >= 0 && qi < L.nx;
         }
         const int lx = qi - i0 + 2, ly = qj - j0 + 2;
-        if (ok && lx >= 0 && lx < HX && ly >= 0 && ly < HY)
+        if (ok && lx >= 0 && lx < HX && ly >= 0 && ly < HYv)
             s[ly][lx] = lds_ok ? ghost_at<T>(lat, W, L, qi, qj) : ghost_at<T>(at, W, L, qi, qj);
     }
 }
@@ -252,21 +254,21 @@ __device__ __forceinline__ void wave_rows8(const T *__restrict__ A, int lda, int
     for (int k = 0; k < 8; ++k) out[k] = wave_sum(acc[k]);
 }
 
-// steps per pass of wave_rows8: rows of up to PLG_LMAX columns in one pass
+// steps per pass of wave_rows8 (16-byte loads in flight per lane and row)
 template <typename T>
 constexpr int rows_unroll() {
-    return (PLG_LMAX + 64 * Vec16<T>::N - 1) / (64 * Vec16<T>::N);
+    return 2;
 }
 
 // ---------------------------------------------------------------------------
 // Launch A, tile role: weighted Jacobi on the SFV cells, eq. (5.5),
 // D = -5(a+c)/(2h^2).  uzero: the old iterate is zero (first sweep of a
 // residual equation), so it is not read.
-template <typename T, bool MIXED>
+template <typename T, bool MIXED, int TYv>
 __device__ __forceinline__ void jacobi_tile(const LevelArgs &L, const T *__restrict__ uold, const T *__restrict__ b,
                                             T *__restrict__ unew, const uint8_t *__restrict__ mask, bool uzero,
                                             int i0, int j0, T (*s)[HX], double *gws) {
-    constexpr int R = TY / (NT / TX);            // rows per thread
+    constexpr int R = TYv / (NT / TX);           // rows per thread
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     const int i = i0 + tx;
     // the per-cell loads are issued before the tile barrier so that their
@@ -288,7 +290,8 @@ __device__ __forceinline__ void jacobi_tile(const LevelArgs &L, const T *__restr
             if (mk[k] == 1) unew[pidx(L, i, j0 + ty + k * (NT / TX))] = wod * bv[k];
         return;
     }
-    load_tile<T>(s, gws, [&](int a, int c) { return uold[pidx(L, a, c)]; }, L, i0, j0);
+    auto uat = [&](int a, int c) { return uold[pidx(L, a, c)]; };
+    load_tile<T, decltype(uat), TYv>(s, gws, uat, L, i0, j0);
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < R; ++k) {
@@ -307,13 +310,12 @@ __device__ __forceinline__ void jacobi_tile(const LevelArgs &L, const T *__restr
 template <typename T, bool MIXED>
 __device__ __forceinline__ void plg_group(const LevelArgs &L, const T *__restrict__ uold, const T *__restrict__ b,
                                           T *__restrict__ unew, bool uzero, const PlgDev<T> &P, int bi, T *lds) {
-    const int4 bk = P.blk1[bi];
-    const int g = bk.x, r0 = bk.y, r1 = bk.z;
-    const int gs = P.grp_start[g], n = P.grp_start[g + 1] - gs;
-    const int h0 = P.hptr[g], nh = P.hptr[g + 1] - h0;
-    T *hv = lds, *tt = lds + PLG_HMAX, *yy = tt + PLG_LMAX;
+    const PlgBlkA bk = P.blk1[bi];
+    const int g = bk.g, r0 = bk.r0, r1 = bk.r1, gs = bk.gs, n = bk.n;
+    T *hv = lds, *tt = lds + PLG_HMAX, *yy = tt + PLG_LMAX;     // yy: PLG_SLICE rows
     const T wod = (T)L.omega_over_d;
-    // b2 of this thread's rows, loaded before the gather
+    // b2 of this thread's rows and this block's entries of A_SB, loaded
+    // before the gather
     constexpr int RPT = (PLG_LMAX + NT - 1) / NT;
     T brow[RPT];
 #pragma unroll
@@ -321,9 +323,17 @@ __device__ __forceinline__ void plg_group(const LevelArgs &L, const T *__restric
         const int q = threadIdx.x + k * NT;
         brow[k] = q < n ? b[P.cell[gs + q]] : (T)0;
     }
+    const int ce = bk.ce0 + threadIdx.x;
+    int ce_row = -1, ce_slot = 0;
+    T ce_val = 0;
+    if (ce < bk.ce1) {
+        ce_row = P.ce_row[ce];
+        ce_slot = P.ce_slot[ce];
+        ce_val = P.ce_val[ce];
+    }
     // u1 after the Jacobi sweep on the SFV cells the group couples to
-    for (int k = threadIdx.x; k < nh; k += NT) {
-        const int id = P.hcell[h0 + k];
+    for (int k = threadIdx.x; k < bk.nh; k += NT) {
+        const int id = P.hcell[bk.h0 + k];
         T v;
         if (uzero) {
             v = wod * b[id];
@@ -333,7 +343,7 @@ __device__ __forceinline__ void plg_group(const LevelArgs &L, const T *__restric
         }
         hv[k] = v;
     }
-    if (nh == 0 && threadIdx.x == 0) hv[0] = 0;   // target of the zero padding
+    if (bk.nh == 0 && threadIdx.x == 0) hv[0] = 0;   // target of the zero padding
     __syncthreads();
     // t = b2 - A21 u1
 #pragma unroll
@@ -355,7 +365,7 @@ __device__ __forceinline__ void plg_group(const LevelArgs &L, const T *__restric
         return;
     }
     // y = B^{-1} t on rows [r0, r1) (row stride npad)
-    const T *inv = P.inv + P.inv_off[g];
+    const T *inv = P.inv + bk.inv_off;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nr = r1 - r0, lr0 = r0 - gs;
     for (int rb = wave * 8; rb < nr; rb += 32) {
@@ -373,28 +383,38 @@ __device__ __forceinline__ void plg_group(const LevelArgs &L, const T *__restric
     }
     for (int q = threadIdx.x; q < nr; q += NT) P.y[r0 + q] = yy[q];
     // entries of A_SB y on these rows (summed per separator row in launch B)
-    for (int k = P.ce_ptr[g] + threadIdx.x; k < P.ce_ptr[g + 1]; k += NT) {
+    if (ce_row >= r0 && ce_row < r1) P.contrib[ce_slot] = ce_val * yy[ce_row - r0];
+    for (int k = bk.ce0 + NT + threadIdx.x; k < bk.ce1; k += NT) {
         const int row = P.ce_row[k];
         if (row >= r0 && row < r1) P.contrib[P.ce_slot[k]] = P.ce_val[k] * yy[row - r0];
     }
 }
 
-template <typename T>
+template <typename T, int TYv>
 constexpr size_t smooth_a_lds() {
-    return sizeof(T) * ((size_t)HY * HX > (size_t)(PLG_HMAX + 2 * PLG_LMAX) ? (size_t)HY * HX
-                                                                           : (size_t)(PLG_HMAX + 2 * PLG_LMAX));
+    return sizeof(T) * ((size_t)(TYv + 4) * HX > (size_t)(PLG_HMAX + PLG_LMAX + PLG_SLICE)
+                            ? (size_t)(TYv + 4) * HX
+                            : (size_t)(PLG_HMAX + PLG_LMAX + PLG_SLICE));
 }
 
-template <typename T, bool MIXED>
+// tile heights of launch A: short tiles on small grids (more blocks, shorter
+// per-thread chains), tall tiles on large grids (less halo traffic)
+constexpr int TY_SMALL = 8;
+template <typename T>
+constexpr long long small_grid_cells() {
+    return sizeof(T) == 4 ? 512 * 512 : 256 * 256;
+}
+
+template <typename T, bool MIXED, int TYv>
 __global__ __launch_bounds__(NT) void k_smooth_a(LevelArgs L, const T *__restrict__ uold, const T *__restrict__ b,
                                                  T *__restrict__ unew, const uint8_t *__restrict__ mask, int tiles_x,
                                                  int ntile, int uzero, PlgDev<T> P) {
-    __shared__ __align__(16) unsigned char smem[smooth_a_lds<T>()];
+    __shared__ __align__(16) unsigned char smem[smooth_a_lds<T, TYv>()];
     __shared__ double gws[32];
     const int bid = blockIdx.x;
     if (bid < ntile) {
-        jacobi_tile<T, MIXED>(L, uold, b, unew, mask, uzero != 0, (bid % tiles_x) * TX, (bid / tiles_x) * TY,
-                              reinterpret_cast<T(*)[HX]>(smem), gws);
+        jacobi_tile<T, MIXED, TYv>(L, uold, b, unew, mask, uzero != 0, (bid % tiles_x) * TX, (bid / tiles_x) * TYv,
+                                   reinterpret_cast<T(*)[HX]>(smem), gws);
         return;
     }
     plg_group<T, MIXED>(L, uold, b, unew, uzero != 0, P, bid - ntile, reinterpret_cast<T *>(smem));
@@ -409,7 +429,22 @@ __global__ __launch_bounds__(NT) void k_smooth_b(PlgDev<T> P, T *__restrict__ u)
     const int ns = P.nsep, nsp = (ns + 3) & ~3;          // dense rows have stride nsp
     T *rs = reinterpret_cast<T *>(smem_raw);
     T *xk = rs + nsp;
-    const int4 bk = P.blk2[blockIdx.x];
+    const PlgBlkB bk = P.blk2[blockIdx.x];
+    const bool seprows = bk.kind == 1;
+    // segment slice: this thread's row of F_j^T and y, loaded before the
+    // separator solve (one row per thread: slices have at most NT rows)
+    constexpr int KU = 32;                               // columns of F_j held in registers
+    const int r = bk.r0 + threadIdx.x;
+    const bool myrow = !seprows && r < bk.r1;
+    T fv[KU], yr = 0;
+    int cr = 0;
+    if (myrow) {
+        const T *f = P.FT + bk.ft_off + (r - bk.s0);
+#pragma unroll
+        for (int kk = 0; kk < KU; ++kk) fv[kk] = kk < bk.kj ? f[(size_t)kk * bk.Lj] : (T)0;
+        yr = P.y[r];
+        cr = P.cell[r];
+    }
     for (int s = threadIdx.x; s < nsp; s += NT) {
         T v = 0;
         if (s < ns) {
@@ -421,11 +456,10 @@ __global__ __launch_bounds__(NT) void k_smooth_b(PlgDev<T> P, T *__restrict__ u)
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const bool seprows = bk.x == 1;
     // dense rows times r_S: rows of S'^{-1} (separator block), or the rows
     // of S'^{-1} at the segment's separator columns
-    const T *A = seprows ? P.sinv + (size_t)bk.z * nsp : P.SJ + P.sj_off[bk.y];
-    const int nr = seprows ? bk.w - bk.z : P.fcols_ptr[bk.y + 1] - P.fcols_ptr[bk.y];
+    const T *A = seprows ? P.sinv + (size_t)bk.r0 * nsp : P.SJ + bk.sj_off;
+    const int nr = seprows ? bk.r1 - bk.r0 : bk.kj;
     for (int rb = wave * 8; rb < nr; rb += 32) {
         T out[8];
         wave_rows8<T, rows_unroll<T>()>(A + (size_t)rb * nsp, nsp, min(8, nr - rb), rs, lane, out);
@@ -433,32 +467,25 @@ __global__ __launch_bounds__(NT) void k_smooth_b(PlgDev<T> P, T *__restrict__ u)
 #pragma unroll
             for (int k = 0; k < 8; ++k)
                 if (rb + k < nr) {
-                    if (seprows) u[P.cell[P.sep_begin + bk.z + rb + k]] = out[k];
+                    if (seprows) u[P.cell[P.sep_begin + bk.r0 + rb + k]] = out[k];
                     else xk[rb + k] = out[k];
                 }
     }
     if (seprows) return;
     __syncthreads();
-    const int j = bk.y, r0 = bk.z, r1 = bk.w, kj = nr;
-    const int s0 = P.seg_start[j], Lj = P.seg_start[j + 1] - s0;
-    const T *FT = P.FT + P.ft_off[j];
-    constexpr int KU = 32;                               // columns of F_j unrolled
-    for (int r = r0 + threadIdx.x; r < r1; r += NT) {
-        const T *f = FT + (r - s0);
-        T fv[KU];
+    if (!myrow) return;
+    const int kj = bk.kj;
+    T v0 = 0, v1 = 0, v2 = 0, v3 = 0;
 #pragma unroll
-        for (int kk = 0; kk < KU; ++kk) fv[kk] = kk < kj ? f[(size_t)kk * Lj] : (T)0;
-        T v0 = 0, v1 = 0, v2 = 0, v3 = 0;
-#pragma unroll
-        for (int kk = 0; kk < KU; kk += 4) {
-            if (kk < kj) v0 += fv[kk] * xk[kk];
-            if (kk + 1 < kj) v1 += fv[kk + 1] * xk[kk + 1];
-            if (kk + 2 < kj) v2 += fv[kk + 2] * xk[kk + 2];
-            if (kk + 3 < kj) v3 += fv[kk + 3] * xk[kk + 3];
-        }
-        for (int kk = KU; kk < kj; ++kk) v0 += f[(size_t)kk * Lj] * xk[kk];
-        u[P.cell[r]] = P.y[r] - ((v0 + v1) + (v2 + v3));
+    for (int kk = 0; kk < KU; kk += 4) {
+        if (kk < kj) v0 += fv[kk] * xk[kk];
+        if (kk + 1 < kj) v1 += fv[kk + 1] * xk[kk + 1];
+        if (kk + 2 < kj) v2 += fv[kk + 2] * xk[kk + 2];
+        if (kk + 3 < kj) v3 += fv[kk + 3] * xk[kk + 3];
     }
+    const T *f = P.FT + bk.ft_off + (r - bk.s0);
+    for (int kk = KU; kk < kj; ++kk) v0 += f[(size_t)kk * bk.Lj] * xk[kk];
+    u[cr] = yr - ((v0 + v1) + (v2 + v3));
 }
 
 // ---------------------------------------------------------------------------
@@ -793,15 +820,16 @@ inline dim3 tile_grid(const LevelArgs &L) { return dim3((L.nx + TX - 1) / TX, (L
 template <typename T>
 void launch_smooth_a(const LevelArgs &L, const T *uold, const T *b, T *unew, const uint8_t *mask, bool uzero,
                      const PlgDev<T> &P, hipStream_t st) {
-    const dim3 tg = tile_grid(L);
-    const int ntile = (int)(tg.x * tg.y);
+    const bool small = (long long)L.nx * L.ny <= small_grid_cells<T>();
+    const int ty = small ? TY_SMALL : TY;
+    const int tiles_x = (L.nx + TX - 1) / TX, ntile = tiles_x * ((L.ny + ty - 1) / ty);
     const dim3 grid(ntile + P.nblk1);
-    if (L.mixed)
-        hipLaunchKernelGGL((k_smooth_a<T, true>), grid, dim3(NT), 0, st, L, uold, b, unew, mask, (int)tg.x, ntile,
-                           uzero ? 1 : 0, P);
-    else
-        hipLaunchKernelGGL((k_smooth_a<T, false>), grid, dim3(NT), 0, st, L, uold, b, unew, mask, (int)tg.x, ntile,
-                           uzero ? 1 : 0, P);
+    const int uz = uzero ? 1 : 0;
+#define MG_SA(MX, TYV) \
+    hipLaunchKernelGGL((k_smooth_a<T, MX, TYV>), grid, dim3(NT), 0, st, L, uold, b, unew, mask, tiles_x, ntile, uz, P)
+    if (L.mixed) { if (small) MG_SA(true, TY_SMALL); else MG_SA(true, TY); }
+    else { if (small) MG_SA(false, TY_SMALL); else MG_SA(false, TY); }
+#undef MG_SA
 }
 
 template <typename T>
@@ -822,7 +850,6 @@ void launch_fill_zero(size_t n, T *u, hipStream_t st) {
     hipLaunchKernelGGL((k_fill_zero<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, u);
 }
 
-size_t smooth_lds_bytes(bool fp64) { return fp64 ? smooth_a_lds<double>() : smooth_a_lds<float>(); }
 
 template <typename T>
 void launch_plg_residual(int m, const int *cell, const int *ptr, const int *col, const T *val, const T *b,

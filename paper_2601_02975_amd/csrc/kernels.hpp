@@ -26,6 +26,24 @@ struct LevelArgs {
     int mixed;                  // b != 0
 };
 
+// Launch A PLG block: rows [r0, r1) of group g (rows [gs, gs + n) in solve
+// order, SFV couplings H = hcell[h0, h0 + nh)); segment groups also carry
+// their inverse and their entries of A_SB [ce0, ce1).
+struct alignas(16) PlgBlkA {
+    int g, r0, r1, gs;
+    int n, h0, nh, ce0;
+    int ce1, pad0;
+    long long inv_off;
+};
+
+// Launch B block: kind 0, rows [r0, r1) of segment j (rows [s0, s0 + Lj),
+// k_j separator columns); kind 1, separator rows [r0, r1).
+struct alignas(16) PlgBlkB {
+    int kind, j, r0, r1;
+    int kj, s0, Lj, pad0;
+    long long sj_off, ft_off;
+};
+
 // PLG block solve data of one level (device pointers).  Rows are numbered
 // in solve order: the segments (consecutive runs), then the separators.
 // Row-wise sparse data have a fixed width of ELL_W entries (zero padding).
@@ -39,7 +57,7 @@ struct PlgDev {
     const int *a21_loc = nullptr;       // [m * ELL_W] index into the group's H
     const T *a21_val = nullptr;
     int nblk1 = 0;
-    const int4 *blk1 = nullptr;         // (group, r0, r1, -)
+    const PlgBlkA *blk1 = nullptr;
     // segments
     const int *seg_start = nullptr;     // [nseg + 1]
     const long long *inv_off = nullptr; // row-major segment inverses
@@ -48,7 +66,7 @@ struct PlgDev {
     const T *ce_val = nullptr;
     // separators (launch B)
     int nblk2 = 0;
-    const int4 *blk2 = nullptr;         // (0 segment slice | 1 separator rows, j, r0, r1)
+    const PlgBlkB *blk2 = nullptr;
     const long long *ft_off = nullptr;  // F_j^T = (B_j^{-1} A_{j,S})^T, row-major k_j x L_j
     const T *FT = nullptr;
     const int *fcols_ptr = nullptr;     // k_j = fcols_ptr[j + 1] - fcols_ptr[j]
@@ -64,7 +82,7 @@ constexpr int ELL_W = 16;               // width of the row-wise sparse data
 
 // Limits of the LDS staging (checked at setup).
 constexpr int PLG_HMAX = 1536;          // SFV cells coupled to one group
-constexpr int PLG_LMAX = 320;           // rows of one group (segments reach 1.25x the nominal 256)
+constexpr int PLG_LMAX = 768;           // rows of one group
 constexpr int PLG_KMAX = 256;           // separator columns of one segment
 constexpr int PLG_SMAX = 4096;          // separator rows of one level
 constexpr int PLG_SLICE = 32;           // segment rows per block

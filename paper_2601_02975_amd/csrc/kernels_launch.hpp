@@ -19,7 +19,6 @@ template <typename T>
 void launch_smooth_b(const PlgDev<T> &P, T *unew, hipStream_t st);
 template <typename T>
 void launch_fill_zero(size_t n, T *u, hipStream_t st);
-size_t smooth_lds_bytes(bool fp64);
 template <typename T>
 void launch_plg_residual(int m, const int *cell, const int *ptr, const int *col, const T *val, const T *b,
                          const T *u, T *r, hipStream_t st);

@@ -359,18 +359,20 @@ void build_plg_plan(const Level &L, const PlgSolver &S, int nx, int slice, int s
             for (int c = 0; c < Lj; ++c)
                 P.INV[P.inv_off[j] + (size_t)r * Lp + c] = S.inv[S.inv_off[j] + (size_t)r * Lj + c];
     }
-    // launch A blocks: segment slices, then one block per separator group
+    // launch A blocks (the A_SB ranges are filled in below)
     for (int g = 0; g < P.ngroup; ++g) {
         const int g0 = P.grp_start[g], g1 = P.grp_start[g + 1];
         const int step = g < S.nseg ? slice : g1 - g0;
-        for (int r = g0; r < g1; r += step) P.blk1.insert(P.blk1.end(), {g, r, std::min(g1, r + step), 0});
+        for (int r = g0; r < g1; r += step) {
+            PlgBlkA b{};
+            b.g = g; b.r0 = r; b.r1 = std::min(g1, r + step); b.gs = g0; b.n = g1 - g0;
+            b.h0 = P.hptr[g]; b.nh = P.hptr[g + 1] - P.hptr[g];
+            b.inv_off = g < S.nseg ? P.inv_off[g] : 0;
+            P.blk1.push_back(b);
+        }
     }
     if (S.nsep == 0) return;
-    // launch B blocks: the same segment slices, then separator rows in runs
-    for (int j = 0; j < S.nseg; ++j)
-        for (int r = S.seg_start[j]; r < S.seg_start[j + 1]; r += slice)
-            P.blk2.insert(P.blk2.end(), {0, j, r, std::min(S.seg_start[j + 1], r + slice)});
-    for (int s = 0; s < S.nsep; s += sep_rows) P.blk2.insert(P.blk2.end(), {1, 0, s, std::min(S.nsep, s + sep_rows)});
+
     // A_SB entries owned by each segment, in ELL slots of the separator rows
     std::vector<int> seg_of(S.sep_begin);
     for (int j = 0, q = 0; q < S.sep_begin; ++q) {
@@ -413,6 +415,25 @@ void build_plg_plan(const Level &L, const PlgSolver &S, int nx, int slice, int s
             P.SJ.insert(P.SJ.end(), P.SINV.begin() + (size_t)row * nsp, P.SINV.begin() + (size_t)(row + 1) * nsp);
         }
         P.kmax = std::max(P.kmax, k);
+    }
+    for (auto &b : P.blk1)
+        if (b.g < S.nseg) {
+            b.ce0 = P.ce_ptr[b.g];
+            b.ce1 = P.ce_ptr[b.g + 1];
+        }
+    // launch B blocks: the segment slices, then separator rows in runs
+    for (int j = 0; j < S.nseg; ++j)
+        for (int r = S.seg_start[j]; r < S.seg_start[j + 1]; r += slice) {
+            PlgBlkB b{};
+            b.kind = 0; b.j = j; b.r0 = r; b.r1 = std::min(S.seg_start[j + 1], r + slice);
+            b.kj = S.fcols_ptr[j + 1] - S.fcols_ptr[j]; b.s0 = S.seg_start[j]; b.Lj = S.seg_start[j + 1] - S.seg_start[j];
+            b.sj_off = P.sj_off[j]; b.ft_off = P.ft_off[j];
+            P.blk2.push_back(b);
+        }
+    for (int s = 0; s < S.nsep; s += sep_rows) {
+        PlgBlkB b{};
+        b.kind = 1; b.r0 = s; b.r1 = std::min(S.nsep, s + sep_rows);
+        P.blk2.push_back(b);
     }
 }
 

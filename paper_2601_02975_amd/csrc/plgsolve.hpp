@@ -43,8 +43,8 @@ struct PlgPlan {
     std::vector<int> hptr, hcell;            // H of each group: padded cell indices
     std::vector<int> a21_loc;                // [m * ELL_W] index into H of the row's group
     std::vector<double> a21_val;             // [m * ELL_W]
-    std::vector<int> blk1;                   // launch A PLG blocks: (group, r0, r1, 0)
-    std::vector<int> blk2;                   // launch B blocks: (kind 0 segment / 1 separators, j, r0, r1)
+    std::vector<PlgBlkA> blk1;               // launch A PLG blocks
+    std::vector<PlgBlkB> blk2;               // launch B blocks
     // A_SB: entry k of separator row s is slot s * ELL_W + k; per segment the
     // entries on its rows: (solve position of the row, slot, value)
     std::vector<int> ce_ptr, ce_row, ce_slot;

@@ -164,7 +164,7 @@ def test_vcycle_iterates(name):
         assert err <= 1e-11
 
 
-@pytest.mark.parametrize("name", ["disk64", "three_disks128"])
+@pytest.mark.parametrize("name", ["disk64", "three_disks128", "star128"])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_solve_matches_oracle(name, precision):
     """mg_solve to 1e-10 (FP64, and FP32 V-cycles in FP64 defect correction)
@@ -216,7 +216,7 @@ def test_mixed_step_is_fp32_accurate(name):
     assert 1e-12 < d < 1e-4
 
 
-@pytest.mark.parametrize("name", ["disk64", "three_disks128"])
+@pytest.mark.parametrize("name", ["disk64", "three_disks128", "star128"])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_graph_replays_match_eager(name, precision):
     """The captured outer iteration (HIP graph) gives bitwise the same
