@@ -95,6 +95,66 @@ def cpu_baseline(P, gpu_iters, sample_cycles):
                       "not included" % (sample_cycles, t_cycle, gpu_iters, t_setup)}
 
 
+def serving_leg(torch, mg, W, n, n_geom, n_rhs, qps, slots, tol):
+    """Serving with resident hierarchies: n_geom three-disk geometries (seeds
+    1..n_geom) at n^2 are set up in the server by one warm-up request each;
+    then n_rhs right-hand sides per geometry arrive as a Poisson process at
+    qps and are solved in mixed precision in `slots` slots.  Reported beside
+    the same solves run one after another on resident hierarchies (mixed and
+    FP64)."""
+    import numpy as np
+    geoms = [W.three_disks_config(s, n) for s in range(1, n_geom + 1)]
+    reqs = [(k, W.with_solution(P, 1000 * k + r, 6)) for k, P in enumerate(geoms) for r in range(n_rhs)]
+    rng = np.random.default_rng(12345)
+    order = rng.permutation(len(reqs))
+    gaps = rng.exponential(1.0 / qps, size=len(reqs))
+    seq = {p: [mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=p, max_iters=1000) for P in geoms]
+           for p in (mg.FP64, mg.MIXED)}
+    inputs = []
+    for k, P in reqs:
+        f, g = seq[mg.FP64][k].project(P.solution)
+        inputs.append((torch.tensor(f, device="cuda"), torch.tensor(g, device="cuda")))
+    seq_rate = {}
+    for p, name in ((mg.FP64, "fp64"), (mg.MIXED, "mixed")):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for (k, P), (f, g) in zip(reqs, inputs):
+            u = torch.zeros_like(f)
+            seq[p][k].solve(f, g, u, tol)
+        torch.cuda.synchronize()
+        seq_rate[name] = len(reqs) / (time.perf_counter() - t0)
+        for S in seq[p]:
+            S.close()
+    srv = mg.Server(max_active=slots, hbm_budget=64 << 30)
+    pids = [srv.add_problem(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=mg.MIXED, max_iters=1000)
+            for P in geoms]
+    warm = []
+    for k in range(n_geom):                        # setup of every hierarchy (not timed)
+        f, g = inputs[k * n_rhs]
+        warm.append(srv.submit(pids[k], f, g, torch.zeros_like(f), tol))
+    setup_lat = [srv.wait(t)["latency_s"] for t in warm]
+    outs = [torch.zeros_like(inputs[i][0]) for i in range(len(reqs))]
+    torch.cuda.synchronize()
+    tickets = []
+    t_start = time.perf_counter()
+    for i, gap in zip(order, gaps):
+        time.sleep(float(gap))
+        f, g = inputs[i]
+        tickets.append(srv.submit(pids[reqs[i][0]], f, g, outs[i], tol))
+    res = [srv.wait(t) for t in tickets]
+    t_all = time.perf_counter() - t_start
+    srv.close()
+    lat = sorted(r["latency_s"] for r in res)
+    pct = lambda q: lat[min(len(lat) - 1, int(math.ceil(q * len(lat))) - 1)]
+    return {"workload": "%d three-disk geometries (seeds 1-%d) at %d^2, resident after one warm-up request each; "
+                        "%d right-hand sides per geometry arriving as a Poisson process at %g/s; %d slots; mixed "
+                        "precision to %g" % (n_geom, n_geom, n, n_rhs, qps, slots, tol),
+            "requests": len(reqs), "failed": sum(r["status"] != 0 for r in res),
+            "p50_latency_s": pct(0.50), "p99_latency_s": pct(0.99), "solves_per_s": len(reqs) / t_all,
+            "sequential_mixed_solves_per_s": seq_rate["mixed"], "sequential_fp64_solves_per_s": seq_rate["fp64"],
+            "setup_latency_s_max": max(setup_lat)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +164,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--cpu-cycles", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -175,6 +236,11 @@ def main():
                      "launches_timed": nl, "avg_launch_ms": avg_ms,
                      "algorithmic_bytes_per_launch": alg_bytes},
     }
+    if not args.no_serving:
+        out["serving"] = serving_leg(torch, mg, W, 512, 4, 8, 400.0, 4, args.tol)
+        print("serving: p50 %.3f s, p99 %.3f s, %.1f solves/s" % (
+            out["serving"]["p50_latency_s"], out["serving"]["p99_latency_s"], out["serving"]["solves_per_s"]),
+            file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(P, it64[-1], args.cpu_cycles)
     print(json.dumps(out))

@@ -180,6 +180,66 @@ const char *mg_error_string(mg_status s);
  * 8192 launches are recorded. */
 mg_status mg_kernel_timing(mg_handle h, int enable, int *launches, double *avg_ms);
 
+/* ---------------------------------------------------------------------------
+ * Solve server (an extension; the paper has no serving layer).
+ *
+ * A persistent loop on one device that admits solve requests continuously:
+ * requests wait in arrival order and are started as soon as one of
+ * max_active slots is free, the request's problem is not already being
+ * solved, and the problem's hierarchy fits in the device-memory budget
+ * (hierarchies stay resident between requests; idle ones are evicted least
+ * recently used first when a new one would exceed the budget).  Each slot
+ * runs its solves on its own non-blocking HIP stream, so solves of different
+ * requests overlap on the device.  The solve of a request is exactly
+ * mg_solve on the problem's hierarchy: its result does not depend on what
+ * else runs.
+ *
+ * A problem is the data of mg_setup (copied; its setup runs in a slot at
+ * the first request).  Requests pass device pointers f_dev, g_dev, u_dev in
+ * the layouts of mg_solve; they must stay valid, and must not be touched by
+ * the caller, until the request is done.  u_dev holds the initial guess.
+ * Calls are thread-safe.
+ */
+typedef struct mg_server_s *mg_server;
+
+typedef struct {
+    int max_active;            /* slots: solves in flight at once (>= 1) */
+    long long hbm_budget;      /* device bytes the resident hierarchies may hold */
+} mg_server_options;
+
+typedef struct {
+    long long submitted, completed, failed;
+    double p50_latency_s, p99_latency_s;    /* submit -> done, completed requests */
+    double p50_solve_s, p99_solve_s;        /* start -> done (setup of a new problem included) */
+    double solves_per_s;                    /* completed / (last done - first submit) */
+    long long resident_bytes;               /* device bytes of resident hierarchies */
+    int resident_problems, evictions;
+} mg_server_stats;
+
+/* Starts the server on the calling thread's current device. */
+mg_status mg_server_create(const mg_server_options *opt, mg_server *out);
+
+/* Registers a problem (no device work yet); *problem is its id. */
+mg_status mg_server_add_problem(mg_server s, const mg_grid *grid, int n_curves, const mg_curve *curves,
+                                double a, double b, double c, const mg_options *opt, int *problem);
+
+/* Queues a solve of problem `problem` to tolerance tol; *ticket names it. */
+mg_status mg_server_submit(mg_server s, int problem, const double *f_dev, const double *g_dev, double *u_dev,
+                           double tol, unsigned long long *ticket);
+
+/* State of a request: *done = 1 once finished; then *status, *iters,
+ * *rel_residual (as mg_solve returns them) and *latency_s (submit -> done)
+ * are valid.  Any output pointer may be NULL.  wait blocks until done. */
+mg_status mg_server_poll(mg_server s, unsigned long long ticket, int *done, mg_status *status, int *iters,
+                         double *rel_residual, double *latency_s);
+mg_status mg_server_wait(mg_server s, unsigned long long ticket, mg_status *status, int *iters,
+                         double *rel_residual, double *latency_s);
+
+mg_status mg_server_get_stats(mg_server s, mg_server_stats *stats);
+
+/* Waits for all queued requests, then frees every resident hierarchy. */
+mg_status mg_server_destroy(mg_server s);
+
 /* Human-readable description of the last failure of any entry point on the
  * calling host thread ("" if none); valid until the next call. */
 const char *mg_last_error(void);

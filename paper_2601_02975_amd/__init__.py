@@ -56,6 +56,18 @@ class mg_info(ctypes.Structure):
                 ("device_bytes", ctypes.c_longlong), ("setup_seconds", ctypes.c_double)]
 
 
+class mg_server_options(ctypes.Structure):
+    _fields_ = [("max_active", ctypes.c_int), ("hbm_budget", ctypes.c_longlong)]
+
+
+class mg_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_longlong), ("completed", ctypes.c_longlong), ("failed", ctypes.c_longlong),
+                ("p50_latency_s", ctypes.c_double), ("p99_latency_s", ctypes.c_double),
+                ("p50_solve_s", ctypes.c_double), ("p99_solve_s", ctypes.c_double),
+                ("solves_per_s", ctypes.c_double), ("resident_bytes", ctypes.c_longlong),
+                ("resident_problems", ctypes.c_int), ("evictions", ctypes.c_int)]
+
+
 def load_library():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libmgcut.so is not built (run __graft_entry__.build() or "
@@ -85,6 +97,14 @@ def load_library():
         "mg_boundary_quadrature": [P, pI, pLL, pLL, pD, pD, pD, pD, pD, pI, pD, pD],
         "mg_destroy": [P],
         "mg_kernel_timing": [P, I, pI, pD],
+        "mg_server_create": [ctypes.POINTER(mg_server_options), ctypes.POINTER(P)],
+        "mg_server_add_problem": [P, ctypes.POINTER(mg_grid), I, ctypes.POINTER(mg_curve), D, D, D,
+                                  ctypes.POINTER(mg_options), pI],
+        "mg_server_submit": [P, I, P, P, P, D, ctypes.POINTER(ctypes.c_ulonglong)],
+        "mg_server_poll": [P, ctypes.c_ulonglong, pI, pI, pI, pD, pD],
+        "mg_server_wait": [P, ctypes.c_ulonglong, pI, pI, pD, pD],
+        "mg_server_get_stats": [P, ctypes.POINTER(mg_server_stats)],
+        "mg_server_destroy": [P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -133,31 +153,43 @@ def _lp(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong))
 
 
+def _curves(curves):
+    """mg_curve array for a list of curves of workloads.Segment; the segment
+    arrays are returned too (they must outlive the call)."""
+    keep = []
+    carr = (mg_curve * len(curves))()
+    for k, curve in enumerate(curves):
+        segs = (mg_segment * len(curve))()
+        for s, sg in enumerate(curve):
+            segs[s].kind = 0 if sg.kind == "line" else 1
+            for t in range(5):
+                segs[s].p[t] = float(sg.p[t]) if t < len(sg.p) else 0.0
+            segs[s].bc = BC[sg.bc]
+            segs[s].alpha1 = float(sg.alpha1)
+            segs[s].alpha2 = float(sg.alpha2)
+        keep.append(segs)
+        carr[k].n_seg = len(curve)
+        carr[k].seg = ctypes.cast(segs, ctypes.POINTER(mg_segment))
+    return carr, keep
+
+
+def _options(eps, omega, nu, n_levels, min_coarse, precision, max_iters):
+    opt = mg_options()
+    lib().mg_default_options(ctypes.byref(opt))
+    opt.eps, opt.omega, opt.nu1, opt.nu2 = eps, omega, nu[0], nu[1]
+    opt.n_levels, opt.min_coarse, opt.precision, opt.max_iters = n_levels, min_coarse, precision, max_iters
+    return opt
+
+
 class Solver:
     """A handle of the C library for one problem (grid, curves, a, b, c)."""
 
     def __init__(self, grid, curves, a, b, c, eps=0.08, omega=0.5, nu=(3, 3), n_levels=0, min_coarse=16,
                  precision=FP64, max_iters=100):
         L = lib()
-        self._segs = []
-        carr = (mg_curve * len(curves))()
-        for k, curve in enumerate(curves):
-            segs = (mg_segment * len(curve))()
-            for s, sg in enumerate(curve):
-                segs[s].kind = 0 if sg.kind == "line" else 1
-                for t in range(5):
-                    segs[s].p[t] = float(sg.p[t]) if t < len(sg.p) else 0.0
-                segs[s].bc = BC[sg.bc]
-                segs[s].alpha1 = float(sg.alpha1)
-                segs[s].alpha2 = float(sg.alpha2)
-            self._segs.append(segs)
-            carr[k].n_seg = len(curve)
-            carr[k].seg = ctypes.cast(segs, ctypes.POINTER(mg_segment))
+        carr, self._segs = _curves(curves)
         g = mg_grid(grid.x0, grid.y0, grid.h, grid.nx, grid.ny)
-        opt = mg_options()
-        L.mg_default_options(ctypes.byref(opt))
-        opt.eps, opt.omega, opt.nu1, opt.nu2 = eps, omega, nu[0], nu[1]
-        opt.n_levels, opt.min_coarse, opt.precision, opt.max_iters = n_levels, min_coarse, precision, max_iters
+        opt = _options(eps, omega, nu, n_levels, min_coarse, precision, max_iters)
         self.grid = grid
         self.nx, self.ny = grid.nx, grid.ny
         h = ctypes.c_void_p()
@@ -307,3 +339,74 @@ def to_padded(grid_vals, nx, ny):
 
 def from_padded(p, nx, ny):
     return np.asarray(p)[2:ny + 2, 2:nx + 2]
+
+
+class Server:
+    """The library's solve server (mg_server_*): requests are admitted into
+    max_active slots as slots and the device-memory budget free up, and the
+    solves of different requests overlap on the device."""
+
+    def __init__(self, max_active=4, hbm_budget=64 << 30):
+        opt = mg_server_options(max_active, hbm_budget)
+        h = ctypes.c_void_p()
+        _check(lib().mg_server_create(ctypes.byref(opt), ctypes.byref(h)), "mg_server_create")
+        self.h = h
+        self._inflight = {}
+
+    def add_problem(self, grid, curves, a, b, c, eps=0.08, omega=0.5, nu=(3, 3), n_levels=0, min_coarse=16,
+                    precision=FP64, max_iters=100):
+        carr, keep = _curves(curves)
+        g = mg_grid(grid.x0, grid.y0, grid.h, grid.nx, grid.ny)
+        opt = _options(eps, omega, nu, n_levels, min_coarse, precision, max_iters)
+        pid = ctypes.c_int()
+        _check(lib().mg_server_add_problem(self.h, ctypes.byref(g), len(curves), carr, a, b, c, ctypes.byref(opt),
+                                           ctypes.byref(pid)), "mg_server_add_problem")
+        return pid.value
+
+    def submit(self, problem, f, g, u, tol):
+        """Queues a solve; f, g, u are device tensors in the layouts of
+        Solver.solve (u: initial guess, overwritten by the solution).  The
+        caller's stream is synchronised first: the server runs on its own
+        streams."""
+        import torch
+        torch.cuda.current_stream().synchronize()
+        t = ctypes.c_ulonglong()
+        _check(lib().mg_server_submit(self.h, problem, _ptr(f), _ptr(g), _ptr(u), tol, ctypes.byref(t)),
+               "mg_server_submit")
+        self._inflight[t.value] = (f, g, u)
+        return t.value
+
+    def _result(self, ticket, st, it, rel, lat):
+        self._inflight.pop(ticket, None)
+        return {"status": st.value, "iters": it.value, "rel_residual": rel.value, "latency_s": lat.value}
+
+    def poll(self, ticket):
+        done, st, it = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        rel, lat = ctypes.c_double(), ctypes.c_double()
+        _check(lib().mg_server_poll(self.h, ticket, ctypes.byref(done), ctypes.byref(st), ctypes.byref(it),
+                                    ctypes.byref(rel), ctypes.byref(lat)), "mg_server_poll")
+        return self._result(ticket, st, it, rel, lat) if done.value else None
+
+    def wait(self, ticket):
+        st, it = ctypes.c_int(), ctypes.c_int()
+        rel, lat = ctypes.c_double(), ctypes.c_double()
+        _check(lib().mg_server_wait(self.h, ticket, ctypes.byref(st), ctypes.byref(it), ctypes.byref(rel),
+                                    ctypes.byref(lat)), "mg_server_wait")
+        return self._result(ticket, st, it, rel, lat)
+
+    def stats(self):
+        s = mg_server_stats()
+        _check(lib().mg_server_get_stats(self.h, ctypes.byref(s)), "mg_server_get_stats")
+        return {k: getattr(s, k) for k, _ in mg_server_stats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mg_server_destroy(self.h)
+            self.h = None
+            self._inflight.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

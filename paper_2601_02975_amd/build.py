@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmgcut.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["geometry.cpp", "discretize.cpp", "plgsolve.cpp", "api.cpp", "kernels.hip"]
+SOURCES = ["geometry.cpp", "discretize.cpp", "plgsolve.cpp", "api.cpp", "server.cpp", "kernels.hip"]
 COMMON = ["-std=c++17", "-O3", "-fPIC", "-fopenmp", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 # device code: gfx950 only; the packed-FP32 instructions are disabled
 DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -11,6 +11,7 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <mutex>
 
 #include "kernels_launch.hpp"
 #include "level.hpp"
@@ -179,9 +180,10 @@ void fit_level(mg_handle h, Level &L, hipStream_t st) {
 }
 
 // dense inverse of a row-major n x n matrix on the GPU (rocSOLVER)
-std::vector<double> gpu_inverse(int n, const std::vector<double> &A) {
+std::vector<double> gpu_inverse(int n, const std::vector<double> &A, hipStream_t st) {
     rocblas_handle rb;
     if (rocblas_create_handle(&rb) != rocblas_status_success) fail(MG_ERR_HIP, "rocblas_create_handle failed");
+    rocblas_set_stream(rb, st);
     double *dA;
     rocblas_int *ipiv, *info;
     HIPCHECK(hipMalloc(&dA, (size_t)n * n * 8));
@@ -192,6 +194,7 @@ std::vector<double> gpu_inverse(int n, const std::vector<double> &A) {
     // of the transpose is the transpose of the inverse, so the result read
     // back row-major is A^{-1}
     rocsolver_dgetrf(rb, n, n, dA, n, ipiv, info);
+    HIPCHECK(hipStreamSynchronize(st));
     rocblas_int hinfo = 0;
     HIPCHECK(hipMemcpy(&hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost));
     if (hinfo != 0) {
@@ -201,7 +204,7 @@ std::vector<double> gpu_inverse(int n, const std::vector<double> &A) {
     }
     rocsolver_dgetri(rb, n, dA, n, ipiv, info);
     std::vector<double> out((size_t)n * n);
-    HIPCHECK(hipDeviceSynchronize());
+    HIPCHECK(hipStreamSynchronize(st));
     HIPCHECK(hipMemcpy(out.data(), dA, (size_t)n * n * 8, hipMemcpyDeviceToHost));
     (void)hipFree(dA); (void)hipFree(ipiv); (void)hipFree(info);
     rocblas_destroy_handle(rb);
@@ -367,7 +370,7 @@ void upload_level(mg_handle h, int l, bool last, hipStream_t st) {
                 for (int e = L.row_ptr[pr]; e < L.row_ptr[pr + 1]; ++e) A[(size_t)r * n + pos[L.col[e]]] += L.val[e];
             }
         }
-        std::vector<double> inv = gpu_inverse(n, A);
+        std::vector<double> inv = gpu_inverse(n, A, st);
         std::vector<int> bc(n);
         for (int r = 0; r < n; ++r) bc[r] = (int)padded_index(nx, act[r]);
         D.nbot = n;
@@ -563,6 +566,15 @@ mg_status guard(mg_handle h, const std::function<void()> &fn) {
     }
 }
 
+void build_ghost_table();
+
+// the ghost weights are the same for every handle: uploaded once per device
+void build_ghost_table_once(int device) {
+    static std::once_flag once[64];
+    if (device < 0 || device >= 64) fail(MG_ERR_INVALID_ARG, "device index out of range");
+    std::call_once(once[device], [] { build_ghost_table(); });
+}
+
 void build_ghost_table() {
     double gw[2][2][4];
     for (int bc = 0; bc < 2; ++bc)
@@ -637,7 +649,7 @@ mg_status mg_setup(const mg_grid *grid, int n_curves, const mg_curve *curves, do
             }
             h->curves.c.push_back(segs);
         }
-        build_ghost_table();
+        build_ghost_table_once(h->device);
         mg_grid g = *grid;
         while (true) {
             auto L = std::make_unique<Level>();
@@ -680,7 +692,7 @@ mg_status mg_setup(const mg_grid *grid, int n_curves, const mg_curve *curves, do
         h->npartial = std::max(maxblk, 1024) + 1;
         h->partial = h->alloc<double>(h->npartial);
         HIPCHECK(hipHostMalloc((void **)&h->host_scalar, sizeof(double) * ITER_CHUNK));
-        HIPCHECK(hipDeviceSynchronize());
+        HIPCHECK(hipStreamSynchronize(st));
         h->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     });
     if (rc != MG_OK) {

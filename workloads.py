@@ -316,3 +316,15 @@ def with_grid(problem, n):
     L = g.h * g.nx
     return Problem(problem.name, Grid(g.x0, g.y0, L / n, n, n), problem.curves, problem.a,
                    problem.b, problem.c, problem.solution, problem.eps, dict(problem.meta))
+
+
+def with_solution(problem, seed, count=6):
+    """The same geometry and operator with another seeded sine-mode solution
+    (another right-hand side)."""
+    rng = np.random.default_rng([int(seed), 7919])
+    modes = _modes(rng, count)
+    meta = dict(problem.meta)
+    meta["modes"] = modes
+    return Problem(problem.name, problem.grid, problem.curves, problem.a, problem.b, problem.c,
+                   SineModes(modes, problem.a, problem.b, problem.c), problem.eps, meta)
+
