@@ -78,6 +78,10 @@ typedef struct { double x0, y0, h; int nx, ny; } mg_grid;
 
 typedef enum { MG_FP64 = 0, MG_MIXED = 1 } mg_precision;
 
+/* Outer iteration of mg_solve: V-cycles (Algorithm 3), or FMG cycles
+ * (Algorithm 4) on the residual equation, u <- u + FMG(b - A u) (Sec. 5.4). */
+typedef enum { MG_CYCLE_V = 0, MG_CYCLE_FMG = 1 } mg_cycle;
+
 typedef struct {
     double eps;        /* volume-fraction threshold of Algorithm 1 (default 0.08) */
     double omega;      /* Jacobi weight of eq. (5.5) (default 0.5) */
@@ -86,6 +90,7 @@ typedef struct {
     int min_coarse;    /* default 16 */
     int precision;     /* mg_precision (default MG_FP64) */
     int max_iters;     /* outer iterations of mg_solve (default 100) */
+    int cycle;         /* mg_cycle (default MG_CYCLE_V) */
 } mg_options;
 
 typedef struct {
@@ -234,6 +239,10 @@ mg_status mg_server_poll(mg_server s, unsigned long long ticket, int *done, mg_s
                          double *rel_residual, double *latency_s);
 mg_status mg_server_wait(mg_server s, unsigned long long ticket, mg_status *status, int *iters,
                          double *rel_residual, double *latency_s);
+
+/* Text of the failure of a finished request ("" if it succeeded or the
+ * ticket is unknown); valid until mg_server_destroy. */
+const char *mg_server_request_error(mg_server s, unsigned long long ticket);
 
 mg_status mg_server_get_stats(mg_server s, mg_server_stats *stats);
 

@@ -21,6 +21,7 @@ STATUS = {0: "MG_OK", -1: "MG_ERR_INVALID_ARG", -2: "MG_ERR_GEOMETRY", -3: "MG_E
           -8: "MG_ERR_UNSUPPORTED"}
 BC = {"D": 0, "N": 1, "R": 2}
 FP64, MIXED = 0, 1
+CYCLE_V, CYCLE_FMG = 0, 1
 
 
 class MGError(RuntimeError):
@@ -46,7 +47,7 @@ class mg_grid(ctypes.Structure):
 class mg_options(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("omega", ctypes.c_double), ("nu1", ctypes.c_int),
                 ("nu2", ctypes.c_int), ("n_levels", ctypes.c_int), ("min_coarse", ctypes.c_int),
-                ("precision", ctypes.c_int), ("max_iters", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("max_iters", ctypes.c_int), ("cycle", ctypes.c_int)]
 
 
 class mg_info(ctypes.Structure):
@@ -114,6 +115,8 @@ def load_library():
     lib.mg_error_string.restype = ctypes.c_char_p
     lib.mg_last_error.argtypes = []
     lib.mg_last_error.restype = ctypes.c_char_p
+    lib.mg_server_request_error.argtypes = [P, ctypes.c_ulonglong]
+    lib.mg_server_request_error.restype = ctypes.c_char_p
     return lib
 
 
@@ -173,11 +176,12 @@ def _curves(curves):
     return carr, keep
 
 
-def _options(eps, omega, nu, n_levels, min_coarse, precision, max_iters):
+def _options(eps, omega, nu, n_levels, min_coarse, precision, max_iters, cycle=0):
     opt = mg_options()
     lib().mg_default_options(ctypes.byref(opt))
     opt.eps, opt.omega, opt.nu1, opt.nu2 = eps, omega, nu[0], nu[1]
     opt.n_levels, opt.min_coarse, opt.precision, opt.max_iters = n_levels, min_coarse, precision, max_iters
+    opt.cycle = cycle
     return opt
 
 
@@ -185,11 +189,11 @@ class Solver:
     """A handle of the C library for one problem (grid, curves, a, b, c)."""
 
     def __init__(self, grid, curves, a, b, c, eps=0.08, omega=0.5, nu=(3, 3), n_levels=0, min_coarse=16,
-                 precision=FP64, max_iters=100):
+                 precision=FP64, max_iters=100, cycle=0):
         L = lib()
         carr, self._segs = _curves(curves)
         g = mg_grid(grid.x0, grid.y0, grid.h, grid.nx, grid.ny)
-        opt = _options(eps, omega, nu, n_levels, min_coarse, precision, max_iters)
+        opt = _options(eps, omega, nu, n_levels, min_coarse, precision, max_iters, cycle)
         self.grid = grid
         self.nx, self.ny = grid.nx, grid.ny
         h = ctypes.c_void_p()
@@ -378,7 +382,9 @@ class Server:
 
     def _result(self, ticket, st, it, rel, lat):
         self._inflight.pop(ticket, None)
-        return {"status": st.value, "iters": it.value, "rel_residual": rel.value, "latency_s": lat.value}
+        err = lib().mg_server_request_error(self.h, ticket).decode(errors="replace") if st.value else ""
+        return {"status": st.value, "iters": it.value, "rel_residual": rel.value, "latency_s": lat.value,
+                "error": err}
 
     def poll(self, ticket):
         done, st, it = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()

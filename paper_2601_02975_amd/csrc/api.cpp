@@ -28,6 +28,11 @@ namespace {
         if (e_ != hipSuccess) fail(MG_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// Device-wide synchronising work (allocation, frees, synchronous copies of
+// setup and destruction) must not overlap a stream capture in another
+// thread: both take this lock.
+std::mutex g_capture_mu;
+
 constexpr int SEG_MAX = 256;       // longest PLG segment (dense inverse per segment)
 constexpr int SEG_WHOLE = 768;     // a level whose hole chains fit in segments this long needs no separators
 constexpr int ITER_CHUNK = 8;      // most outer iterations per launch (chunks of 1, 2, 4, 8)
@@ -58,6 +63,8 @@ struct DevLevel {
     double *ainv = nullptr;
     int cur = 0;
     long long sweep_words = 0;    // words moved by one smoother launch A (algorithmic)
+    // finest level, FP64 FMG: residual equation right-hand side and its iterate
+    double *r64 = nullptr, *e64[2] = {nullptr, nullptr};
 };
 
 }  // namespace
@@ -73,7 +80,8 @@ struct mg_handle_s {
     int nrhs = 0;
     int *rhs_ptr = nullptr, *rhs_cell = nullptr, *rhs_gidx = nullptr;
     double *rhs_coef = nullptr;
-    double *partial = nullptr, *host_scalar = nullptr;
+    double *partial = nullptr, *host_scalar = nullptr, *host_scalar_dev = nullptr;
+    unsigned *counter = nullptr;      // zeroed word for the residual kernel's final reduction
     int npartial = 0;
     std::vector<void *> allocs;
     long long bytes = 0;
@@ -474,8 +482,31 @@ void vcycle(mg_handle h, int l, bool uzero, hipStream_t st) {
                        nu1 == 0 ? Prec<T>::u(C, 0) : nullptr, D.ex_nt, D.ex_ptr, D.ex_target, D.ex_child, st);
     vcycle<T>(h, l + 1, true, st);
     launch_prolong<T>(D.args, C.args, D.mask, C.mask, Prec<T>::u(C, C.cur), Prec<T>::u(D, D.cur), D.pex_n, D.pex_fine,
-                      D.pex_coarse, st);
+                      D.pex_coarse, false, st);
     for (int k = 0; k < h->opt.nu2; ++k) smooth<T>(h, l, false, st);
+}
+
+// Algorithm 4 on level l for the residual equation whose right-hand side is
+// the level's b: restrict b down (eq. (5.8) on b itself), solve at the
+// bottom, then on the way up start each level's V-cycle from the
+// interpolated coarse result (eq. (5.9)).  The result is u(l, cur).
+template <typename T>
+void fmg(mg_handle h, int l, hipStream_t st) {
+    DevLevel &D = h->dev[l];
+    const int last = (int)h->dev.size() - 1;
+    if (l == last) {
+        launch_bottom<T, T>(D.nbot, D.bot_cells, D.ainv, Prec<T>::b(D), Prec<T>::u(D, D.cur), st);
+        return;
+    }
+    DevLevel &C = h->dev[l + 1];
+    launch_restrict<T>(D.args, C.args, nullptr, Prec<T>::b(D), D.mask, D.plgidx, nullptr, D.rmask, Prec<T>::b(C),
+                       nullptr, D.ex_nt, D.ex_ptr, D.ex_target, D.ex_child, st);
+    C.cur = 0;
+    fmg<T>(h, l + 1, st);
+    D.cur = 0;
+    launch_prolong<T>(D.args, C.args, D.mask, C.mask, Prec<T>::u(C, C.cur), Prec<T>::u(D, 0), D.pex_n, D.pex_fine,
+                      D.pex_coarse, true, st);
+    vcycle<T>(h, l, false, st);
 }
 
 double device_absmax_finish(mg_handle h, int nblocks, hipStream_t st) {
@@ -487,54 +518,74 @@ double device_absmax_finish(mg_handle h, int nblocks, hipStream_t st) {
 
 double residual_norm(mg_handle h, int l, const double *u, const double *b, double *r64, hipStream_t st) {
     DevLevel &D = h->dev[l];
-    int nb = launch_residual_norm(D.args, u, nullptr, nullptr, b, D.mask, D.m, D.plg_cell, D.fe_col, D.fe_val,
-                                  nullptr, r64, h->partial, st);
+    int nb = launch_residual_norm(D.args, u, nullptr, false, nullptr, b, D.mask, D.m, D.plg_cell, D.fe_col, D.fe_val,
+                                  nullptr, r64, h->partial, nullptr, nullptr, st);
     return device_absmax_finish(h, nb, st);
 }
 
+// Outer iterations either update u64[0] in place (FP64 V-cycles), or are
+// in correction form (mixed precision, FMG): the cycle solves the residual
+// equation from the residual left by the previous iteration, and the next
+// residual pass adds its result e to u64[par], writing u64[1 - par].
+bool correction_form(mg_handle h) { return h->opt.precision == MG_MIXED || h->opt.cycle == MG_CYCLE_FMG; }
+
 // ||b - A u||_inf of the finest level into h->host_scalar[slot] (no
 // synchronisation); u is u64[src] (+ e, written to u64[1 - src], when e is
-// given); mixed: the residual also goes to b32 in FP32
-void enqueue_residual(mg_handle h, bool mixed, int src, const float *e, int slot, hipStream_t st) {
+// given); the residual itself goes to b32 (mixed) or r64 (FP64 FMG)
+void enqueue_residual(mg_handle h, int src, const void *e, bool e64, int slot, hipStream_t st) {
     DevLevel &D = h->dev[0];
-    int nb = launch_residual_norm(D.args, D.u64[src], e, e ? D.u64[1 - src] : nullptr, D.b64, D.mask, D.m,
-                                  D.plg_cell, D.fe_col, D.fe_val, mixed ? D.b32 : nullptr, nullptr, h->partial, st);
-    launch_absmax(nb, h->partial, nullptr, h->partial + h->npartial - 1, 1, st);
-    HIPCHECK(hipMemcpyAsync(h->host_scalar + slot, h->partial + h->npartial - 1, sizeof(double),
-                            hipMemcpyDeviceToHost, st));
+    const bool mixed = h->opt.precision == MG_MIXED;
+    const bool fmg64 = !mixed && h->opt.cycle == MG_CYCLE_FMG;
+    launch_residual_norm(D.args, D.u64[src], e, e64, e ? D.u64[1 - src] : nullptr, D.b64, D.mask, D.m, D.plg_cell,
+                         D.fe_col, D.fe_val, mixed ? D.b32 : nullptr, fmg64 ? D.r64 : nullptr, h->partial, h->counter,
+                         h->host_scalar_dev + slot, st);
 }
 
-// one outer iteration on the handle's own buffers: a V-cycle (FP64), or an
-// FP32 V-cycle from zero on the FP32 residual whose result corrects the FP64
-// iterate u64[par] into u64[1 - par] (mixed); then the residual
-void enqueue_iteration(mg_handle h, bool mixed, int par, int slot, hipStream_t st) {
+// one outer iteration on the handle's own buffers, then the residual
+void enqueue_iteration(mg_handle h, int par, int slot, hipStream_t st) {
     DevLevel &D = h->dev[0];
+    const bool mixed = h->opt.precision == MG_MIXED, fmg_cycle = h->opt.cycle == MG_CYCLE_FMG;
     D.cur = 0;
     if (mixed) {
-        vcycle<float>(h, 0, true, st);
+        if (fmg_cycle) fmg<float>(h, 0, st);
+        else vcycle<float>(h, 0, true, st);
         const float *e = D.u32[D.cur];
         D.cur = 0;
-        enqueue_residual(h, true, par, e, slot, st);
+        enqueue_residual(h, par, e, false, slot, st);
+    } else if (fmg_cycle) {
+        // the FP64 cycle runs on the residual equation's own buffers
+        std::swap(D.b64, D.r64);
+        std::swap(D.u64[0], D.e64[0]);
+        std::swap(D.u64[1], D.e64[1]);
+        fmg<double>(h, 0, st);
+        const double *e = D.u64[D.cur];
+        std::swap(D.b64, D.r64);
+        std::swap(D.u64[0], D.e64[0]);
+        std::swap(D.u64[1], D.e64[1]);
+        D.cur = 0;
+        enqueue_residual(h, par, e, true, slot, st);
     } else {
         vcycle<double>(h, 0, false, st);
         if (D.cur != 0) HIPCHECK(hipMemcpyAsync(D.u64[0], D.u64[1], D.ncells * 8, hipMemcpyDeviceToDevice, st));
         D.cur = 0;
-        enqueue_residual(h, false, 0, nullptr, slot, st);
+        enqueue_residual(h, 0, nullptr, false, slot, st);
     }
 }
 
 // k outer iterations (k = 1, 2, 4 or 8); residual norms in
 // h->host_scalar[0, k)
-void run_iterations(mg_handle h, bool mixed, int k, hipStream_t st) {
-    const int par = mixed ? h->upar : 0;
-    const int p = mixed ? 1 + par : 0, c = k == 1 ? 0 : k == 2 ? 1 : k == 4 ? 2 : 3;
+void run_iterations(mg_handle h, int k, hipStream_t st) {
+    const bool corr = correction_form(h);
+    const int par = corr ? h->upar : 0;
+    const int p = corr ? 1 + par : 0, c = k == 1 ? 0 : k == 2 ? 1 : k == 4 ? 2 : 3;
     auto enqueue = [&](hipStream_t s) {
-        for (int i = 0; i < k; ++i) enqueue_iteration(h, mixed, mixed ? (par + i) & 1 : 0, i, s);
+        for (int i = 0; i < k; ++i) enqueue_iteration(h, corr ? (par + i) & 1 : 0, i, s);
     };
     if (h->timing) {                     // eager launches (events around the sweeps)
         enqueue(st);
     } else {
         if (!h->iter_exec[p][c]) {
+            std::lock_guard<std::mutex> lk(g_capture_mu);
             if (!h->cap_stream) HIPCHECK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
             HIPCHECK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
             enqueue(h->cap_stream);
@@ -543,7 +594,7 @@ void run_iterations(mg_handle h, bool mixed, int k, hipStream_t st) {
         }
         HIPCHECK(hipGraphLaunch(h->iter_exec[p][c], st));
     }
-    if (mixed && (k & 1)) h->upar = 1 - h->upar;
+    if (corr && (k & 1)) h->upar = 1 - h->upar;
 }
 
 thread_local std::string g_last_error;
@@ -601,6 +652,7 @@ mg_status mg_default_options(mg_options *opt) {
     opt->min_coarse = 16;
     opt->precision = MG_FP64;
     opt->max_iters = 100;
+    opt->cycle = MG_CYCLE_V;
     return MG_OK;
 }
 
@@ -616,7 +668,8 @@ mg_status mg_setup(const mg_grid *grid, int n_curves, const mg_curve *curves, do
     mg_default_options(&o);
     if (opt) o = *opt;
     if (!(o.eps > 0 && o.eps < 1) || o.nu1 < 0 || o.nu2 < 0 || o.max_iters < 1 || o.min_coarse < 4 ||
-        (o.precision != MG_FP64 && o.precision != MG_MIXED) || o.n_levels < 0 || o.n_levels > 16)
+        (o.precision != MG_FP64 && o.precision != MG_MIXED) || o.n_levels < 0 || o.n_levels > 16 ||
+        (o.cycle != MG_CYCLE_V && o.cycle != MG_CYCLE_FMG))
         return MG_ERR_INVALID_ARG;
     for (int k = 0; k < n_curves; ++k) {
         if (curves[k].n_seg < 1 || !curves[k].seg) return MG_ERR_INVALID_ARG;
@@ -631,6 +684,7 @@ mg_status mg_setup(const mg_grid *grid, int n_curves, const mg_curve *curves, do
     auto h = std::make_unique<mg_handle_s>();
     hipStream_t st = (hipStream_t)stream;
     mg_status rc = guard(h.get(), [&]() {
+        std::lock_guard<std::mutex> lk(g_capture_mu);
         auto t0 = std::chrono::steady_clock::now();
         HIPCHECK(hipGetDevice(&h->device));
         h->opt = o;
@@ -686,12 +740,21 @@ mg_status mg_setup(const mg_grid *grid, int n_curves, const mg_curve *curves, do
         h->dev.resize(nl);
         for (int l = 0; l < nl; ++l) upload_level(h.get(), l, l == nl - 1, st);
         upload_rhs(h.get());
+        if (o.cycle == MG_CYCLE_FMG && o.precision == MG_FP64) {
+            DevLevel &D0 = h->dev[0];
+            D0.r64 = h->alloc<double>(D0.ncells);
+            D0.e64[0] = h->alloc<double>(D0.ncells);
+            D0.e64[1] = h->alloc<double>(D0.ncells);
+        }
         int maxblk = 1;
         for (auto &D : h->dev)
             maxblk = std::max(maxblk, ((D.args.nx + 63) / 64) * ((D.args.ny + 31) / 32) + (D.m + 255) / 256);
         h->npartial = std::max(maxblk, 1024) + 1;
         h->partial = h->alloc<double>(h->npartial);
-        HIPCHECK(hipHostMalloc((void **)&h->host_scalar, sizeof(double) * ITER_CHUNK));
+        HIPCHECK(hipHostMalloc((void **)&h->host_scalar, sizeof(double) * ITER_CHUNK,
+                               hipHostMallocMapped | hipHostMallocCoherent));
+        HIPCHECK(hipHostGetDevicePointer((void **)&h->host_scalar_dev, h->host_scalar, 0));
+        h->counter = h->alloc<unsigned>(1);
         HIPCHECK(hipStreamSynchronize(st));
         h->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     });
@@ -769,7 +832,7 @@ mg_status mg_solve(mg_handle h, const double *f_dev, const double *g_dev, double
         // so the captured iteration can be replayed)
         HIPCHECK(hipMemcpyAsync(D.u64[0], u_dev, D.ncells * 8, hipMemcpyDeviceToDevice, st));
         h->upar = 0;
-        enqueue_residual(h, mixed, 0, nullptr, 0, st);
+        enqueue_residual(h, 0, nullptr, false, 0, st);
         HIPCHECK(hipStreamSynchronize(st));
         int it = 0, grow = 0;
         double rel = h->host_scalar[0] / bnorm;
@@ -785,7 +848,7 @@ mg_status mg_solve(mg_handle h, const double *f_dev, const double *g_dev, double
                 const double need = std::log(tol / rel) / (1.5 * std::log(rmin));
                 while (k < ITER_CHUNK && need >= 2 * k + 1 && it + 2 * k <= h->opt.max_iters) k *= 2;
             }
-            run_iterations(h, mixed, k, st);
+            run_iterations(h, k, st);
             HIPCHECK(hipStreamSynchronize(st));
             for (int i = 0; i < k && !stop; ++i) {
                 ++it;
@@ -801,7 +864,8 @@ mg_status mg_solve(mg_handle h, const double *f_dev, const double *g_dev, double
                 prev = rel;
             }
         }
-        HIPCHECK(hipMemcpyAsync(u_dev, D.u64[mixed ? h->upar : 0], D.ncells * 8, hipMemcpyDeviceToDevice, st));
+        HIPCHECK(hipMemcpyAsync(u_dev, D.u64[correction_form(h) ? h->upar : 0], D.ncells * 8,
+                                hipMemcpyDeviceToDevice, st));
         launch_zero_inactive(D.ncells, D.mask, u_dev, st);
         HIPCHECK(hipStreamSynchronize(st));
         if (result == MG_OK && rel > tol) result = MG_ERR_NO_CONVERGENCE;
@@ -1020,6 +1084,7 @@ mg_status mg_kernel_timing(mg_handle h, int enable, int *launches, double *avg_m
 
 mg_status mg_destroy(mg_handle h) {
     if (!h) return MG_OK;
+    std::lock_guard<std::mutex> lk(g_capture_mu);
     for (auto &e : h->ev) (void)hipEventDestroy(e);
     for (int p = 0; p < 3; ++p)
         for (int c = 0; c < 4; ++c) {

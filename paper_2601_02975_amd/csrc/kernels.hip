@@ -501,15 +501,16 @@ __global__ void k_plg_residual(int m, const int *__restrict__ cell, const int *_
     r[q] = v;
 }
 
-// Residual of the fine level fused with the restriction of eq. (5.8): one
-// thread per coarse cell, children summed with weight 1/4.  Fine PLG cells
+// Residual of the fine level fused with the restriction of eq. (5.8) (RESID;
+// else the restriction of b itself, as FMG restricts residuals): one thread
+// per coarse cell, children summed with weight 1/4.  Fine PLG cells
 // contribute rplg, or 0 when rplg is null (after a block-smoother sweep the
 // PLG rows are solved exactly, Definition 5.6).  rmask (coarse level): 0
 // inactive (b = 0), 1 regular, 2 a cell that also absorbs fine cells of a
 // merged-away coarse cell, computed by the extra blocks after the tiles,
 // one thread per such cell over its list of children.  uc (optional) is the
 // coarse iterate, set to zero.
-template <typename T, bool MIXED>
+template <typename T, bool MIXED, bool RESID>
 __global__ __launch_bounds__(NT) void k_restrict(LevelArgs L, LevelArgs C, int tiles_x, int ntile,
                                                  const T *__restrict__ u, const T *__restrict__ b,
                                                  const uint8_t *__restrict__ mask, const int *__restrict__ plgidx,
@@ -526,7 +527,9 @@ __global__ __launch_bounds__(NT) void k_restrict(LevelArgs L, LevelArgs C, int t
         for (int e = ex_ptr[t]; e < ex_ptr[t + 1]; ++e) {
             const int id = ex_child[e];
             const int j = id / L.pitch - 2, i = id - (j + 2) * L.pitch - 2;
-            if (mask[id] == 1)
+            if (!RESID)
+                sum += mask[id] ? b[id] : (T)0;
+            else if (mask[id] == 1)
                 sum += b[id] - sfv_global<T, MIXED>(L, u, i, j);
             else if (mask[id] == 2 && rplg)
                 sum += rplg[plgidx[id]];
@@ -555,8 +558,10 @@ __global__ __launch_bounds__(NT) void k_restrict(LevelArgs L, LevelArgs C, int t
             fb[n][q] = b[id];
         }
     }
-    load_tile<T>(s, gws, [&](int a, int c) { return u[pidx(L, a, c)]; }, L, i0, j0);
-    __syncthreads();
+    if (RESID) {
+        load_tile<T>(s, gws, [&](int a, int c) { return u[pidx(L, a, c)]; }, L, i0, j0);
+        __syncthreads();
+    }
 #pragma unroll
     for (int n = 0; n < NC; ++n) {
         const int t = threadIdx.x + n * NT;
@@ -569,7 +574,9 @@ __global__ __launch_bounds__(NT) void k_restrict(LevelArgs L, LevelArgs C, int t
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int fi = 2 * ci + (q & 1), fj = 2 * cj + (q >> 1);
-                if (fk[n][q] == 1) {
+                if (!RESID) {
+                    if (fk[n][q]) sum += fb[n][q];
+                } else if (fk[n][q] == 1) {
                     const int lx = fi - i0 + 2, ly = fj - j0 + 2;
                     sum += fb[n][q] - apply_sfv<T, MIXED>(L, [&](int dx, int dy) { return s[ly + dy][lx + dx]; });
                 } else if (fk[n][q] == 2 && rplg) {
@@ -581,16 +588,20 @@ __global__ __launch_bounds__(NT) void k_restrict(LevelArgs L, LevelArgs C, int t
     }
 }
 
-// Piecewise-constant interpolation and correction, eq. (5.9): blocks
+// Piecewise-constant interpolation and correction, eq. (5.9) (SET: the
+// interpolant itself, as FMG starts a V-cycle from it): blocks
 // [0, nmain) cover the fine rows; the rest handle the fine cells whose coarse
 // parent was merged away (they take the value of the absorbing cell).
-template <typename T>
+template <typename T, bool SET>
 __global__ void k_prolong(LevelArgs L, LevelArgs C, int bx_per_row, int nmain, const uint8_t *__restrict__ mask,
                           const uint8_t *__restrict__ cmask, const T *__restrict__ ec, T *__restrict__ u, int nex,
                           const int *__restrict__ ex_fine, const int *__restrict__ ex_coarse) {
     if ((int)blockIdx.x >= nmain) {
         const int k = (blockIdx.x - nmain) * blockDim.x + threadIdx.x;
-        if (k < nex) u[ex_fine[k]] += ec[ex_coarse[k]];
+        if (k < nex) {
+            if (SET) u[ex_fine[k]] = ec[ex_coarse[k]];
+            else u[ex_fine[k]] += ec[ex_coarse[k]];
+        }
         return;
     }
     const int j = blockIdx.x / bx_per_row;
@@ -598,7 +609,12 @@ __global__ void k_prolong(LevelArgs L, LevelArgs C, int bx_per_row, int nmain, c
     if (i >= L.nx) return;
     const size_t id = pidx(L, i, j);
     const size_t cid = pidx(C, i >> 1, j >> 1);
-    if (mask[id] && cmask[cid]) u[id] += ec[cid];
+    if (SET) {
+        if (mask[id] && cmask[cid]) u[id] = ec[cid];
+        else if (!mask[id]) u[id] = 0;
+    } else if (mask[id] && cmask[cid]) {
+        u[id] += ec[cid];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -635,17 +651,20 @@ __global__ __launch_bounds__(64 * BOT_WAVES) void k_bottom(int n, const int *__r
 // Residual max-norm over the active cells, FP64: tiles compute the SFV rows
 // by the stencil; blocks after the tiles compute the PLG rows from their
 // fixed-width rows (one thread per row).  CORRECT: the iterate is u + e (e
-// the FP32 V-cycle correction) and the tiles write it to uout (a different
-// buffer); WRITE32: the residual is also written in FP32 (the next FP32
-// V-cycle's right-hand side).  One partial maximum per block.
-template <bool MIXED, bool WRITE32, bool CORRECT>
+// the correction of the cycle just run, FP32 or FP64) and the tiles write it
+// to uout (a different buffer); WRITE32: the residual is also written in FP32 (the next FP32
+// V-cycle's right-hand side).  One partial maximum per block; with result
+// given, the last block to finish writes their maximum there (counter: a
+// zeroed word, left zeroed).
+template <bool MIXED, bool WRITE32, bool CORRECT, typename TE>
 __global__ __launch_bounds__(NT) void k_residual_norm(LevelArgs L, int tiles_x, int ntile, const double *__restrict__ u,
-                                                      const float *__restrict__ e, double *__restrict__ uout,
+                                                      const TE *__restrict__ e, double *__restrict__ uout,
                                                       const double *__restrict__ b, const uint8_t *__restrict__ mask,
                                                       int m, const int *__restrict__ pcell,
                                                       const int *__restrict__ fe_col,
                                                       const double *__restrict__ fe_val, float *__restrict__ r32,
-                                                      double *__restrict__ r64, double *__restrict__ partial) {
+                                                      double *__restrict__ r64, double *__restrict__ partial,
+                                                      unsigned *__restrict__ counter, double *__restrict__ result) {
     __shared__ double s[HY][HX];
     __shared__ double gws[32];
     __shared__ double red[NT / 64];
@@ -701,10 +720,32 @@ __global__ __launch_bounds__(NT) void k_residual_norm(LevelArgs L, int tiles_x, 
     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_down(mx, off, 64));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
     __syncthreads();
+    __shared__ int last;
     if (threadIdx.x == 0) {
         double v = red[0];
         for (int w = 1; w < NT / 64; ++w) v = fmax(v, red[w]);
         partial[blockIdx.x] = v;
+        last = 0;
+        if (result) {
+            // the last block to finish reduces the partial maxima
+            __threadfence();
+            last = atomicAdd(counter, 1u) == gridDim.x - 1;
+        }
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    double gm = 0.0;
+    for (int k = threadIdx.x; k < (int)gridDim.x; k += NT)
+        gm = fmax(gm, __hip_atomic_load(partial + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    for (int off = 32; off > 0; off >>= 1) gm = fmax(gm, __shfl_down(gm, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = gm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v = red[0];
+        for (int w = 1; w < NT / 64; ++w) v = fmax(v, red[w]);
+        *result = v;
+        atomicExch(counter, 0u);
     }
 }
 
@@ -865,20 +906,26 @@ void launch_restrict(const LevelArgs &L, const LevelArgs &C, const T *u, const T
     const int tx = (C.nx + TX / 2 - 1) / (TX / 2), ty = (C.ny + TY / 2 - 1) / (TY / 2);
     const int ntile = tx * ty;
     const dim3 grid(ntile + (nt + NT - 1) / NT);
-    if (L.mixed)
-        hipLaunchKernelGGL((k_restrict<T, true>), grid, dim3(NT), 0, st, L, C, tx, ntile, u, b, mask, plgidx, rplg,
-                           rmask, bc, uc, nt, ex_ptr, ex_target, ex_child);
-    else
-        hipLaunchKernelGGL((k_restrict<T, false>), grid, dim3(NT), 0, st, L, C, tx, ntile, u, b, mask, plgidx, rplg,
-                           rmask, bc, uc, nt, ex_ptr, ex_target, ex_child);
+#define MG_RS(MX, RS)                                                                                            \
+    hipLaunchKernelGGL((k_restrict<T, MX, RS>), grid, dim3(NT), 0, st, L, C, tx, ntile, u, b, mask, plgidx, rplg, \
+                       rmask, bc, uc, nt, ex_ptr, ex_target, ex_child)
+    if (!u) MG_RS(false, false);
+    else if (L.mixed) MG_RS(true, true);
+    else MG_RS(false, true);
+#undef MG_RS
 }
 
 template <typename T>
 void launch_prolong(const LevelArgs &L, const LevelArgs &C, const uint8_t *mask, const uint8_t *cmask, const T *ec,
-                    T *u, int nex, const int *ex_fine, const int *ex_coarse, hipStream_t st) {
+                    T *u, int nex, const int *ex_fine, const int *ex_coarse, bool set, hipStream_t st) {
     const int bxr = (L.nx + 255) / 256, nmain = bxr * L.ny;
-    hipLaunchKernelGGL((k_prolong<T>), dim3(nmain + (nex + 255) / 256), dim3(256), 0, st, L, C, bxr, nmain, mask, cmask,
-                       ec, u, nex, ex_fine, ex_coarse);
+    const dim3 grid(nmain + (nex + 255) / 256);
+    if (set)
+        hipLaunchKernelGGL((k_prolong<T, true>), grid, dim3(256), 0, st, L, C, bxr, nmain, mask, cmask, ec, u, nex,
+                           ex_fine, ex_coarse);
+    else
+        hipLaunchKernelGGL((k_prolong<T, false>), grid, dim3(256), 0, st, L, C, bxr, nmain, mask, cmask, ec, u, nex,
+                           ex_fine, ex_coarse);
 }
 
 template <typename TI, typename TO>
@@ -887,22 +934,24 @@ void launch_bottom(int n, const int *cells, const double *ainv, const TI *b, TO 
                        sizeof(double) * n, st, n, cells, ainv, b, x);
 }
 
-int launch_residual_norm(const LevelArgs &L, const double *u, const float *e, double *uout, const double *b,
+int launch_residual_norm(const LevelArgs &L, const double *u, const void *e, bool e64, double *uout, const double *b,
                          const uint8_t *mask, int m, const int *pcell, const int *fe_col, const double *fe_val,
-                         float *r32, double *r64, double *partial, hipStream_t st) {
+                         float *r32, double *r64, double *partial, unsigned *counter, double *result,
+                         hipStream_t st) {
     const dim3 tg = tile_grid(L);
     const int ntile = (int)(tg.x * tg.y), nblk = ntile + (m + NT - 1) / NT;
-#define MG_RES(MX, W32, CORR)                                                                                         \
-    hipLaunchKernelGGL((k_residual_norm<MX, W32, CORR>), dim3(nblk), dim3(NT), 0, st, L, (int)tg.x, ntile, u, e, uout, \
-                       b, mask, m, pcell, fe_col, fe_val, r32, r64, partial)
-    const bool w32 = r32 != nullptr, corr = e != nullptr;
-    if (L.mixed) {
-        if (corr) { if (w32) MG_RES(true, true, true); else MG_RES(true, false, true); }
-        else { if (w32) MG_RES(true, true, false); else MG_RES(true, false, false); }
-    } else {
-        if (corr) { if (w32) MG_RES(false, true, true); else MG_RES(false, false, true); }
-        else { if (w32) MG_RES(false, true, false); else MG_RES(false, false, false); }
-    }
+#define MG_RES(MX, W32, CORR, TE)                                                                                      \
+    hipLaunchKernelGGL((k_residual_norm<MX, W32, CORR, TE>), dim3(nblk), dim3(NT), 0, st, L, (int)tg.x, ntile, u,       \
+                       static_cast<const TE *>(e), uout, b, mask, m, pcell, fe_col, fe_val, r32, r64, partial, \
+                       counter, result)
+#define MG_RES2(MX, W32)                                          \
+    if (!e) MG_RES(MX, W32, false, float);                        \
+    else if (e64) MG_RES(MX, W32, true, double);                  \
+    else MG_RES(MX, W32, true, float);
+    const bool w32 = r32 != nullptr;
+    if (L.mixed) { if (w32) { MG_RES2(true, true) } else { MG_RES2(true, false) } }
+    else { if (w32) { MG_RES2(false, true) } else { MG_RES2(false, false) } }
+#undef MG_RES2
 #undef MG_RES
     return nblk;
 }
@@ -939,8 +988,8 @@ template void launch_plg_residual<double>(int, const int *, const int *, const i
 template void launch_plg_residual<float>(int, const int *, const int *, const int *, const float *, const float *, const float *, float *, hipStream_t);
 template void launch_restrict<double>(const LevelArgs &, const LevelArgs &, const double *, const double *, const uint8_t *, const int *, const double *, const uint8_t *, double *, double *, int, const int *, const int *, const int *, hipStream_t);
 template void launch_restrict<float>(const LevelArgs &, const LevelArgs &, const float *, const float *, const uint8_t *, const int *, const float *, const uint8_t *, float *, float *, int, const int *, const int *, const int *, hipStream_t);
-template void launch_prolong<double>(const LevelArgs &, const LevelArgs &, const uint8_t *, const uint8_t *, const double *, double *, int, const int *, const int *, hipStream_t);
-template void launch_prolong<float>(const LevelArgs &, const LevelArgs &, const uint8_t *, const uint8_t *, const float *, float *, int, const int *, const int *, hipStream_t);
+template void launch_prolong<double>(const LevelArgs &, const LevelArgs &, const uint8_t *, const uint8_t *, const double *, double *, int, const int *, const int *, bool, hipStream_t);
+template void launch_prolong<float>(const LevelArgs &, const LevelArgs &, const uint8_t *, const uint8_t *, const float *, float *, int, const int *, const int *, bool, hipStream_t);
 template void launch_bottom<double, double>(int, const int *, const double *, const double *, double *, hipStream_t);
 template void launch_bottom<float, float>(int, const int *, const double *, const float *, float *, hipStream_t);
 

@@ -12,6 +12,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -34,6 +35,7 @@ struct Problem {
     long long bytes = 0;          // device bytes of the hierarchy (estimate until set up)
     bool busy = false, failed = false;
     mg_status setup_status = MG_OK;
+    std::string setup_error;
     long long last_used = 0;
 };
 
@@ -47,6 +49,7 @@ struct Request {
     mg_status status = MG_OK;
     int iters = 0;
     double rel = 0;
+    std::string error;            // mg_last_error() of a failed setup or solve
 };
 
 // device bytes a hierarchy is assumed to need before its setup has run:
@@ -124,8 +127,10 @@ struct mg_server_s {
             r.t_start = Clock::now();
             lk.unlock();
             mg_status rc = MG_OK;
+            std::string err;
             if (p.failed) {
                 rc = p.setup_status;
+                err = p.setup_error;
             } else if (!p.h) {
                 std::vector<mg_curve> cv(p.segs.size());
                 for (size_t k = 0; k < p.segs.size(); ++k) cv[k] = {(int)p.segs[k].size(), p.segs[k].data()};
@@ -133,6 +138,7 @@ struct mg_server_s {
                 rc = mg_setup(&p.grid, (int)cv.size(), cv.data(), p.a, p.b, p.c, &p.opt, st, &h);
                 mg_info info{};
                 if (rc == MG_OK) mg_query(h, &info);
+                else err = mg_last_error();
                 lk.lock();
                 resident_bytes -= p.bytes;
                 if (rc == MG_OK) {
@@ -142,16 +148,21 @@ struct mg_server_s {
                 } else {
                     p.failed = true;
                     p.setup_status = rc;
+                    p.setup_error = err;
                     p.bytes = 0;
                 }
                 lk.unlock();
             }
             int iters = 0;
             double rel = 0;
-            if (rc == MG_OK) rc = mg_solve(p.h, r.f, r.g, r.u, r.tol, st, &iters, &rel);
+            if (rc == MG_OK) {
+                rc = mg_solve(p.h, r.f, r.g, r.u, r.tol, st, &iters, &rel);
+                if (rc != MG_OK) err = mg_last_error();
+            }
             const auto t = Clock::now();
             lk.lock();
             r.status = rc;
+            r.error = err;
             r.iters = iters;
             r.rel = rel;
             r.t_done = t;
@@ -278,6 +289,13 @@ mg_status mg_server_wait(mg_server s, unsigned long long ticket, mg_status *stat
         s->cv_done.wait(lk, [&] { return it->second.done; });
     }
     return mg_server_poll(s, ticket, nullptr, status, iters, rel_residual, latency_s);
+}
+
+const char *mg_server_request_error(mg_server s, unsigned long long ticket) {
+    if (!s) return "";
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    return it == s->reqs.end() ? "" : it->second.error.c_str();
 }
 
 mg_status mg_server_get_stats(mg_server s, mg_server_stats *st) {

@@ -58,7 +58,7 @@ def test_server_results_equal_alone(budget, precision):
     st = srv.stats()
     srv.close()
     for (u0, it0, rel0), u, r in zip(alone, outs, res):
-        assert r["status"] == 0
+        assert r["status"] == 0, r
         assert r["iters"] == it0 and r["rel_residual"] == rel0
         assert torch.equal(u, u0)
     assert st["completed"] == len(reqs) and st["failed"] == 0

@@ -150,3 +150,33 @@ def test_fourth_order_convergence_disk():
         u = spla.spsolve(L.A.tocsc(), b)
         errs.append(np.abs(u - cell_averages(L, P.solution.u)).max())
     assert errs[0] / errs[1] > 8.0
+
+
+def test_fmg_converges_to_direct_solution(disk_hierarchy):
+    """FMG cycles on residual equations (Algorithm 4, Sec. 5.4) converge to
+    the same discrete solution u* = A^{-1} b as the direct solve."""
+    P, H, b = disk_hierarchy
+    L = H.levels[0]
+    direct = spla.spsolve(L.A.tocsc(), b)
+    u, it, rel = H.solve(b, tol=1e-12, max_iters=60, cycle="FMG")
+    assert rel <= 1e-12
+    assert np.abs(u - direct).max() <= 1e-9 * np.abs(direct).max()
+
+
+def test_fmg_factor_is_h_independent_and_beats_vcycle():
+    """Averaged residual reduction of the FMG iteration on the unit square,
+    (a,b,c) = (1,0,2), nu = (3,3): independent of h (Sec. 5.4: O(1) cycles)
+    and better than the V-cycle's, which grows with the depth here."""
+    factors = {}
+    for n in (64, 128):
+        P = W.unit_square_config(n, 1.0, 0.0, 2.0)
+        H = Hierarchy(P.grid, P.curves, P.a, P.b, P.c, P.eps)
+        b, _, _ = rhs(H.levels[0], P.solution)
+        for cyc in ("V", "FMG"):
+            hist = []
+            H.solve(b, tol=1e-11, max_iters=80, history=hist, cycle=cyc)
+            rels = [r for _, r in hist]
+            factors[(n, cyc)] = (rels[-1] / rels[0]) ** (1.0 / (len(rels) - 1))
+    assert abs(factors[(64, "FMG")] - factors[(128, "FMG")]) <= 0.05
+    assert factors[(128, "FMG")] < factors[(128, "V")]
+    assert factors[(128, "FMG")] < 0.5
