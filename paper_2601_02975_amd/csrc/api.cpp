@@ -80,8 +80,7 @@ struct mg_handle_s {
     int nrhs = 0;
     int *rhs_ptr = nullptr, *rhs_cell = nullptr, *rhs_gidx = nullptr;
     double *rhs_coef = nullptr;
-    double *partial = nullptr, *host_scalar = nullptr, *host_scalar_dev = nullptr;
-    unsigned *counter = nullptr;      // zeroed word for the residual kernel's final reduction
+    double *partial = nullptr, *host_scalar = nullptr, *host_scalar_dev = nullptr;   // mapped host memory
     int npartial = 0;
     std::vector<void *> allocs;
     long long bytes = 0;
@@ -519,7 +518,7 @@ double device_absmax_finish(mg_handle h, int nblocks, hipStream_t st) {
 double residual_norm(mg_handle h, int l, const double *u, const double *b, double *r64, hipStream_t st) {
     DevLevel &D = h->dev[l];
     int nb = launch_residual_norm(D.args, u, nullptr, false, nullptr, b, D.mask, D.m, D.plg_cell, D.fe_col, D.fe_val,
-                                  nullptr, r64, h->partial, nullptr, nullptr, st);
+                                  nullptr, r64, h->partial, st);
     return device_absmax_finish(h, nb, st);
 }
 
@@ -536,9 +535,11 @@ void enqueue_residual(mg_handle h, int src, const void *e, bool e64, int slot, h
     DevLevel &D = h->dev[0];
     const bool mixed = h->opt.precision == MG_MIXED;
     const bool fmg64 = !mixed && h->opt.cycle == MG_CYCLE_FMG;
-    launch_residual_norm(D.args, D.u64[src], e, e64, e ? D.u64[1 - src] : nullptr, D.b64, D.mask, D.m, D.plg_cell,
-                         D.fe_col, D.fe_val, mixed ? D.b32 : nullptr, fmg64 ? D.r64 : nullptr, h->partial, h->counter,
-                         h->host_scalar_dev + slot, st);
+    const int nb = launch_residual_norm(D.args, D.u64[src], e, e64, e ? D.u64[1 - src] : nullptr, D.b64, D.mask, D.m,
+                                        D.plg_cell, D.fe_col, D.fe_val, mixed ? D.b32 : nullptr,
+                                        fmg64 ? D.r64 : nullptr, h->partial, st);
+    // the one-block reduction writes the norm straight into mapped host memory
+    launch_absmax(nb, h->partial, nullptr, h->host_scalar_dev + slot, 1, st);
 }
 
 // one outer iteration on the handle's own buffers, then the residual
@@ -754,7 +755,6 @@ mg_status mg_setup(const mg_grid *grid, int n_curves, const mg_curve *curves, do
         HIPCHECK(hipHostMalloc((void **)&h->host_scalar, sizeof(double) * ITER_CHUNK,
                                hipHostMallocMapped | hipHostMallocCoherent));
         HIPCHECK(hipHostGetDevicePointer((void **)&h->host_scalar_dev, h->host_scalar, 0));
-        h->counter = h->alloc<unsigned>(1);
         HIPCHECK(hipStreamSynchronize(st));
         h->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     });

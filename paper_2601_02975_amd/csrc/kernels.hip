@@ -653,9 +653,7 @@ __global__ __launch_bounds__(64 * BOT_WAVES) void k_bottom(int n, const int *__r
 // fixed-width rows (one thread per row).  CORRECT: the iterate is u + e (e
 // the correction of the cycle just run, FP32 or FP64) and the tiles write it
 // to uout (a different buffer); WRITE32: the residual is also written in FP32 (the next FP32
-// V-cycle's right-hand side).  One partial maximum per block; with result
-// given, the last block to finish writes their maximum there (counter: a
-// zeroed word, left zeroed).
+// V-cycle's right-hand side).  One partial maximum per block.
 template <bool MIXED, bool WRITE32, bool CORRECT, typename TE>
 __global__ __launch_bounds__(NT) void k_residual_norm(LevelArgs L, int tiles_x, int ntile, const double *__restrict__ u,
                                                       const TE *__restrict__ e, double *__restrict__ uout,
@@ -663,8 +661,7 @@ __global__ __launch_bounds__(NT) void k_residual_norm(LevelArgs L, int tiles_x, 
                                                       int m, const int *__restrict__ pcell,
                                                       const int *__restrict__ fe_col,
                                                       const double *__restrict__ fe_val, float *__restrict__ r32,
-                                                      double *__restrict__ r64, double *__restrict__ partial,
-                                                      unsigned *__restrict__ counter, double *__restrict__ result) {
+                                                      double *__restrict__ r64, double *__restrict__ partial) {
     __shared__ double s[HY][HX];
     __shared__ double gws[32];
     __shared__ double red[NT / 64];
@@ -720,32 +717,10 @@ __global__ __launch_bounds__(NT) void k_residual_norm(LevelArgs L, int tiles_x, 
     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_down(mx, off, 64));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
     __syncthreads();
-    __shared__ int last;
     if (threadIdx.x == 0) {
         double v = red[0];
         for (int w = 1; w < NT / 64; ++w) v = fmax(v, red[w]);
         partial[blockIdx.x] = v;
-        last = 0;
-        if (result) {
-            // the last block to finish reduces the partial maxima
-            __threadfence();
-            last = atomicAdd(counter, 1u) == gridDim.x - 1;
-        }
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    double gm = 0.0;
-    for (int k = threadIdx.x; k < (int)gridDim.x; k += NT)
-        gm = fmax(gm, __hip_atomic_load(partial + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    for (int off = 32; off > 0; off >>= 1) gm = fmax(gm, __shfl_down(gm, off, 64));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = gm;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double v = red[0];
-        for (int w = 1; w < NT / 64; ++w) v = fmax(v, red[w]);
-        *result = v;
-        atomicExch(counter, 0u);
     }
 }
 
@@ -936,14 +911,12 @@ void launch_bottom(int n, const int *cells, const double *ainv, const TI *b, TO 
 
 int launch_residual_norm(const LevelArgs &L, const double *u, const void *e, bool e64, double *uout, const double *b,
                          const uint8_t *mask, int m, const int *pcell, const int *fe_col, const double *fe_val,
-                         float *r32, double *r64, double *partial, unsigned *counter, double *result,
-                         hipStream_t st) {
+                         float *r32, double *r64, double *partial, hipStream_t st) {
     const dim3 tg = tile_grid(L);
     const int ntile = (int)(tg.x * tg.y), nblk = ntile + (m + NT - 1) / NT;
 #define MG_RES(MX, W32, CORR, TE)                                                                                      \
     hipLaunchKernelGGL((k_residual_norm<MX, W32, CORR, TE>), dim3(nblk), dim3(NT), 0, st, L, (int)tg.x, ntile, u,       \
-                       static_cast<const TE *>(e), uout, b, mask, m, pcell, fe_col, fe_val, r32, r64, partial, \
-                       counter, result)
+                       static_cast<const TE *>(e), uout, b, mask, m, pcell, fe_col, fe_val, r32, r64, partial)
 #define MG_RES2(MX, W32)                                          \
     if (!e) MG_RES(MX, W32, false, float);                        \
     else if (e64) MG_RES(MX, W32, true, double);                  \

@@ -34,13 +34,11 @@ void launch_prolong(const LevelArgs &L, const LevelArgs &C, const uint8_t *mask,
 template <typename TI, typename TO>
 void launch_bottom(int n, const int *cells, const double *ainv, const TI *b, TO *x, hipStream_t st);
 // residual b - A u (u + e when e is given, FP32 or FP64 (e64), written to
-// uout); the max-norm goes to *result (device or mapped host memory) when
-// result is given (counter: a zeroed word), else stays in per-block partial
+// uout) with partial
 // max-norms per block; returns the number of blocks
 int launch_residual_norm(const LevelArgs &L, const double *u, const void *e, bool e64, double *uout, const double *b,
                          const uint8_t *mask, int m, const int *pcell, const int *fe_col, const double *fe_val,
-                         float *r32, double *r64, double *partial, unsigned *counter, double *result,
-                         hipStream_t st);
+                         float *r32, double *r64, double *partial, hipStream_t st);
 void launch_absmax(int n, const double *v, const uint8_t *mask, double *partial, int nblocks, hipStream_t st);
 void launch_rhs(size_t n, const uint8_t *mask, const double *f, double *b, int nrows, const int *ptr, const int *cell,
                 const int *gidx, const double *coef, const double *g, hipStream_t st);
