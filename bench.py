@@ -2,10 +2,12 @@
 
 Workload: [0,1]^2 minus 3 seeded disks (radius U[0.05, 0.15]), 1024 x 1024
 cells, a=1, b=0.5, c=2, Dirichlet outside, Neumann on the holes, 6 seeded
-sine modes (seed 0).  A step is one whole solve from u = 0 (outer iteration
-of V-cycles until ||b - A u||_inf <= 1e-10 ||b||_inf) with the inputs already
-resident on the device.  `value` is the mixed-precision rate (FP32 V-cycles
-inside FP64 defect correction); the plain FP64 rate is reported beside it.
+sine modes (seed 0).  A step is one whole solve from u = 0 (the outer
+iteration of Section 5.4: FMG cycles of Algorithm 4 on the residual equation
+until ||b - A u||_inf <= 1e-10 ||b||_inf) with the inputs already resident on
+the device.  `value` is the mixed-precision rate (FP32 cycles inside FP64
+defect correction); the plain FP64 rate is reported beside it, and both rates
+again with V-cycles (Algorithm 3) as the outer iteration.
 
 Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
 """
@@ -68,10 +70,11 @@ def timed_solves(torch, S, f, g, steps, warmup, tol, record=False):
     return dt, iters, rel, u, launches, avg_ms
 
 
-def cpu_baseline(P, gpu_iters, sample_cycles):
+def cpu_baseline(P, gpu_iters, sample_cycles, cycle):
     """The oracle (plain NumPy/SciPy, FP64) on the same workload: time a
-    bounded number of its V-cycles and scale to one solve with the iteration
-    count the solve needs (the GPU FP64 iteration count: the iterates agree)."""
+    bounded number of its cycles (FMG on the residual equation, or V-cycles)
+    and scale to one solve with the iteration count the solve needs (the GPU
+    FP64 iteration count: the iterates agree)."""
     from threadpoolctl import threadpool_limits
 
     from oracle.multigrid import Hierarchy
@@ -81,18 +84,19 @@ def cpu_baseline(P, gpu_iters, sample_cycles):
         H = Hierarchy(P.grid, P.curves, P.a, P.b, P.c, P.eps)
         t_setup = time.perf_counter() - t0
         b, _, _ = rhs(H.levels[0], P.solution)
+        A = H.levels[0].A
         u = b * 0.0
         t0 = time.perf_counter()
         for _ in range(sample_cycles):
-            u = H.vcycle(0, u, b)
-            r = b - H.levels[0].A @ u
+            u = u + H.fmg(0, b - A @ u) if cycle == "FMG" else H.vcycle(0, u, b)
+            r = b - A @ u
             _ = float(abs(r).max())
         t_cycle = (time.perf_counter() - t0) / sample_cycles
     per_solve = gpu_iters * t_cycle
     return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": "%d V-cycles (with residual norms) of the FP64 oracle on the same 1024^2 workload, "
+            "sample": "%d %s cycles (with residual norms) of the FP64 oracle on the same 1024^2 workload, "
                       "%.3f s each, scaled by the %d cycles a solve to 1e-10 takes; oracle setup %.1f s "
-                      "not included" % (sample_cycles, t_cycle, gpu_iters, t_setup)}
+                      "not included" % (sample_cycles, cycle, t_cycle, gpu_iters, t_setup)}
 
 
 def serving_leg(torch, mg, W, n, n_geom, n_rhs, qps, slots, tol):
@@ -108,7 +112,8 @@ def serving_leg(torch, mg, W, n, n_geom, n_rhs, qps, slots, tol):
     rng = np.random.default_rng(12345)
     order = rng.permutation(len(reqs))
     gaps = rng.exponential(1.0 / qps, size=len(reqs))
-    seq = {p: [mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=p, max_iters=1000) for P in geoms]
+    seq = {p: [mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=p, max_iters=1000,
+                         cycle=mg.CYCLE_FMG) for P in geoms]
            for p in (mg.FP64, mg.MIXED)}
     inputs = []
     for k, P in reqs:
@@ -126,8 +131,8 @@ def serving_leg(torch, mg, W, n, n_geom, n_rhs, qps, slots, tol):
         for S in seq[p]:
             S.close()
     srv = mg.Server(max_active=slots, hbm_budget=64 << 30)
-    pids = [srv.add_problem(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=mg.MIXED, max_iters=1000)
-            for P in geoms]
+    pids = [srv.add_problem(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=mg.MIXED, max_iters=1000,
+                            cycle=mg.CYCLE_FMG) for P in geoms]
     warm = []
     for k in range(n_geom):                        # setup of every hierarchy (not timed)
         f, g = inputs[k * n_rhs]
@@ -147,7 +152,7 @@ def serving_leg(torch, mg, W, n, n_geom, n_rhs, qps, slots, tol):
     lat = sorted(r["latency_s"] for r in res)
     pct = lambda q: lat[min(len(lat) - 1, int(math.ceil(q * len(lat))) - 1)]
     return {"workload": "%d three-disk geometries (seeds 1-%d) at %d^2, resident after one warm-up request each; "
-                        "%d right-hand sides per geometry arriving as a Poisson process at %g/s; %d slots; mixed "
+                        "%d right-hand sides per geometry arriving as a Poisson process at %g/s; %d slots; FMG in mixed "
                         "precision to %g" % (n_geom, n_geom, n, n_rhs, qps, slots, tol),
             "requests": len(reqs), "failed": sum(r["status"] != 0 for r in res),
             "p50_latency_s": pct(0.50), "p99_latency_s": pct(0.99), "solves_per_s": len(reqs) / t_all,
@@ -181,9 +186,16 @@ def main():
     torch.cuda.set_device(0)
     P = W.three_disks_config(0, args.n)
     t0 = time.perf_counter()
-    S32 = mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=mg.MIXED, max_iters=1000)
-    t_setup = time.perf_counter() - t0
-    S64 = mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=mg.FP64, max_iters=1000)
+    solvers = {}
+    t_setup = None
+    for cyc in (mg.CYCLE_FMG, mg.CYCLE_V):
+        for prec in (mg.MIXED, mg.FP64):
+            t0 = time.perf_counter()
+            solvers[(cyc, prec)] = mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=prec,
+                                             max_iters=1000, cycle=cyc)
+            if t_setup is None:
+                t_setup = time.perf_counter() - t0
+    S32, S64 = solvers[(mg.CYCLE_FMG, mg.MIXED)], solvers[(mg.CYCLE_FMG, mg.FP64)]
     fh, gh = S64.project(P.solution)
     f = torch.tensor(fh, device="cuda")
     g = torch.tensor(gh, device="cuda")
@@ -198,10 +210,17 @@ def main():
         torch.cuda.synchronize()
         print("calibration copy: 3 x %d bytes read and written" % (src_t.numel() * 8), file=sys.stderr)
         del src_t, dst_t
+    dtv = {}
+    for prec, name in ((mg.FP64, "fp64"), (mg.MIXED, "mixed")):
+        dt, it, rel, _, _, _ = timed_solves(torch, solvers[(mg.CYCLE_V, prec)], f, g, args.steps, args.warmup,
+                                            args.tol)
+        dtv[name] = (dt, it[-1], rel)
+        print("V-cycle %s: %.4f s/solve, %d iterations" % (name, dt / args.steps, it[-1]), file=sys.stderr,
+              flush=True)
     dt64, it64, rel64, u64, _, _ = timed_solves(torch, S64, f, g, args.steps, args.warmup, args.tol)
-    print("fp64: %.4f s/solve, %d iterations" % (dt64 / args.steps, it64[-1]), file=sys.stderr, flush=True)
+    print("FMG fp64: %.4f s/solve, %d iterations" % (dt64 / args.steps, it64[-1]), file=sys.stderr, flush=True)
     dt32, it32, rel32, u32, nl, avg_ms = timed_solves(torch, S32, f, g, args.steps, args.warmup, args.tol, True)
-    print("mixed: %.4f s/solve, %d iterations" % (dt32 / args.steps, it32[-1]), file=sys.stderr, flush=True)
+    print("FMG mixed: %.4f s/solve, %d iterations" % (dt32 / args.steps, it32[-1]), file=sys.stderr, flush=True)
     diff = float((u32 - u64).abs().max() / u64.abs().max())
 
     n_cells = P.grid.nx * P.grid.ny
@@ -222,14 +241,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 V-cycle in f64 defect correction",
+        "dtype": "f32 cycles in f64 defect correction",
         "data": "synthetic",
         "config": {"workload": "three_disks_1024x1024_seed0 (a=1, b=0.5, c=2; Dirichlet box, Neumann holes; "
                                "6 sine modes)", "tol": args.tol, "cells": n_cells,
+                   "solver": "FMG cycles (Algorithm 4) on residual equations, nu = (3, 3)",
                    "levels": S64.info["nx"], "plg_cells": S64.info["n_plg"]},
         "fp64": {"value": args.steps / dt64, "unit": "solves/s", "iterations": it64[-1], "rel_residual": rel64},
         "mixed": {"iterations": it32[-1], "rel_residual": rel32, "max_rel_diff_vs_fp64": diff},
         "speedup_mixed_over_fp64": dt64 / dt32,
+        "vcycle": {name: {"value": args.steps / d[0], "unit": "solves/s", "iterations": d[1], "rel_residual": d[2]}
+                   for name, d in dtv.items()},
         "roofline": {"bound": "hbm", "kernel": "k_smooth_a<float> (finest level: SFV Jacobi tiles + PLG segment solves)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
@@ -242,7 +264,7 @@ def main():
             out["serving"]["p50_latency_s"], out["serving"]["p99_latency_s"], out["serving"]["solves_per_s"]),
             file=sys.stderr, flush=True)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(P, it64[-1], args.cpu_cycles)
+        out["cpu_baseline"] = cpu_baseline(P, it64[-1], args.cpu_cycles, "FMG")
     print(json.dumps(out))
 
 

@@ -23,11 +23,14 @@ Readings of points the paper leaves open (each also listed in the design doc):
   * lattice selection (the cited PLG algorithm is not reproduced): K is the
     set of active cells in the 7x7 index box centred at i (9x9 if needed);
     a nearest-first greedy with an exact rank test is run under each of the
-    8 grid symmetries, and the lattice whose full-cell fit has the smallest
-    weighted norm ||beta||_{W^{-1}} is kept (see ``select_lattice``).  A
-    single greedy pass, or a 5x5 box shifted inward, gives lopsided rows with
-    a positive centre weight on coarse levels, which make the two-grid
-    correction diverge;
+    8 grid symmetries (see ``candidate_lattices``); each candidate is fitted
+    for the actual cell, and the one whose row is the most diagonally
+    dominant with a negative own coefficient is kept (``Level._lattice``).
+    Ranking candidates by the weighted norm of a full-cell fit instead
+    leaves rows with a positive own coefficient near curved Neumann and
+    Robin boundaries and with a strong cross term, which make the two-grid
+    correction diverge; widening the candidates (shifted centres, 9x9 boxes)
+    improves the worst rows further but slows the V- and FMG cycles down;
   * the basis centre p is the centre of the grid cell of i;
   * the minimum-W^{-1}-norm solution is computed as beta = W^{1/2} gamma with
     gamma the minimum-2-norm solution of (M W^{1/2}) gamma = phibar, which is
@@ -105,44 +108,21 @@ _SYMMETRIES = ((1, 0, 0, 1), (0, -1, 1, 0), (-1, 0, 0, -1), (0, 1, -1, 0),
                (1, 0, 0, -1), (0, 1, 1, 0), (-1, 0, 0, 1), (0, -1, -1, 0))
 
 
-def _regular_fit_norm(lat, abc):
-    """||beta||^2 in the W^{-1} norm of eq. (4.17) for the lattice `lat` of
-    full cells with spacing 1 (beta solves M beta = phibar of eq. (4.14))."""
-    a, b, c = abc
-    full = full_cell_moments()
-    M = np.array([shift_moments(full, d[0], d[1]) for d in lat]).T
-    phibar = np.zeros(NBASIS)
-    for k, (p, q) in enumerate(MONOS):
-        s = 0.0
-        if p >= 2:
-            s += a * p * (p - 1) * full[MONO_INDEX[(p - 2, q)]]
-        if p >= 1 and q >= 1:
-            s += b * p * q * full[MONO_INDEX[(p - 1, q - 1)]]
-        if q >= 2:
-            s += c * q * (q - 1) * full[MONO_INDEX[(p, q - 2)]]
-        phibar[k] = s
-    beta = np.linalg.solve(M, phibar)
-    w = np.array([max(math.hypot(d[0], d[1]), W_MIN) for d in lat])
-    return float(np.sum(w * beta * beta))
-
-
-def select_lattice(window, abc):
+def candidate_lattices(window):
     """window: frozenset of offsets d (|d|_inf <= 4) of the active cells around
-    the PLG cell i; abc: the coefficients (a, b, c).
+    the PLG cell i.  Returns the poised lattices S_PLG(i) the selection chooses
+    from (Definitions 4.2-4.3).
 
     K is the set of active cells in the 7x7 box centred at i (the 9x9 box if
     the 7x7 one holds no poised subset).  For each of the 8 symmetries g of
     the grid, nodes of K are taken nearest-first, ordered by (|d|^2, angle of
     g(d) in [0, 2pi)), whenever they raise the exact rank of the point-sample
-    matrix [d^alpha], |alpha| <= 4, until 15 are chosen.  Of these (up to 8)
-    poised lattices the one whose fit for full cells has the smallest
-    ||beta||_{W^{-1}} (eqs. (4.16)-(4.17)) is kept; a tie within a relative
-    1e-9 keeps the earlier symmetry.  Returns the 15 offsets of S_PLG(i)."""
-    key = (window, abc)
-    hit = _LATTICE_MEMO.get(key)
+    matrix [d^alpha], |alpha| <= 4, until 15 are chosen.  Each lattice starts
+    with d = (0, 0).  Distinct lattices are returned in symmetry order."""
+    hit = _LATTICE_MEMO.get(window)
     if hit is not None:
         return hit
-    best, bestv = None, None
+    out = []
     for half in (3, 4):
         box = [d for d in window if abs(d[0]) <= half and abs(d[1]) <= half]
         if len(box) < NBASIS:
@@ -151,17 +131,23 @@ def select_lattice(window, abc):
             order = sorted(box, key=lambda d: (d[0] * d[0] + d[1] * d[1],
                                                _angle((g[0] * d[0] + g[1] * d[1], g[2] * d[0] + g[3] * d[1]))))
             lat = _greedy(order)
-            if lat is None:
-                continue
-            v = _regular_fit_norm(lat, abc)
-            if bestv is None or v < bestv * (1.0 - 1e-9):
-                best, bestv = lat, v
-        if best is not None:
+            if lat is not None and lat not in out:
+                out.append(lat)
+        if out:
             break
-    if best is None:
+    if not out:
         raise GeometryError("no poised lattice for a PLG cell")
-    _LATTICE_MEMO[key] = best
-    return best
+    _LATTICE_MEMO[window] = out
+    return out
+
+
+def row_dominance(beta):
+    """Selection key of a fitted PLG row whose lattice starts at the cell
+    itself: sum_{k>0} |beta_k| / (-beta_0) when the cell's own coefficient is
+    negative (the sign of the operator's diagonal), else +inf."""
+    if beta[0] >= 0.0:
+        return math.inf
+    return float(np.sum(np.abs(beta[1:]))) / float(-beta[0])
 
 
 # ----------------------------------------------------------------------------
@@ -329,9 +315,21 @@ class Level:
         self.N.sum_duplicates()
 
     def _lattice(self, i, j):
+        """S_PLG(i): of the candidate lattices, the one whose fitted row (for
+        this cell, its neighbours and B_i) is the most diagonally dominant
+        (smallest row_dominance); a key within a relative 1e-9 of the best so
+        far keeps the earlier candidate; with no negative diagonal among the
+        candidates, the first candidate."""
         win = frozenset((dx, dy) for dx in range(-4, 5) for dy in range(-4, 5)
                         if self.cg.is_active(i + dx, j + dy))
-        return select_lattice(win, (self.a, self.b, self.c))
+        cands = candidate_lattices(win)
+        best, bestv = cands[0], math.inf
+        for lat in cands:
+            beta, _ = self._fit(i, j, lat)
+            v = row_dominance(beta)
+            if v < bestv * (1.0 - 1e-9):
+                best, bestv = lat, v
+        return best
 
     def _avg_monomials(self, cell, d):
         """<((x - p)/h)^alpha>_cell for p the centre of grid cell cell - d."""

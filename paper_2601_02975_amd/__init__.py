@@ -358,10 +358,10 @@ class Server:
         self._inflight = {}
 
     def add_problem(self, grid, curves, a, b, c, eps=0.08, omega=0.5, nu=(3, 3), n_levels=0, min_coarse=16,
-                    precision=FP64, max_iters=100):
+                    precision=FP64, max_iters=100, cycle=0):
         carr, keep = _curves(curves)
         g = mg_grid(grid.x0, grid.y0, grid.h, grid.nx, grid.ny)
-        opt = _options(eps, omega, nu, n_levels, min_coarse, precision, max_iters)
+        opt = _options(eps, omega, nu, n_levels, min_coarse, precision, max_iters, cycle)
         pid = ctypes.c_int()
         _check(lib().mg_server_add_problem(self.h, ctypes.byref(g), len(curves), carr, a, b, c, ctypes.byref(opt),
                                            ctypes.byref(pid)), "mg_server_add_problem")

@@ -1,8 +1,11 @@
 // One level's linear system (Section 4): SFV/PLG classification
 // (Definition 4.1), SFV rows with ghost cells eliminated (Section 4.1), poised
-// lattices (Definitions 4.2-4.3) and the inputs of the weighted minimum-norm
-// fits (eqs. (4.10)-(4.18)); the fits themselves run on the GPU.
+// lattices (Definitions 4.2-4.3; candidates ranked by a host fit of the
+// actual row) and the inputs of the weighted minimum-norm fits
+// (eqs. (4.10)-(4.18)); the fits used by the solver run on the GPU.
+
 #include <algorithm>
+#include <map>
 #include <array>
 #include <cmath>
 #include <cstring>
@@ -226,65 +229,73 @@ double angle_of(int x, int y) {
     return t;
 }
 
-// LU solve with partial pivoting, n <= 15
-bool dense_solve(int n, double *A, double *b) {
-    std::vector<int> piv(n);
-    for (int k = 0; k < n; ++k) {
-        int p = k;
-        for (int r = k + 1; r < n; ++r)
-            if (std::fabs(A[r * n + k]) > std::fabs(A[p * n + k])) p = r;
-        if (A[p * n + k] == 0.0) return false;
-        if (p != k) {
-            for (int c = 0; c < n; ++c) std::swap(A[k * n + c], A[p * n + c]);
-            std::swap(b[k], b[p]);
-        }
-        for (int r = k + 1; r < n; ++r) {
-            double f = A[r * n + k] / A[k * n + k];
-            for (int c = k; c < n; ++c) A[r * n + c] -= f * A[k * n + c];
-            b[r] -= f * b[k];
+// Weighted minimum-norm fit of eqs. (4.16)-(4.18) on the host, used to rank
+// candidate lattices: beta = W^{1/2} gamma with gamma the minimum-2-norm
+// solution of (M W^{1/2}) gamma = phibar, W = diag(1 / w_k).  M is column-major
+// (NB rows, ncol columns).  Householder QR of (M W^{1/2})^T = Q R, then
+// gamma = Q R^{-T} phibar.  Returns false for a rank-deficient M.
+bool host_fit(int ncol, const double *M, const double *phi, const double *w, double *beta) {
+    double A[(NB + 1) * NB];                      // A[k * NB + q] = M[q, k] / sqrt(w_k)
+    double v[NB][NB + 1], tau[NB];
+    for (int k = 0; k < ncol; ++k)
+        for (int q = 0; q < NB; ++q) A[k * NB + q] = M[(size_t)k * NB + q] / std::sqrt(w[k]);
+    for (int q = 0; q < NB; ++q) {
+        double nrm = 0.0;
+        for (int k = q; k < ncol; ++k) nrm += A[k * NB + q] * A[k * NB + q];
+        nrm = std::sqrt(nrm);
+        if (nrm == 0.0) return false;
+        double alpha = A[q * NB + q] > 0 ? -nrm : nrm;
+        for (int k = 0; k < ncol; ++k) v[q][k] = k < q ? 0.0 : A[k * NB + q];
+        v[q][q] -= alpha;
+        double vv = 0.0;
+        for (int k = q; k < ncol; ++k) vv += v[q][k] * v[q][k];
+        tau[q] = vv > 0.0 ? 2.0 / vv : 0.0;
+        for (int c = q; c < NB; ++c) {
+            double d = 0.0;
+            for (int k = q; k < ncol; ++k) d += v[q][k] * A[k * NB + c];
+            d *= tau[q];
+            for (int k = q; k < ncol; ++k) A[k * NB + c] -= d * v[q][k];
         }
     }
-    for (int k = n - 1; k >= 0; --k) {
-        double s = b[k];
-        for (int c = k + 1; c < n; ++c) s -= A[k * n + c] * b[c];
-        b[k] = s / A[k * n + k];
+    // R^T z = phibar (R = upper triangle of A's first NB rows)
+    double g[NB + 1] = {};
+    for (int q = 0; q < NB; ++q) {
+        double s = phi[q];
+        for (int k = 0; k < q; ++k) s -= A[k * NB + q] * g[k];
+        if (A[q * NB + q] == 0.0) return false;
+        g[q] = s / A[q * NB + q];
     }
+    // gamma = H_0 ... H_{NB-1} [z; 0]
+    for (int q = NB - 1; q >= 0; --q) {
+        double d = 0.0;
+        for (int k = q; k < ncol; ++k) d += v[q][k] * g[k];
+        d *= tau[q];
+        for (int k = q; k < ncol; ++k) g[k] -= d * v[q][k];
+    }
+    for (int k = 0; k < ncol; ++k) beta[k] = g[k] / std::sqrt(w[k]);
     return true;
 }
 
-// ||beta||^2_{W^{-1}} of the full-cell fit on a lattice (eqs. (4.14), (4.17))
-double regular_fit_norm(const std::vector<std::array<int, 2>> &lat, double a, double b, double c) {
-    double full[NB];
-    full_moments(full);
-    double M[NB * NB], rhs[NB];
-    for (int k = 0; k < NB; ++k) {
-        double sh[NB];
-        shift_moments(full, lat[k][0], lat[k][1], sh);
-        for (int r = 0; r < NB; ++r) M[r * NB + k] = sh[r];
-    }
-    for (int r = 0; r < NB; ++r) {
-        int p = MONO_P[r], q = MONO_Q[r];
-        double s = 0.0;
-        if (p >= 2) s += a * p * (p - 1) * full[mono_index(p - 2, q)];
-        if (p >= 1 && q >= 1) s += b * p * q * full[mono_index(p - 1, q - 1)];
-        if (q >= 2) s += c * q * (q - 1) * full[mono_index(p, q - 2)];
-        rhs[r] = s;
-    }
-    if (!dense_solve(NB, M, rhs)) return INFINITY;
-    double v = 0.0;
-    for (int k = 0; k < NB; ++k) v += std::max(std::hypot((double)lat[k][0], (double)lat[k][1]), 0.5) * rhs[k] * rhs[k];
-    return v;
+// Ranking key of a fitted row whose lattice starts at the cell itself:
+// sum_{k>0} |beta_k| / (-beta_0) when the cell's own coefficient is negative
+// (the sign of the operator's diagonal), else +inf.
+double row_dominance(const double *beta) {
+    if (!(beta[0] < 0.0)) return INFINITY;
+    double s = 0.0;
+    for (int k = 1; k < NB; ++k) s += std::fabs(beta[k]);
+    return s / -beta[0];
 }
 
 }  // namespace
 
-// Lattice S_PLG(i): K = active cells of the 7x7 box centred at i (9x9 if no
-// poised subset exists).  For each of the 8 grid symmetries g, take nodes
-// nearest-first by (|d|^2, angle of g(d) in [0, 2pi)) when they raise the
-// exact rank of the point-sample matrix [d^alpha], |alpha| <= 4, until 15.
-// Keep the lattice of smallest full-cell ||beta||_{W^{-1}}; ties within a
-// relative 1e-9 keep the earlier symmetry.
-std::vector<std::array<int, 2>> Level::lattice(int i, int j, LatticeMemo &memo) const {
+// Candidate lattices S_PLG(i) (Definitions 4.2-4.3): K = active cells of the
+// 7x7 box centred at i (9x9 if no poised subset exists).  For each of the 8
+// grid symmetries g, take nodes nearest-first by (|d|^2, angle of g(d) in
+// [0, 2pi)) when they raise the exact rank of the point-sample matrix
+// [d^alpha], |alpha| <= 4, until 15.  Distinct lattices in symmetry order;
+// each starts with d = (0, 0).
+// the 9x9 activity pattern around (i, j): the candidates depend on nothing else
+__uint128_t Level::lattice_key(int i, int j) const {
     const int nx = g.nx, ny = g.ny;
     __uint128_t key = 0;
     for (int dy = -4; dy <= 4; ++dy)
@@ -293,12 +304,14 @@ std::vector<std::array<int, 2>> Level::lattice(int i, int j, LatticeMemo &memo) 
             bool act = qi >= 0 && qi < nx && qj >= 0 && qj < ny && cg.active[(size_t)qj * nx + qi];
             key = (key << 1) | (act ? 1 : 0);
         }
-    auto it = memo.find(key);
-    if (it != memo.end()) return it->second;
+    return key;
+}
+
+std::vector<std::vector<std::array<int, 2>>> Level::lattice_candidates(int i, int j) const {
+    const int nx = g.nx, ny = g.ny;
     static const int SYM[8][4] = {{1, 0, 0, 1}, {0, -1, 1, 0}, {-1, 0, 0, -1}, {0, 1, -1, 0},
                                   {1, 0, 0, -1}, {0, 1, 1, 0}, {-1, 0, 0, 1}, {0, -1, -1, 0}};
-    std::vector<std::array<int, 2>> best;
-    double bestv = 0.0;
+    std::vector<std::vector<std::array<int, 2>>> out;
     for (int half : {3, 4}) {
         std::vector<std::array<int, 2>> box;
         for (int dy = -half; dy <= half; ++dy)
@@ -319,21 +332,20 @@ std::vector<std::array<int, 2>> Level::lattice(int i, int j, LatticeMemo &memo) 
                 if ((int)lat.size() == NB) break;
             }
             if ((int)lat.size() < NB) continue;
-            double v = regular_fit_norm(lat, a, b, c);
-            if (best.empty() || v < bestv * (1.0 - 1e-9)) {
-                best = lat;
-                bestv = v;
-            }
+            if (std::find(out.begin(), out.end(), lat) == out.end()) out.push_back(lat);
         }
-        if (!best.empty()) break;
+        if (!out.empty()) break;
     }
-    if (best.empty()) fail(MG_ERR_GEOMETRY, "no poised lattice for a PLG cell");
-    memo[key] = best;
-    return best;
+    if (out.empty()) fail(MG_ERR_GEOMETRY, "no poised lattice for a PLG cell");
+    return out;
 }
 
 // ---------------------------------------------------------------------------
-// fit inputs: M (15 x ncol, column-major per cell), phibar, weights
+// fit inputs: M (15 x ncol, column-major per cell), phibar, weights.  The
+// lattice of each PLG cell is the candidate whose fitted row (host fit of the
+// actual cell, its neighbours and B_i) has the smallest row_dominance; a key
+// within a relative 1e-9 of the best so far keeps the earlier candidate, and
+// with no negative own coefficient among them the first candidate is kept.
 void Level::fit_inputs(std::vector<double> &Mall, std::vector<double> &phi, std::vector<double> &wall,
                        std::vector<int> &ncol) {
     const int nx = g.nx;
@@ -344,22 +356,38 @@ void Level::fit_inputs(std::vector<double> &Mall, std::vector<double> &phi, std:
     wall.assign((size_t)m * (NB + 1), 0.0);
     ncol.assign(m, NB);
     lattices.resize(m);
-    LatticeMemo memo;
+    // candidates: one search per distinct activity pattern, in parallel
+    std::vector<__uint128_t> keys(m);
+#pragma omp parallel for schedule(static)
+    for (int r = 0; r < m; ++r) keys[r] = lattice_key(plg_cells[r] % nx, plg_cells[r] / nx);
+    std::map<__uint128_t, int> first;                 // pattern -> first row with it
+    std::vector<int> rep;
+    for (int r = 0; r < m; ++r)
+        if (first.emplace(keys[r], r).second) rep.push_back(r);
+    std::vector<std::vector<std::vector<std::array<int, 2>>>> found(rep.size());
+    int failed = 0;
+#pragma omp parallel for schedule(dynamic)
+    for (int k = 0; k < (int)rep.size(); ++k) {
+        try {
+            found[k] = lattice_candidates(plg_cells[rep[k]] % nx, plg_cells[rep[k]] / nx);
+        } catch (const status_error &) {
+#pragma omp atomic write
+            failed = 1;
+        }
+    }
+    if (failed) fail(MG_ERR_GEOMETRY, "no poised lattice for a PLG cell");
+    std::map<__uint128_t, int> slot;
+    for (int k = 0; k < (int)rep.size(); ++k) slot[keys[rep[k]]] = k;
+    std::vector<int> cand_of(m);
+    for (int r = 0; r < m; ++r) cand_of[r] = slot[keys[r]];
     std::vector<double> gx, gw;
     gauss_legendre(16, gx, gw);
+#pragma omp parallel for schedule(dynamic, 16)
     for (int r = 0; r < m; ++r) {
         int cell = plg_cells[r];
         int i = cell % nx, j = cell / nx;
-        lattices[r] = lattice(i, j, memo);
         double *M = &Mall[(size_t)r * NB * (NB + 1)];
-        for (int k = 0; k < NB; ++k) {
-            int qi = i + lattices[r][k][0], qj = j + lattices[r][k][1];
-            double mom[NB], sh[NB];
-            cell_moments(cg, qi, qj, mom);
-            shift_moments(mom, lattices[r][k][0], lattices[r][k][1], sh);
-            for (int q = 0; q < NB; ++q) M[(size_t)k * NB + q] = sh[q] / mom[0];
-            wall[(size_t)r * (NB + 1) + k] = std::max(std::hypot((double)lattices[r][k][0], (double)lattices[r][k][1]), 0.5);
-        }
+        double *w = &wall[(size_t)r * (NB + 1)];
         double mom[NB];
         cell_moments(cg, i, j, mom);
         for (int q = 0; q < NB; ++q) {
@@ -399,9 +427,35 @@ void Level::fit_inputs(std::vector<double> &Mall, std::vector<double> &phi, std:
                 }
             }
             for (int q = 0; q < NB; ++q) M[(size_t)NB * NB + q] = tot[q] / len;
-            wall[(size_t)r * (NB + 1) + NB] = 0.5;
+            w[NB] = 0.5;
             ncol[r] = NB + 1;
         }
+        // rank the candidates by their fitted rows
+        auto load = [&](const std::vector<std::array<int, 2>> &lat) {
+            for (int k = 0; k < NB; ++k) {
+                int qi = i + lat[k][0], qj = j + lat[k][1];
+                double mk[NB], sh[NB];
+                cell_moments(cg, qi, qj, mk);
+                shift_moments(mk, lat[k][0], lat[k][1], sh);
+                for (int q = 0; q < NB; ++q) M[(size_t)k * NB + q] = sh[q] / mk[0];
+                w[k] = std::max(std::hypot((double)lat[k][0], (double)lat[k][1]), 0.5);
+            }
+        };
+        const auto &cands = found[cand_of[r]];
+        int best = 0;
+        double bestv = INFINITY;
+        for (int cidx = 0; cidx < (int)cands.size() && cands.size() > 1; ++cidx) {
+            load(cands[cidx]);
+            double beta[NB + 1];
+            if (!host_fit(ncol[r], M, &phi[(size_t)r * NB], w, beta)) continue;
+            double v = row_dominance(beta);
+            if (v < bestv * (1.0 - 1e-9)) {
+                best = cidx;
+                bestv = v;
+            }
+        }
+        lattices[r] = cands[best];
+        load(cands[best]);
     }
 }
 

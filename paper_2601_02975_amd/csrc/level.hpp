@@ -10,8 +10,6 @@
 
 namespace mgc {
 
-using LatticeMemo = std::map<__uint128_t, std::vector<std::array<int, 2>>>;
-
 void ghost_weights(int bc, int which, double w[5]);
 void corner_weights(int bcx, int bcy, int m, int k, double h, double wu[4][4], double wgy[4], double wgx[4]);
 
@@ -32,7 +30,8 @@ struct Level {
 
     int face_index(int side, int k) const;
     void classify();
-    std::vector<std::array<int, 2>> lattice(int i, int j, LatticeMemo &memo) const;
+    __uint128_t lattice_key(int i, int j) const;
+    std::vector<std::vector<std::array<int, 2>>> lattice_candidates(int i, int j) const;
     void fit_inputs(std::vector<double> &M, std::vector<double> &phi, std::vector<double> &w, std::vector<int> &ncol);
     void sfv_row(int i, int j, std::vector<std::pair<int, double>> &cells,
                  std::vector<std::pair<int, double>> &gdat) const;

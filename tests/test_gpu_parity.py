@@ -140,8 +140,15 @@ def test_residual_parity(name):
         want = b - L.A @ u
         rd = to_dev(L, np.zeros(L.n))
         nrm = S.residual(l, to_dev(L, b), to_dev(L, u), rd)
-        assert rel(from_dev(L, rd), want) <= 1e-13
-        assert nrm == pytest.approx(np.abs(want).max(), rel=1e-13)
+        # rounding of the stencil sums (16 eps of |b| + |A||u|), plus the
+        # fitted PLG coefficients, which match the oracle's to the setup
+        # parity bound of 1e-12 relative (eqs. (4.16)-(4.18): QR on the GPU,
+        # SVD in the oracle)
+        au = abs(L.A) @ np.abs(u)
+        bound = 16 * np.finfo(float).eps * (np.abs(b) + au) + 1e-12 * au * L.is_plg
+        got = from_dev(L, rd)
+        assert np.all(np.abs(got - want) <= bound)
+        assert abs(nrm - np.abs(want).max()) <= bound.max()
 
 
 @pytest.mark.parametrize("name", list(CASES))
