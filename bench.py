@@ -81,7 +81,8 @@ def cpu_baseline(P, gpu_iters, sample_cycles, cycle):
     from oracle.rhs import rhs
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        H = Hierarchy(P.grid, P.curves, P.a, P.b, P.c, P.eps)
+        H = Hierarchy(P.grid, P.curves, P.a, P.b, P.c, P.eps,
+                      progress=lambda msg: print("oracle setup: " + msg, file=sys.stderr, flush=True))
         t_setup = time.perf_counter() - t0
         b, _, _ = rhs(H.levels[0], P.solution)
         A = H.levels[0].A
@@ -112,8 +113,7 @@ def serving_leg(torch, mg, W, n, n_geom, n_rhs, qps, slots, tol):
     rng = np.random.default_rng(12345)
     order = rng.permutation(len(reqs))
     gaps = rng.exponential(1.0 / qps, size=len(reqs))
-    seq = {p: [mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=p, max_iters=1000,
-                         cycle=mg.CYCLE_FMG) for P in geoms]
+    seq = {p: [mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=p, max_iters=1000) for P in geoms]
            for p in (mg.FP64, mg.MIXED)}
     inputs = []
     for k, P in reqs:
@@ -131,8 +131,8 @@ def serving_leg(torch, mg, W, n, n_geom, n_rhs, qps, slots, tol):
         for S in seq[p]:
             S.close()
     srv = mg.Server(max_active=slots, hbm_budget=64 << 30)
-    pids = [srv.add_problem(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=mg.MIXED, max_iters=1000,
-                            cycle=mg.CYCLE_FMG) for P in geoms]
+    pids = [srv.add_problem(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=mg.MIXED, max_iters=1000)
+            for P in geoms]
     warm = []
     for k in range(n_geom):                        # setup of every hierarchy (not timed)
         f, g = inputs[k * n_rhs]
@@ -152,8 +152,8 @@ def serving_leg(torch, mg, W, n, n_geom, n_rhs, qps, slots, tol):
     lat = sorted(r["latency_s"] for r in res)
     pct = lambda q: lat[min(len(lat) - 1, int(math.ceil(q * len(lat))) - 1)]
     return {"workload": "%d three-disk geometries (seeds 1-%d) at %d^2, resident after one warm-up request each; "
-                        "%d right-hand sides per geometry arriving as a Poisson process at %g/s; %d slots; FMG in mixed "
-                        "precision to %g" % (n_geom, n_geom, n, n_rhs, qps, slots, tol),
+                        "%d right-hand sides per geometry arriving as a Poisson process at %g/s; %d slots; V-cycles in "
+                        "mixed precision to %g (faster than FMG at this size)" % (n_geom, n_geom, n, n_rhs, qps, slots, tol),
             "requests": len(reqs), "failed": sum(r["status"] != 0 for r in res),
             "p50_latency_s": pct(0.50), "p99_latency_s": pct(0.99), "solves_per_s": len(reqs) / t_all,
             "sequential_mixed_solves_per_s": seq_rate["mixed"], "sequential_fp64_solves_per_s": seq_rate["fp64"],

@@ -156,15 +156,20 @@ def row_dominance(beta):
 class Level:
     """Cut cells, classification and the assembled system of one grid."""
 
-    def __init__(self, grid, curves, a, b, c, eps, omega=0.5):
+    def __init__(self, grid, curves, a, b, c, eps, omega=0.5, progress=None):
+        """progress: optional callable(str) told when each stage is done."""
         self.grid = grid
         self.a, self.b, self.c = float(a), float(b), float(c)
         self.h, self.nx, self.ny = grid.h, grid.nx, grid.ny
         self.curves = curves
+        note = progress or (lambda msg: None)
         self.cg = CutGrid(grid, curves, eps)
+        note("%dx%d: cut cells" % (grid.nx, grid.ny))
         self._classify()
         self._index()
+        note("%dx%d: classification" % (grid.nx, grid.ny))
         self._assemble()
+        note("%dx%d: assembly" % (grid.nx, grid.ny))
 
     # -- Definition 4.1 ---------------------------------------------------------
     def _classify(self):

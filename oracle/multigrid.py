@@ -42,10 +42,11 @@ class _Grid:
 
 
 class Hierarchy:
-    def __init__(self, grid, curves, a, b, c, eps, n_levels=0, omega=0.5, nu=(3, 3), min_cells=16):
+    def __init__(self, grid, curves, a, b, c, eps, n_levels=0, omega=0.5, nu=(3, 3), min_cells=16,
+                 progress=None):
         self.omega = float(omega)
         self.nu1, self.nu2 = nu
-        self.levels = [Level(grid, curves, a, b, c, eps)]
+        self.levels = [Level(grid, curves, a, b, c, eps, progress=progress)]
         while n_levels == 0 or len(self.levels) < n_levels:
             g = self.levels[-1].grid
             if g.nx % 2 or g.ny % 2 or g.nx // 2 < min_cells or g.ny // 2 < min_cells:
@@ -54,7 +55,7 @@ class Hierarchy:
                 break
             cg = _Grid(g.x0, g.y0, 2 * g.h, g.nx // 2, g.ny // 2)
             try:
-                self.levels.append(Level(cg, curves, a, b, c, eps))
+                self.levels.append(Level(cg, curves, a, b, c, eps, progress=progress))
             except GeometryError:
                 if n_levels:
                     raise
