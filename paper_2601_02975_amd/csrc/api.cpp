@@ -270,7 +270,7 @@ void upload_level(mg_handle h, int l, bool last, hipStream_t st) {
     D.rplg64 = h->alloc<double>(S.m);
     D.rplg32 = h->alloc<float>(S.m);
     PlgPlan G;
-    build_plg_plan(L, S, nx, PLG_SLICE, PLG_LMAX, PLG_SEP_ROWS, G);
+    build_plg_plan(L, S, nx, PLG_SLICE, PLG_B_ROWS, PLG_LMAX, PLG_SEP_ROWS, G);
     if (G.hmax > PLG_HMAX || G.lmax > PLG_LMAX || G.kmax > PLG_KMAX || S.nsep > PLG_SMAX)
         fail(MG_ERR_UNSUPPORTED, "PLG block partition exceeds the LDS staging limits");
     int *grp_start = h->upload(G.grp_start), *hptr = h->upload(G.hptr), *hcell = h->upload(G.hcell);

@@ -126,7 +126,7 @@ __device__ __forceinline__ T sfv_global(const LevelArgs &L, const T *__restrict_
 }
 
 constexpr int TX = 64, TY = 32, HX = TX + 4, HY = TY + 4, NT = 256;
-static_assert(PLG_SLICE <= NT, "launch B holds one segment row per thread");
+static_assert(PLG_SLICE <= NT && PLG_B_ROWS <= NT, "launch B holds one segment row per thread");
 
 // Loads the (TY+4) x (TX+4) tile with halo into LDS from in-box values
 // at(i, j); halo positions outside the box get ghost values.  A block at the
@@ -268,16 +268,16 @@ template <typename T, bool MIXED, int TYv>
 __device__ __forceinline__ void jacobi_tile(const LevelArgs &L, const T *__restrict__ uold, const T *__restrict__ b,
                                             T *__restrict__ unew, const uint8_t *__restrict__ mask, bool uzero,
                                             int i0, int j0, T (*s)[HX], double *gws) {
-    constexpr int R = TYv / (NT / TX);           // rows per thread
+    constexpr int R = TYv / (NT / TX);           // consecutive rows per thread
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-    const int i = i0 + tx;
+    const int i = i0 + tx, r0 = ty * R;
     // the per-cell loads are issued before the tile barrier so that their
     // latency overlaps the tile load
     uint8_t mk[R];
     T bv[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-        const int j = j0 + ty + k * (NT / TX);
+        const int j = j0 + r0 + k;
         const bool in = i < L.nx && j < L.ny;
         const size_t id = pidx(L, in ? i : 0, in ? j : 0);
         mk[k] = in ? mask[id] : 0;
@@ -287,19 +287,31 @@ __device__ __forceinline__ void jacobi_tile(const LevelArgs &L, const T *__restr
     if (uzero) {
 #pragma unroll
         for (int k = 0; k < R; ++k)
-            if (mk[k] == 1) unew[pidx(L, i, j0 + ty + k * (NT / TX))] = wod * bv[k];
+            if (mk[k] == 1) unew[pidx(L, i, j0 + r0 + k)] = wod * bv[k];
         return;
     }
     auto uat = [&](int a, int c) { return uold[pidx(L, a, c)]; };
     load_tile<T, decltype(uat), TYv>(s, gws, uat, L, i0, j0);
     __syncthreads();
+    // a 5 x 5 window of the tile slides down the thread's column: one new
+    // row of 5 LDS values per cell instead of the whole stencil
+    const int lx = tx + 2;
+    T w[5][5];
+#pragma unroll
+    for (int a = 1; a < 5; ++a)
+#pragma unroll
+        for (int c = 0; c < 5; ++c) w[a][c] = s[r0 + a - 1][lx - 2 + c];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 5; ++c) w[a][c] = w[a + 1][c];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) w[4][c] = s[r0 + k + 4][lx - 2 + c];
         if (mk[k] != 1) continue;
-        const int r = ty + k * (NT / TX);
-        const int lx = tx + 2, ly = r + 2;
-        T au = apply_sfv<T, MIXED>(L, [&](int dx, int dy) { return s[ly + dy][lx + dx]; });
-        unew[pidx(L, i, j0 + r)] = s[ly][lx] + wod * (bv[k] - au);
+        T au = apply_sfv<T, MIXED>(L, [&](int dx, int dy) { return w[dy + 2][dx + 2]; });
+        unew[pidx(L, i, j0 + r0 + k)] = w[2][2] + wod * (bv[k] - au);
     }
 }
 
@@ -418,6 +430,23 @@ __global__ __launch_bounds__(NT) void k_smooth_a(LevelArgs L, const T *__restric
         return;
     }
     plg_group<T, MIXED>(L, uold, b, unew, uzero != 0, P, bid - ntile, reinterpret_cast<T *>(smem));
+}
+
+// Launch A on large grids, tile role alone: it needs far fewer registers
+// than the PLG role (about 55 against 145 VGPRs in FP32), so a kernel of its
+// own keeps more waves per SIMD in flight to cover the memory latency; the
+// PLG groups follow as k_smooth_a with no tiles.
+constexpr long long SPLIT_CELLS = 2048LL * 2048;
+
+template <typename T, bool MIXED, int TYv>
+__global__ __launch_bounds__(NT) void k_smooth_tiles(LevelArgs L, const T *__restrict__ uold,
+                                                     const T *__restrict__ b, T *__restrict__ unew,
+                                                     const uint8_t *__restrict__ mask, int tiles_x, int uzero) {
+    __shared__ __align__(16) T smem[(TYv + 4) * HX];
+    __shared__ double gws[32];
+    const int bid = blockIdx.x;
+    jacobi_tile<T, MIXED, TYv>(L, uold, b, unew, mask, uzero != 0, (bid % tiles_x) * TX, (bid / tiles_x) * TYv,
+                               reinterpret_cast<T(*)[HX]>(smem), gws);
 }
 
 // Launch B: r_S = t_S - A_SB y (every block forms all of it in LDS), then
@@ -839,8 +868,25 @@ void launch_smooth_a(const LevelArgs &L, const T *uold, const T *b, T *unew, con
     const bool small = (long long)L.nx * L.ny <= small_grid_cells<T>();
     const int ty = small ? TY_SMALL : TY;
     const int tiles_x = (L.nx + TX - 1) / TX, ntile = tiles_x * ((L.ny + ty - 1) / ty);
-    const dim3 grid(ntile + P.nblk1);
     const int uz = uzero ? 1 : 0;
+    if (!small && (long long)L.nx * L.ny >= SPLIT_CELLS) {
+        // the two roles write disjoint cells (SFV tiles, PLG rows)
+        if (L.mixed)
+            hipLaunchKernelGGL((k_smooth_tiles<T, true, TY>), dim3(ntile), dim3(NT), 0, st, L, uold, b, unew, mask,
+                               tiles_x, uz);
+        else
+            hipLaunchKernelGGL((k_smooth_tiles<T, false, TY>), dim3(ntile), dim3(NT), 0, st, L, uold, b, unew, mask,
+                               tiles_x, uz);
+        if (P.nblk1 == 0) return;
+        if (L.mixed)
+            hipLaunchKernelGGL((k_smooth_a<T, true, TY>), dim3(P.nblk1), dim3(NT), 0, st, L, uold, b, unew, mask,
+                               tiles_x, 0, uz, P);
+        else
+            hipLaunchKernelGGL((k_smooth_a<T, false, TY>), dim3(P.nblk1), dim3(NT), 0, st, L, uold, b, unew, mask,
+                               tiles_x, 0, uz, P);
+        return;
+    }
+    const dim3 grid(ntile + P.nblk1);
 #define MG_SA(MX, TYV) \
     hipLaunchKernelGGL((k_smooth_a<T, MX, TYV>), grid, dim3(NT), 0, st, L, uold, b, unew, mask, tiles_x, ntile, uz, P)
     if (L.mixed) { if (small) MG_SA(true, TY_SMALL); else MG_SA(true, TY); }

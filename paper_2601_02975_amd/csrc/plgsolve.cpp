@@ -310,8 +310,8 @@ void build_plg_solver(const Level &L, int seg_max, PlgSolver &S) {
 
 namespace mgc {
 
-void build_plg_plan(const Level &L, const PlgSolver &S, int nx, int slice, int sep_group, int sep_rows,
-                    PlgPlan &P) {
+void build_plg_plan(const Level &L, const PlgSolver &S, int nx, int slice, int bslice, int sep_group,
+                    int sep_rows, PlgPlan &P) {
     P = PlgPlan();
     const int m = S.m;
     auto padded = [nx](int cell) { return (cell / nx + 2) * (nx + 4) + (cell % nx + 2); };
@@ -421,11 +421,13 @@ void build_plg_plan(const Level &L, const PlgSolver &S, int nx, int slice, int s
             b.ce0 = P.ce_ptr[b.g];
             b.ce1 = P.ce_ptr[b.g + 1];
         }
-    // launch B blocks: the segment slices, then separator rows in runs
+    // launch B blocks: the segments in slices of bslice rows, then separator
+    // rows in runs (more blocks shorten the longest block's dense products,
+    // which bound the launch, although each block forms all of r_S)
     for (int j = 0; j < S.nseg; ++j)
-        for (int r = S.seg_start[j]; r < S.seg_start[j + 1]; r += slice) {
+        for (int r = S.seg_start[j]; r < S.seg_start[j + 1]; r += bslice) {
             PlgBlkB b{};
-            b.kind = 0; b.j = j; b.r0 = r; b.r1 = std::min(S.seg_start[j + 1], r + slice);
+            b.kind = 0; b.j = j; b.r0 = r; b.r1 = std::min(S.seg_start[j + 1], r + bslice);
             b.kj = S.fcols_ptr[j + 1] - S.fcols_ptr[j]; b.s0 = S.seg_start[j]; b.Lj = S.seg_start[j + 1] - S.seg_start[j];
             b.sj_off = P.sj_off[j]; b.ft_off = P.ft_off[j];
             P.blk2.push_back(b);

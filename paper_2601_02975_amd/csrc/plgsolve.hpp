@@ -62,7 +62,7 @@ struct PlgPlan {
     int hmax = 0, lmax = 0, kmax = 0;
 };
 
-void build_plg_plan(const Level &L, const PlgSolver &S, int nx, int slice, int sep_group, int sep_rows,
-                    PlgPlan &P);
+void build_plg_plan(const Level &L, const PlgSolver &S, int nx, int slice, int bslice, int sep_group,
+                    int sep_rows, PlgPlan &P);
 
 }  // namespace mgc

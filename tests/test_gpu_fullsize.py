@@ -2,7 +2,9 @@
 three-disk workload), against the oracle: classification of every level and
 fitted coefficients of sampled PLG rows, one V-cycle from zero on every cell,
 and the oracle's own residual of the GPU solutions (FP64 and mixed) at the
-tolerance of the benchmark."""
+tolerance of the benchmark; and the 4096 x 4096 star workload, too large for
+the oracle, through a manufactured solution its discretization reproduces
+exactly."""
 import functools
 
 import numpy as np
@@ -99,3 +101,65 @@ def test_full_size_solve_residual(precision):
     rr = np.abs(r).max() / np.abs(bg).max()
     print("%s: %d iterations, GPU rel %.3e, CPU rel %.3e" % ("mixed" if precision else "fp64", it, rel, rr))
     assert rr <= 1e-10 * 1.01 + 1e-12
+
+
+POLY3 = {(0, 0): 0.3, (1, 0): -0.7, (0, 1): 0.2, (2, 0): 0.5, (1, 1): -0.4, (0, 2): 0.9, (3, 0): 0.25,
+         (2, 1): -0.6, (1, 2): 0.35, (0, 3): -0.45}
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_star4096_cubic_solution(precision):
+    """The 4096 x 4096 star workload (Robin (1, 0.5) on the star, a=2, b=-1,
+    c=1) at its full size, with a cubic manufactured solution: every row of
+    the discretization is exact on cubics (eq. (4.7), the PLG fits on Pi_4,
+    the corner ghosts of the cross term on Pi_3), so the discrete solution is
+    the exact cell averages u*.  First, b - A u* vanishes to rounding
+    (|A| |u*| is about 4e8 here against |b| of 2e8, so 1e-12 |b| leaves
+    room for sums of a few hundred rounding errors).  Then the solve with the
+    benchmark's setting (V-cycles, nu = (6, 6)) must reach u*:
+    |u - u*| <= |A^-1|_inf 1e-10 |b|_inf, with |A^-1|_inf <= 0.1 (the
+    continuous operator's is the maximum of the solution of L v = 1, about
+    0.05), plus the rounding of exact rows (1e-9 |u*|, as in the oracle's
+    exactness test).  Grids of 2048^2 and more run launch A as two kernels
+    (tiles, then PLG groups), so this also checks that path."""
+    torch = _torch()
+    import paper_2601_02975_amd as mg
+    base = W.star_config(0, 4096)
+    P = W.Problem(base.name, base.grid, base.curves, base.a, base.b, base.c,
+                  W.Poly(POLY3, base.a, base.b, base.c), base.eps)
+    S = mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=precision, max_iters=400, nu=(6, 6))
+    fh, gh = S.project(P.solution)
+    nx, ny, h = P.grid.nx, P.grid.ny, P.grid.h
+    # exact cell averages: 3-point Gauss-Legendre per direction on full cells
+    # (exact to degree 5), the library's cut-cell rules on cut cells
+    s, w = np.polynomial.legendre.leggauss(3)
+    ue = np.zeros((ny, nx))
+    xs = P.grid.x0 + (np.arange(nx)[:, None] + 0.5 + 0.5 * s[None, :]) * h
+    for j0 in range(0, ny, 256):
+        j1 = min(ny, j0 + 256)
+        ys = P.grid.y0 + (np.arange(j0, j1)[:, None] + 0.5 + 0.5 * s[None, :]) * h
+        vals = P.solution.u(xs[None, :, :, None], ys[:, None, None, :])
+        ue[j0:j1] = 0.25 * np.einsum("a,b,rnab->rn", w, w, vals)
+    cell, ptr, qx, qy, qw = S.cell_quadrature()
+    v = P.solution.u(qx, qy) * qw
+    ue.reshape(-1)[cell] = np.add.reduceat(v, ptr[:-1])
+    kind = S.export_level(0)[0]
+    act = (kind != 0).reshape(ny, nx)
+    f = torch.tensor(fh, device="cuda")
+    g = torch.tensor(gh, device="cuda")
+    bd = torch.zeros_like(f)
+    S.rhs(f, g, bd)
+    bmax = float(bd.abs().max())
+    ued = torch.zeros_like(f)
+    ued[2:ny + 2, 2:nx + 2] = torch.tensor(np.where(act, ue, 0.0), device="cuda")
+    tau = S.residual(0, bd, ued, torch.zeros_like(f))
+    u = torch.zeros_like(f)
+    it, rel, code = S.solve(f, g, u, 1e-10)
+    assert code == 0 and rel <= 1e-10
+    uh = u.cpu().numpy()[2:ny + 2, 2:nx + 2]
+    err = float(np.abs(uh - ue)[act].max())
+    umax = float(np.abs(ue[act]).max())
+    print("star 4096 %s: |b - A u*| %.2e, %d iterations, rel %.2e, max |u - u*| %.2e (|u*| %.2e, |b| %.2e)" % (
+        "mixed" if precision else "fp64", tau, it, rel, err, umax, bmax))
+    assert tau <= 1e-12 * bmax
+    assert err <= 0.1 * 1e-10 * bmax + 1e-9 * umax
