@@ -180,3 +180,26 @@ def test_fmg_factor_is_h_independent_and_beats_vcycle():
     assert abs(factors[(64, "FMG")] - factors[(128, "FMG")]) <= 0.05
     assert factors[(128, "FMG")] < factors[(128, "V")]
     assert factors[(128, "FMG")] < 0.5
+
+
+def test_vcycle_factor_is_h_independent_with_four_sweeps():
+    """Averaged V-cycle residual reduction on the unit square, (a,b,c) =
+    (1,0,2), coarsening to 16^2 (3, 4 and 5 levels at 64^2, 128^2, 256^2):
+    with nu = (4, 4) it is independent of h (spread <= 0.05) and in the range
+    of Table 7, as Sec. 5.4 expects of the V-cycle; with nu = (3, 3) it grows
+    with the depth (0.36, 0.52, 0.71 here), which is why the benchmark runs
+    more sweeps."""
+    factors = {}
+    for nu in ((3, 3), (4, 4)):
+        for n in (64, 128, 256):
+            P = W.unit_square_config(n, 1.0, 0.0, 2.0)
+            H = Hierarchy(P.grid, P.curves, P.a, P.b, P.c, P.eps, nu=nu)
+            b, _, _ = rhs(H.levels[0], P.solution)
+            hist = []
+            H.solve(b, tol=1e-11, max_iters=200, history=hist)
+            rels = [r for _, r in hist]
+            factors[(nu, n)] = (rels[-1] / rels[0]) ** (1.0 / (len(rels) - 1))
+    f44 = [factors[((4, 4), n)] for n in (64, 128, 256)]
+    assert max(f44) - min(f44) <= 0.05
+    assert max(f44) < 0.4
+    assert factors[((3, 3), 256)] > factors[((3, 3), 64)] + 0.2
