@@ -45,7 +45,7 @@ import scipy.sparse as sp
 
 from .geometry import (MONOS, MONO_INDEX, CutGrid, GeometryError, _GL, full_cell_moments, seg_deriv,
                        seg_normal, seg_point, shift_moments)
-from .stencil import corner_ghost_weights, ghost_weights, operator_terms
+from .stencil import corner_ghost_weights, face_ghost_weights, operator_terms
 
 NBASIS = len(MONOS)        # dim Pi_4^2 = 15
 W_MIN = 0.5                # eq. (4.17)
@@ -246,7 +246,7 @@ class Level:
                 r, cx, cy = srow[k], int(qi[k]), int(qj[k])
                 xside, m = (3, -cx) if cx < 0 else (1, cx - nx + 1)
                 yside, kk = (0, -cy) if cy < 0 else (2, cy - ny + 1)
-                wu, wgy, wgx = corner_ghost_weights(box_bc[xside][0], box_bc[yside][0], m, kk, h)
+                wu, wgy, wgx = corner_ghost_weights(box_bc[xside], box_bc[yside], m, kk, h)
                 colx = lambda p: p if xside == 3 else nx - 1 - p
                 rowy = lambda q: q if yside == 0 else ny - 1 - q
                 for p in range(4):
@@ -269,12 +269,12 @@ class Level:
                     sel = (qi >= nx) & (qj >= 0) & (qj < ny); depth = qi - nx + 1; along = qj
                 if not sel.any():
                     continue
-                bc = box_bc[side][0]
+                bc = box_bc[side]
                 for which in (1, 2):
                     s2 = sel & (depth == which)
                     if not s2.any():
                         continue
-                    gw = ghost_weights(bc, which)
+                    gw = face_ghost_weights(bc[0], bc[1], bc[2], h, which)
                     al = along[s2]
                     r = srow[s2]
                     for k in range(4):          # interior cell k steps inward
@@ -288,7 +288,7 @@ class Level:
                             ci, cj = np.full(al.shape, nx - 1 - k), al
                         rows.append(r); cols.append(self.idx[cj, ci])
                         vals.append(np.full(r.shape, w * gw[k]))
-                    fw = gw[4] * (h if bc == "N" else 1.0)
+                    fw = gw[4]
                     nrows.append(r)
                     ncols.append(np.array([self.face_index(side, int(k)) for k in al], np.int64))
                     nvals.append(np.full(r.shape, w * fw))

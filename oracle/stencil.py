@@ -22,6 +22,8 @@ and the cross derivative applies the first formula in x and then in y.
 """
 from fractions import Fraction as Fr
 
+import numpy as np
+
 # (c_i, c_{i-1}, c_{i-2}, c_{i-3}, c_face, denominator) for ghosts i+1 and i+2
 GHOST_DIRICHLET = ((-77, 43, -17, 3, 60, 12), (-505, 335, -145, 27, 300, 12))
 GHOST_NEUMANN = ((5, 9, -5, 1, 12, 10), (-15, 29, -15, 3, 12, 2))
@@ -58,6 +60,34 @@ def ghost_weights(bc, which):
     return tuple(float(Fr(v, c[5])) for v in c[:5])
 
 
+def face_ghost_weights(bc, alpha1, alpha2, h, which):
+    """(w_i, w_{i-1}, w_{i-2}, w_{i-3}, w_g) of ghost `which` (1 or 2) with the
+    face datum g entering as given: g = u on a Dirichlet face, g = du/dn on a
+    Neumann face (the tables above, face weight times h), and
+    g = alpha1 u + alpha2 du/dn on a Robin face.
+
+    Reading for Robin (Section 4.1 gives Dirichlet, Neumann and periodic
+    ghosts only): the same construction as the other two, i.e. the polynomial
+    p of degree 4 in the normal coordinate x (cell widths 1, the face at
+    x = 0, the cells i, i-1, i-2, i-3 on [-1, 0], ..., [-4, -3], the outward
+    normal along +x) whose averages over the four cells are u_i .. u_{i-3} and
+    with alpha1 p(0) + alpha2 p'(0) / h = g; the ghost is p's average over
+    [which - 1, which]."""
+    if bc in ("D", "N"):
+        w = ghost_weights(bc, which)
+        return w[:4] + (w[4] * (h if bc == "N" else 1.0),)
+
+    def avg(a, k):                      # average of x^k over [a, a + 1]
+        return ((a + 1.0) ** (k + 1) - a ** (k + 1)) / (k + 1)
+
+    M = np.zeros((5, 5))
+    for m in range(4):                  # cell i - m on [-(m + 1), -m]
+        M[m] = [avg(-(m + 1.0), k) for k in range(5)]
+    M[4, 0], M[4, 1] = alpha1, alpha2 / h
+    e = np.array([avg(which - 1.0, k) for k in range(5)])
+    return tuple(float(v) for v in np.linalg.solve(M.T, e))
+
+
 def operator_terms(a, b, c, h):
     """The SFV stencil of L = a d_xx + b d_xy + c d_yy as a list of
     ((m1, m2), weight) over offsets in [-2, 2]^2 (eq. (4.7) and the mixed term)."""
@@ -74,18 +104,17 @@ def operator_terms(a, b, c, h):
     return sorted(terms.items())
 
 
-def corner_ghost_weights(bc_x, bc_y, m, k, h):
+def corner_ghost_weights(bcx, bcy, m, k, h):
     """Weights of the corner ghost m cells beyond the x-face and k cells beyond
-    the y-face.  Returns (wu, wgy, wgx): wu[p][q] on the interior cell p steps
-    inward in x and q steps inward in y; wgy[p] on the y-face datum at the
-    column p steps inward; wgx[q] on the x-face datum at the row q steps
-    inward.  Face data are g (Dirichlet) or g = <du/dn> (Neumann)."""
-    gx = ghost_weights(bc_x, m)
-    gy = ghost_weights(bc_y, k)
-    sx = h if bc_x == "N" else 1.0
-    sy = h if bc_y == "N" else 1.0
+    the y-face; bcx, bcy: (bc, alpha1, alpha2) of the two faces.  Returns
+    (wu, wgy, wgx): wu[p][q] on the interior cell p steps inward in x and q
+    steps inward in y; wgy[p] on the y-face datum at the column p steps
+    inward; wgx[q] on the x-face datum at the row q steps inward.  Face data
+    enter as in ``face_ghost_weights``."""
+    gx = face_ghost_weights(bcx[0], bcx[1], bcx[2], h, m)
+    gy = face_ghost_weights(bcy[0], bcy[1], bcy[2], h, k)
     ex, ey = FACE_EXTRAP[m - 1], FACE_EXTRAP[k - 1]
     wu = [[gx[p] * gy[q] for q in range(4)] for p in range(4)]
-    wgy = [0.5 * gy[4] * sy * (gx[p] + ex[p]) for p in range(4)]
-    wgx = [0.5 * gx[4] * sx * (gy[q] + ey[q]) for q in range(4)]
+    wgy = [0.5 * gy[4] * (gx[p] + ex[p]) for p in range(4)]
+    wgx = [0.5 * gx[4] * (gy[q] + ey[q]) for q in range(4)]
     return wu, wgy, wgx

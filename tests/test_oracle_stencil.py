@@ -6,7 +6,7 @@ from fractions import Fraction as Fr
 import pytest
 
 from oracle.stencil import (D1, D2, GHOST_DIRICHLET, GHOST_NEUMANN, FACE_EXTRAP,
-                            corner_ghost_weights)
+                            corner_ghost_weights, face_ghost_weights)
 
 
 def cell_avg_monomial(p, k):
@@ -64,30 +64,65 @@ def test_second_derivative_not_exact_degree6():
     assert approx != 30 * cell_avg_monomial(4, 0)
 
 
+BCS = {"D": ("D", 1.0, 0.0), "N": ("N", 0.0, 1.0), "R": ("R", 1.0, 0.5), "R2": ("R", 0.3, 2.0)}
+
+
 @pytest.mark.parametrize("m,k", [(1, 1), (1, 2), (2, 1), (2, 2)])
-@pytest.mark.parametrize("bcx,bcy", [("D", "D"), ("D", "N"), ("N", "N")])
+@pytest.mark.parametrize("bcx,bcy", [("D", "D"), ("D", "N"), ("N", "N"), ("R", "D"), ("N", "R2"), ("R", "R2")])
 def test_corner_ghost_exact_bicubic(m, k, bcx, bcy):
     """A corner ghost reproduces cell averages of x^p y^q for p, q <= 3 given
     exact face data (corner at the origin, interior in x > 0, y > 0, the
-    ghost occupies [-m, -m+1] x [-k, -k+1])."""
-    wu, wgy, wgx = corner_ghost_weights(bcx, bcy, m, k, 1.0)
+    ghost occupies [-m, -m+1] x [-k, -k+1]; h = 1)."""
+    wu, wgy, wgx = corner_ghost_weights(BCS[bcx], BCS[bcy], m, k, 1.0)
+    ax1, ax2 = BCS[bcx][1], BCS[bcx][2]
+    ay1, ay2 = BCS[bcy][1], BCS[bcy][2]
     for p in range(4):
         for q in range(4 - p):
             avg = lambda cx, cy: float(cell_avg_monomial(p, cx) * cell_avg_monomial(q, cy))
-            # face data: y-face (y = 0) at column P: Dirichlet -> average of x^p 0^q,
-            # Neumann -> average of -d/dy (outward normal -y)
+
+            # face data alpha1 u + alpha2 du/dn (Dirichlet (1, 0), Neumann
+            # (0, 1)): the y-face (y = 0, outward normal -y) at column P,
+            # the x-face (x = 0, outward normal -x) at row Q
             def gy(P):
-                if bcy == "D":
-                    return float(cell_avg_monomial(p, P)) * (1.0 if q == 0 else 0.0)
-                return -float(cell_avg_monomial(p, P)) * (1.0 if q == 1 else 0.0)
+                a = float(cell_avg_monomial(p, P))
+                return ay1 * a * (1.0 if q == 0 else 0.0) - ay2 * a * (1.0 if q == 1 else 0.0)
 
             def gx(Q):
-                if bcx == "D":
-                    return float(cell_avg_monomial(q, Q)) * (1.0 if p == 0 else 0.0)
-                return -float(cell_avg_monomial(q, Q)) * (1.0 if p == 1 else 0.0)
+                a = float(cell_avg_monomial(q, Q))
+                return ax1 * a * (1.0 if p == 0 else 0.0) - ax2 * a * (1.0 if p == 1 else 0.0)
             val = sum(wu[a][b] * avg(a, b) for a in range(4) for b in range(4))
             val += sum(wgy[a] * gy(a) for a in range(4)) + sum(wgx[b] * gx(b) for b in range(4))
             assert val == pytest.approx(avg(-m, -k), abs=1e-9)
+
+
+@pytest.mark.parametrize("which", [1, 2])
+@pytest.mark.parametrize("alpha1,alpha2,h", [(1.0, 0.5, 1.0 / 64), (0.3, 2.0, 1.0 / 8), (2.0, 0.01, 0.5)])
+def test_robin_ghost_exact_degree4(which, alpha1, alpha2, h):
+    """The Robin ghost (reading of Sec. 4.1: the degree-4 reconstruction with
+    alpha1 u + alpha2 du/dn as the face condition) reproduces the ghost
+    average of every monomial of degree <= 4 in the physical normal
+    coordinate X = h x (face at X = 0, outward normal +X)."""
+    w = face_ghost_weights("R", alpha1, alpha2, h, which)
+    for p in range(5):
+        # X^p = h^p x^p: cell averages scale by h^p, d/dX at 0 is 1 for p = 1
+        interior = [h ** p * float(cell_avg_monomial(p, -1 - m)) for m in range(4)]
+        g = alpha1 * (1.0 if p == 0 else 0.0) + alpha2 * (1.0 if p == 1 else 0.0)
+        val = sum(c * v for c, v in zip(w[:4], interior)) + w[4] * g
+        assert val == pytest.approx(h ** p * float(cell_avg_monomial(p, which - 1)), abs=1e-11 * max(1.0, h ** p))
+
+
+@pytest.mark.parametrize("which", [1, 2])
+def test_robin_ghost_reduces_to_the_printed_formulas(which):
+    """alpha2 = 0 gives the Dirichlet ghost, alpha1 = 0 the Neumann ghost
+    (whose face weight multiplies h g)."""
+    h = 1.0 / 32
+    d = GHOST_DIRICHLET[which - 1]
+    n = GHOST_NEUMANN[which - 1]
+    wd = face_ghost_weights("R", 1.0, 0.0, h, which)
+    wn = face_ghost_weights("R", 0.0, 1.0, h, which)
+    assert wd == pytest.approx([v / d[5] for v in d[:5]], abs=1e-12)
+    assert wn[:4] == pytest.approx([v / n[5] for v in n[:4]], abs=1e-12)
+    assert wn[4] == pytest.approx(n[4] / n[5] * h, abs=1e-14)
 
 
 def test_face_extrapolation_cubic():
