@@ -10,7 +10,9 @@
  *  - Omega is the grid box minus holes.  curves[0] must be the grid box
  *    itself, counter-clockwise, one line segment per side (bottom, right,
  *    top, left), each carrying the boundary condition of that side
- *    (Dirichlet or Neumann).  curves[1..] are holes made of line segments
+ *    (Dirichlet, Neumann or Robin; the Robin ghost cells are the degree-4
+ *    reconstruction of Section 4.1 with the Robin condition at the face).
+ *    curves[1..] are holes made of line segments
  *    and circular arcs, closed, clockwise (Omega on the left, Section 2),
  *    strictly inside the box.
  *  - Cell arrays (f, u, b, r) are row-major with a halo of 2 cells on each
@@ -55,7 +57,8 @@ typedef enum {
     MG_ERR_DIVERGED = -5,      /* residual grew for 3 iterations or became NaN */
     MG_ERR_OOM = -6,           /* device allocation failed */
     MG_ERR_HIP = -7,           /* a HIP runtime call failed */
-    MG_ERR_UNSUPPORTED = -8    /* e.g. a Robin condition on a box side */
+    MG_ERR_UNSUPPORTED = -8    /* e.g. a PLG row wider than the kernels' row width, a coarsest
+                                  level too large for the dense bottom solve */
 } mg_status;
 
 typedef enum { MG_BC_DIRICHLET = 0, MG_BC_NEUMANN = 1, MG_BC_ROBIN = 2 } mg_bc;

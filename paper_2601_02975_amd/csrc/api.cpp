@@ -135,7 +135,6 @@ LevelArgs make_args(const Level &L, double omega) {
     a.cxy = L.b / h2;
     a.cyy = L.c / h2;
     a.omega_over_d = omega / (-2.5 * (L.a + L.c) / h2);
-    for (int s = 0; s < 4; ++s) a.bc[s] = L.cg.box_bc[s] == MG_BC_NEUMANN ? 1 : 0;
     a.mixed = L.b != 0.0;
     return a;
 }
@@ -224,6 +223,15 @@ void upload_level(mg_handle h, int l, bool last, hipStream_t st) {
     DevLevel &D = h->dev[l];
     const int nx = L.g.nx, ny = L.g.ny;
     D.args = make_args(L, h->opt.omega);
+    // ghost weights of the four box sides on this level (h-dependent for Robin)
+    std::vector<double> gw(32);
+    for (int side = 0; side < 4; ++side)
+        for (int d = 1; d <= 2; ++d) {
+            double w[5];
+            face_ghost(L.cg.box_bc[side], L.cg.box_al[side][0], L.cg.box_al[side][1], L.g.h, d, w);
+            for (int k = 0; k < 4; ++k) gw[(side * 2 + d - 1) * 4 + k] = w[k];
+        }
+    D.args.gw = h->upload(gw);
     D.ncells = (size_t)(nx + 4) * (ny + 4);
     std::vector<uint8_t> mask(D.ncells, 0);
     std::vector<int> plgidx(D.ncells, -1);
@@ -618,26 +626,6 @@ mg_status guard(mg_handle h, const std::function<void()> &fn) {
     }
 }
 
-void build_ghost_table();
-
-// the ghost weights are the same for every handle: uploaded once per device
-void build_ghost_table_once(int device) {
-    static std::once_flag once[64];
-    if (device < 0 || device >= 64) fail(MG_ERR_INVALID_ARG, "device index out of range");
-    std::call_once(once[device], [] { build_ghost_table(); });
-}
-
-void build_ghost_table() {
-    double gw[2][2][4];
-    for (int bc = 0; bc < 2; ++bc)
-        for (int d = 1; d <= 2; ++d) {
-            double w[5];
-            ghost_weights(bc == 0 ? MG_BC_DIRICHLET : MG_BC_NEUMANN, d, w);
-            for (int k = 0; k < 4; ++k) gw[bc][d - 1][k] = w[k];
-        }
-    HIPCHECK(upload_ghost_table(gw));
-}
-
 }  // namespace
 
 // ===========================================================================
@@ -679,7 +667,6 @@ mg_status mg_setup(const mg_grid *grid, int n_curves, const mg_curve *curves, do
             if ((sg.kind != MG_SEG_LINE && sg.kind != MG_SEG_ARC) || sg.bc < 0 || sg.bc > 2) return MG_ERR_INVALID_ARG;
             for (double v : sg.p)
                 if (std::isnan(v)) return MG_ERR_INVALID_ARG;
-            if (k == 0 && sg.bc == MG_BC_ROBIN) return MG_ERR_UNSUPPORTED;
         }
     }
     auto h = std::make_unique<mg_handle_s>();
@@ -704,7 +691,6 @@ mg_status mg_setup(const mg_grid *grid, int n_curves, const mg_curve *curves, do
             }
             h->curves.c.push_back(segs);
         }
-        build_ghost_table_once(h->device);
         mg_grid g = *grid;
         while (true) {
             auto L = std::make_unique<Level>();

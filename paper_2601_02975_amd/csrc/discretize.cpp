@@ -28,20 +28,56 @@ void ghost_weights(int bc, int which, double w[5]) {
     for (int k = 0; k < 5; ++k) w[k] = src[k];
 }
 
+// Ghost weights of a box face with the face datum g taken as given: g = u
+// (Dirichlet), g = du/dn (Neumann: the face weight above times h), and
+// g = alpha1 u + alpha2 du/dn (Robin).  Section 4.1 gives no Robin ghost; the
+// reading: the degree-4 polynomial p in the normal coordinate x (cells of
+// width 1, face at x = 0, interior cells i .. i-3 on [-1, 0] .. [-4, -3],
+// outward normal +x) with those four cell averages and
+// alpha1 p(0) + alpha2 p'(0) / h = g, averaged over the ghost cell
+// [which - 1, which].
+void face_ghost(int bc, double al1, double al2, double h, int which, double w[5]) {
+    if (bc != MG_BC_ROBIN) {
+        ghost_weights(bc, which, w);
+        if (bc == MG_BC_NEUMANN) w[4] *= h;
+        return;
+    }
+    auto avg = [](double a, int k) { return (std::pow(a + 1.0, k + 1) - std::pow(a, k + 1)) / (k + 1); };
+    // rows: conditions on the coefficients of p; w solves M^T w = e
+    double A[5][6];
+    for (int m = 0; m < 4; ++m)
+        for (int k = 0; k < 5; ++k) A[k][m] = avg(-(m + 1.0), k);         // transposed
+    for (int k = 0; k < 5; ++k) A[k][4] = k == 0 ? al1 : (k == 1 ? al2 / h : 0.0);
+    for (int k = 0; k < 5; ++k) A[k][5] = avg(which - 1.0, k);
+    for (int c = 0; c < 5; ++c) {                                          // Gauss-Jordan, partial pivoting
+        int piv = c;
+        for (int r = c + 1; r < 5; ++r)
+            if (std::fabs(A[r][c]) > std::fabs(A[piv][c])) piv = r;
+        if (A[piv][c] == 0.0) fail(MG_ERR_INVALID_ARG, "Robin coefficients give no ghost formula");
+        for (int k = 0; k < 6; ++k) std::swap(A[c][k], A[piv][k]);
+        for (int r = 0; r < 5; ++r) {
+            if (r == c) continue;
+            const double f = A[r][c] / A[c][c];
+            for (int k = c; k < 6; ++k) A[r][k] -= f * A[c][k];
+        }
+    }
+    for (int k = 0; k < 5; ++k) w[k] = A[k][5] / A[k][k];
+}
+
 // Corner ghost (beyond the x-face by m cells and the y-face by k cells):
 // the face-ghost formula of one face applied to the ghosts of the other,
 // averaged over both orders; the face data beyond the corner are the cubic
 // extrapolation of that face's data along the face.
-void corner_weights(int bcx, int bcy, int m, int k, double h, double wu[4][4], double wgy[4], double wgx[4]) {
+void corner_weights(const CutGrid &cg, int xside, int yside, int m, int k, double h, double wu[4][4], double wgy[4],
+                    double wgx[4]) {
     static const double E[2][4] = {{4, -6, 4, -1}, {10, -20, 15, -4}};
     double gx[5], gy[5];
-    ghost_weights(bcx, m, gx);
-    ghost_weights(bcy, k, gy);
-    double sx = bcx == MG_BC_NEUMANN ? h : 1.0, sy = bcy == MG_BC_NEUMANN ? h : 1.0;
+    face_ghost(cg.box_bc[xside], cg.box_al[xside][0], cg.box_al[xside][1], h, m, gx);
+    face_ghost(cg.box_bc[yside], cg.box_al[yside][0], cg.box_al[yside][1], h, k, gy);
     for (int p = 0; p < 4; ++p)
         for (int q = 0; q < 4; ++q) wu[p][q] = gx[p] * gy[q];
-    for (int p = 0; p < 4; ++p) wgy[p] = 0.5 * gy[4] * sy * (gx[p] + E[m - 1][p]);
-    for (int q = 0; q < 4; ++q) wgx[q] = 0.5 * gx[4] * sx * (gy[q] + E[k - 1][q]);
+    for (int p = 0; p < 4; ++p) wgy[p] = 0.5 * gy[4] * (gx[p] + E[m - 1][p]);
+    for (int q = 0; q < 4; ++q) wgx[q] = 0.5 * gx[4] * (gy[q] + E[k - 1][q]);
 }
 
 // SFV stencil of L = a d_xx + b d_xy + c d_yy, eq. (4.7) and the mixed term
@@ -91,7 +127,7 @@ void Level::sfv_row(int i, int j, std::vector<std::pair<int, double>> &cells,
             int xside = qi < 0 ? 3 : 1, yside = qj < 0 ? 0 : 2;
             int m = qi < 0 ? -qi : qi - nx + 1, k = qj < 0 ? -qj : qj - ny + 1;
             double wu[4][4], wgy[4], wgx[4];
-            corner_weights(cg.box_bc[xside], cg.box_bc[yside], m, k, h, wu, wgy, wgx);
+            corner_weights(cg, xside, yside, m, k, h, wu, wgy, wgx);
             for (int p = 0; p < 4; ++p) {
                 int col = xside == 3 ? p : nx - 1 - p;
                 for (int q = 0; q < 4; ++q) {
@@ -109,8 +145,7 @@ void Level::sfv_row(int i, int j, std::vector<std::pair<int, double>> &cells,
             else if (qi < 0) { side = 3; depth = -qi; along = qj; }
             else { side = 1; depth = qi - nx + 1; along = qj; }
             double gw[5];
-            int bc = cg.box_bc[side];
-            ghost_weights(bc, depth, gw);
+            face_ghost(cg.box_bc[side], cg.box_al[side][0], cg.box_al[side][1], h, depth, gw);
             for (int k = 0; k < 4; ++k) {
                 int ci, cj;
                 if (side == 0) { ci = along; cj = k; }
@@ -119,7 +154,7 @@ void Level::sfv_row(int i, int j, std::vector<std::pair<int, double>> &cells,
                 else { ci = nx - 1 - k; cj = along; }
                 cells.push_back({cj * nx + ci, w * gw[k]});
             }
-            gdat.push_back({face_index(side, along), w * gw[4] * (bc == MG_BC_NEUMANN ? h : 1.0)});
+            gdat.push_back({face_index(side, along), w * gw[4]});
         }
     }
 }

@@ -243,6 +243,8 @@ void build_cutgrid(const Curves &cv, const mg_grid &g, double eps, CutGrid &cg) 
                 if (std::fabs(box[s].p[k] - want[s][k]) > 1e-12 * std::max(1.0, std::fabs(want[s][k])))
                     fail(MG_ERR_GEOMETRY, "the outer curve must be the counter-clockwise grid box");
             cg.box_bc[s] = box[s].bc;
+            cg.box_al[s][0] = box[s].al1;
+            cg.box_al[s][1] = box[s].al2;
         }
     }
     // runs per cell

@@ -21,26 +21,15 @@
 
 namespace mgc {
 
-__constant__ double c_gw[2][2][4];     // [bc][depth-1][k] ghost weights on the cells k steps inward
-
-hipError_t upload_ghost_table(const double gw[2][2][4]) {
-    return hipMemcpyToSymbol(HIP_SYMBOL(c_gw), gw, sizeof(double) * 16);
-}
-
 __device__ __forceinline__ size_t pidx(const LevelArgs &L, int i, int j) {
     return (size_t)(j + 2) * L.pitch + (size_t)(i + 2);
 }
 
-// boundary condition of a box side without indexing the argument struct at
-// run time (that would place it in scratch memory)
-__device__ __forceinline__ int side_bc(const LevelArgs &L, int side) {
-    return side == 0 ? L.bc[0] : side == 1 ? L.bc[1] : side == 2 ? L.bc[2] : L.bc[3];
-}
-
-// ghost weights from the constant table
+// ghost weights of the level (a device array: indexing it at run time keeps
+// the argument struct out of scratch memory)
 struct GhostW {
     const LevelArgs &L;
-    __device__ double operator()(int side, int depth, int k) const { return c_gw[side_bc(L, side)][depth - 1][k]; }
+    __device__ double operator()(int side, int depth, int k) const { return L.gw[(side * 2 + depth - 1) * 4 + k]; }
 };
 
 // ghost weights staged in LDS: w[side][depth - 1][k]
@@ -139,10 +128,7 @@ template <typename T, typename At, int TYv = TY>
 __device__ __forceinline__ void load_tile(T (*s)[HX], double *gws, const At &at, const LevelArgs &L, int i0, int j0) {
     constexpr int HYv = TYv + 4;
     const bool edge = i0 < 2 || j0 < 2 || i0 + TX + 2 > L.nx || j0 + TYv + 2 > L.ny;
-    if (edge && threadIdx.x < 32) {
-        const int side = threadIdx.x >> 3, d = (threadIdx.x >> 2) & 1, k = threadIdx.x & 3;
-        gws[threadIdx.x] = c_gw[side_bc(L, side)][d][k];
-    }
+    if (edge && threadIdx.x < 32) gws[threadIdx.x] = L.gw[threadIdx.x];
     // all global loads of a thread are issued before any LDS store
     constexpr int NL = (HX * HYv + NT - 1) / NT;
     T v[NL];
@@ -437,6 +423,11 @@ __global__ __launch_bounds__(NT) void k_smooth_a(LevelArgs L, const T *__restric
 // own keeps more waves per SIMD in flight to cover the memory latency; the
 // PLG groups follow as k_smooth_a with no tiles.
 constexpr long long SPLIT_CELLS = 2048LL * 2048;
+// tile height of k_smooth_tiles (the shorter FP64 tiles need fewer registers)
+template <typename T>
+constexpr int ty_split() {
+    return sizeof(T) == 4 ? 32 : 16;
+}
 
 template <typename T, bool MIXED, int TYv>
 __global__ __launch_bounds__(NT) void k_smooth_tiles(LevelArgs L, const T *__restrict__ uold,
@@ -871,12 +862,14 @@ void launch_smooth_a(const LevelArgs &L, const T *uold, const T *b, T *unew, con
     const int uz = uzero ? 1 : 0;
     if (!small && (long long)L.nx * L.ny >= SPLIT_CELLS) {
         // the two roles write disjoint cells (SFV tiles, PLG rows)
+        constexpr int tys = ty_split<T>();
+        const int nts = tiles_x * ((L.ny + tys - 1) / tys);
         if (L.mixed)
-            hipLaunchKernelGGL((k_smooth_tiles<T, true, TY>), dim3(ntile), dim3(NT), 0, st, L, uold, b, unew, mask,
-                               tiles_x, uz);
+            hipLaunchKernelGGL((k_smooth_tiles<T, true, tys>), dim3(nts), dim3(NT), 0, st, L, uold, b, unew,
+                               mask, tiles_x, uz);
         else
-            hipLaunchKernelGGL((k_smooth_tiles<T, false, TY>), dim3(ntile), dim3(NT), 0, st, L, uold, b, unew, mask,
-                               tiles_x, uz);
+            hipLaunchKernelGGL((k_smooth_tiles<T, false, tys>), dim3(nts), dim3(NT), 0, st, L, uold, b, unew,
+                               mask, tiles_x, uz);
         if (P.nblk1 == 0) return;
         if (L.mixed)
             hipLaunchKernelGGL((k_smooth_a<T, true, TY>), dim3(P.nblk1), dim3(NT), 0, st, L, uold, b, unew, mask,

@@ -7,22 +7,16 @@
 
 namespace mgc {
 
-// Ghost weights on the 4 interior cells (homogeneous part; boundary data
-// enter through the right-hand side).  gw[bc][depth-1][k], bc 0 Dirichlet,
-// 1 Neumann; k = steps inward.
-struct GhostTable {
-    double gw[2][2][4];
-    double face[2][2];          // face-datum weights (for reference)
-    double ext[2][4];           // cubic extrapolation along a face
-};
-
 // Launch-time parameters of one level (passed by value).
 struct LevelArgs {
     int nx, ny, pitch;          // pitch = nx + 4, origin at (2, 2)
     double h;
     double cxx, cxy, cyy;       // a/h^2, b/h^2, c/h^2
     double omega_over_d;        // omega / D, D = -5(a+c)/(2h^2)
-    int bc[4];                  // box sides: bottom, right, top, left (0 D, 1 N)
+    // ghost weights on the 4 interior cells (homogeneous part; boundary data
+    // enter through the right-hand side), device array gw[(side * 2 + depth - 1) * 4 + k],
+    // sides bottom, right, top, left, k = steps inward
+    const double *gw;
     int mixed;                  // b != 0
 };
 

@@ -7,8 +7,6 @@
 
 namespace mgc {
 
-hipError_t upload_ghost_table(const double gw[2][2][4]);
-
 // one block-smoother sweep (Definition 5.6), uold -> unew: launch A (SFV
 // tiles, PLG gathers and segment solves), then launch B (separators and
 // segment corrections; nothing on levels without separators)

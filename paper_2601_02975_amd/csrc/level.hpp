@@ -11,7 +11,9 @@
 namespace mgc {
 
 void ghost_weights(int bc, int which, double w[5]);
-void corner_weights(int bcx, int bcy, int m, int k, double h, double wu[4][4], double wgy[4], double wgx[4]);
+void face_ghost(int bc, double al1, double al2, double h, int which, double w[5]);
+void corner_weights(const CutGrid &cg, int xside, int yside, int m, int k, double h, double wu[4][4], double wgy[4],
+                    double wgx[4]);
 
 struct Level {
     mg_grid g{};

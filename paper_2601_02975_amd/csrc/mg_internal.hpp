@@ -67,6 +67,7 @@ struct CutGrid {
     mg_grid g;
     double eps;
     int box_bc[4];                    // bottom, right, top, left
+    double box_al[4][2];              // Robin (alpha1, alpha2) of the box sides
     std::vector<uint8_t> active, regular;     // [j*nx + i]
     std::vector<double> volfrac;
     std::vector<Comp> comps;

@@ -18,11 +18,21 @@ import workloads as W
 
 pytestmark = pytest.mark.gpu
 
+def _robin_box(base, alpha1, alpha2):
+    """base with Robin (alpha1, alpha2) on every box side."""
+    box = W.box_curve(0.0, 0.0, 1.0, 1.0, W.BC_ROBIN, alpha1, alpha2)
+    return W.Problem(base.name + "_robin_box", base.grid, [box] + list(base.curves[1:]), base.a, base.b, base.c,
+                     base.solution, base.eps)
+
+
 CASES = {
     "disk64": lambda: W.unit_disk_config(0, 64),
     "three_disks128": lambda: W.three_disks_config(0, 128),
     "star128": lambda: W.star_config(0, 128),
     "square_cross32": lambda: W.unit_square_config(32, 1.0, 0.5, 2.0),
+    # Robin box sides (face and, with the cross term, corner ghosts)
+    "disk_robin_box64": lambda: _robin_box(W.unit_disk_config(0, 64), 1.0, 0.5),
+    "square_cross_robin_box32": lambda: _robin_box(W.unit_square_config(32, 1.0, 0.5, 2.0), 2.0, 0.25),
 }
 
 
@@ -173,7 +183,7 @@ def test_vcycle_iterates(name, nu):
         assert err <= 1e-11
 
 
-@pytest.mark.parametrize("name", ["disk64", "three_disks128", "star128"])
+@pytest.mark.parametrize("name", ["disk64", "three_disks128", "star128", "disk_robin_box64"])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_solve_matches_oracle(name, precision):
     """mg_solve to 1e-10 (FP64, and FP32 V-cycles in FP64 defect correction)
@@ -225,7 +235,7 @@ def test_mixed_step_is_fp32_accurate(name):
     assert 1e-12 < d < 1e-4
 
 
-@pytest.mark.parametrize("name", ["disk64", "three_disks128", "star128"])
+@pytest.mark.parametrize("name", ["disk64", "three_disks128", "star128", "disk_robin_box64"])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_graph_replays_match_eager(name, precision):
     """The captured outer iteration (HIP graph) gives bitwise the same
