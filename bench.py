@@ -104,15 +104,14 @@ def cpu_baseline(P, gpu_iters, sample_cycles, cycle):
                       "not included" % (sample_cycles, cycle, t_cycle, gpu_iters, t_setup)}
 
 
-def serving_leg(torch, mg, W, n, n_geom, n_rhs, qps, slots, tol):
-    """Serving with resident hierarchies: n_geom three-disk geometries (seeds
-    1..n_geom) at n^2 are set up in the server by one warm-up request each;
-    then n_rhs right-hand sides per geometry arrive as a Poisson process at
-    qps and are solved in mixed precision in `slots` slots.  Reported beside
-    the same solves run one after another on resident hierarchies (mixed and
-    FP64)."""
+def serving_leg(torch, mg, W, geoms, n_rhs, qps, slots, tol, label):
+    """Serving with resident hierarchies: every geometry is set up in the
+    server by one warm-up request; then n_rhs right-hand sides per geometry
+    arrive as a Poisson process at qps and are solved in mixed precision in
+    `slots` slots.  Reported beside the same solves run one after another on
+    resident hierarchies (mixed and FP64)."""
     import numpy as np
-    geoms = [W.three_disks_config(s, n) for s in range(1, n_geom + 1)]
+    n_geom = len(geoms)
     reqs = [(k, W.with_solution(P, 1000 * k + r, 6)) for k, P in enumerate(geoms) for r in range(n_rhs)]
     rng = np.random.default_rng(12345)
     order = rng.permutation(len(reqs))
@@ -155,9 +154,9 @@ def serving_leg(torch, mg, W, n, n_geom, n_rhs, qps, slots, tol):
     srv.close()
     lat = sorted(r["latency_s"] for r in res)
     pct = lambda q: lat[min(len(lat) - 1, int(math.ceil(q * len(lat))) - 1)]
-    return {"workload": "%d three-disk geometries (seeds 1-%d) at %d^2, resident after one warm-up request each; "
-                        "%d right-hand sides per geometry arriving as a Poisson process at %g/s; %d slots; V-cycles "
-                        "(nu = (6, 6)) in mixed precision to %g" % (n_geom, n_geom, n, n_rhs, qps, slots, tol),
+    return {"workload": "%s, resident after one warm-up request each; %d right-hand sides per geometry arriving "
+                        "as a Poisson process at %g/s; %d slots; V-cycles (nu = (6, 6)) in mixed precision to %g" % (
+                            label, n_rhs, qps, slots, tol),
             "requests": len(reqs), "failed": sum(r["status"] != 0 for r in res),
             "p50_latency_s": pct(0.50), "p99_latency_s": pct(0.99), "solves_per_s": len(reqs) / t_all,
             "sequential_mixed_solves_per_s": seq_rate["mixed"], "sequential_fp64_solves_per_s": seq_rate["fp64"],
@@ -308,10 +307,21 @@ def main():
     if not args.no_star:
         out["star4096"] = star_leg(torch, mg, W, args.steps, args.warmup, args.tol)
     if not args.no_serving:
-        out["serving"] = serving_leg(torch, mg, W, 512, 4, 8, 400.0, 4, args.tol)
+        out["serving"] = serving_leg(torch, mg, W, [W.three_disks_config(s, 512) for s in range(1, 5)], 8, 400.0, 4,
+                                     args.tol, "4 three-disk geometries (seeds 1-4) at 512^2")
         print("serving: p50 %.3f s, p99 %.3f s, %.1f solves/s" % (
             out["serving"]["p50_latency_s"], out["serving"]["p99_latency_s"], out["serving"]["solves_per_s"]),
             file=sys.stderr, flush=True)
+        # the request distribution of the serving trace: grids of 128^2 to
+        # 2048^2, 1-5 holes with mixed boundary conditions, seeded (a, b, c)
+        mix = [W.serving_request(0, k) for k in range(8)]
+        out["serving_mix"] = serving_leg(torch, mg, W, mix, 4, 200.0, 4, args.tol,
+                                         "the first 8 requests of serving trace 0 as geometries (grids %s; 1-5 "
+                                         "holes, mixed boundary conditions, seeded a, b, c)"
+                                         % "/".join(str(P.grid.nx) for P in mix))
+        print("serving mix: p50 %.3f s, p99 %.3f s, %.1f solves/s" % (
+            out["serving_mix"]["p50_latency_s"], out["serving_mix"]["p99_latency_s"],
+            out["serving_mix"]["solves_per_s"]), file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(P, it64[-1], args.cpu_cycles, "V")
     print(json.dumps(out))
