@@ -224,7 +224,8 @@ def main():
     ap.add_argument("--no-star", action="store_true")
     ap.add_argument("--only-star", action="store_true", help="run only the 4096^2 star leg")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run a 256 MiB device-to-device copy (reference for HBM byte counters)")
+                    help="also move 256 MiB with the runtime's copy kernel and with an elementwise kernel "
+                         "(references for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d refused)" % args.gpus,
@@ -242,8 +243,12 @@ def main():
         dst_t = torch.empty_like(src_t)
         for _ in range(3):
             dst_t.copy_(src_t)
+        # the same bytes through an ordinary elementwise kernel (plain loads
+        # and stores, unlike the runtime's copy kernel)
+        for _ in range(3):
+            torch.mul(src_t, 2.0, out=dst_t)
         torch.cuda.synchronize()
-        print("calibration copy: 3 x %d bytes read and written" % (src_t.numel() * 8), file=sys.stderr)
+        print("calibration copy: 3 + 3 x %d bytes read and written" % (src_t.numel() * 8), file=sys.stderr)
         del src_t, dst_t
     if args.only_star:
         print(json.dumps({"star4096": star_leg(torch, mg, W, args.steps, args.warmup, args.tol)}))
