@@ -232,6 +232,18 @@ void upload_level(mg_handle h, int l, bool last, hipStream_t st) {
             for (int k = 0; k < 4; ++k) gw[(side * 2 + d - 1) * 4 + k] = w[k];
         }
     D.args.gw = h->upload(gw);
+    // blocks of 64 x 8 cells made only of SFV cells
+    D.args.full_bx = (nx + 63) / 64;
+    D.args.full_by = (ny + 7) / 8;
+    std::vector<uint8_t> full((size_t)D.args.full_bx * D.args.full_by, 0);
+    for (int by = 0; by < D.args.full_by; ++by)
+        for (int bx = 0; bx < D.args.full_bx; ++bx) {
+            bool all = bx * 64 + 64 <= nx && by * 8 + 8 <= ny;
+            for (int j = by * 8; all && j < by * 8 + 8; ++j)
+                for (int i = bx * 64; all && i < bx * 64 + 64; ++i) all = L.kind[(size_t)j * nx + i] == 1;
+            full[(size_t)by * D.args.full_bx + bx] = all ? 1 : 0;
+        }
+    D.args.full = h->upload(full);
     D.ncells = (size_t)(nx + 4) * (ny + 4);
     std::vector<uint8_t> mask(D.ncells, 0);
     std::vector<int> plgidx(D.ncells, -1);

@@ -257,6 +257,14 @@ __device__ __forceinline__ void jacobi_tile(const LevelArgs &L, const T *__restr
     constexpr int R = TYv / (NT / TX);           // consecutive rows per thread
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     const int i = i0 + tx, r0 = ty * R;
+    // a tile made of blocks whose cells are all SFV cells skips the class
+    // bytes (TYv is a multiple of 8, i0 of 64, j0 of TYv)
+    bool full = true;
+#pragma unroll
+    for (int q = 0; q < TYv / 8; ++q) {
+        const int by = (j0 >> 3) + q;
+        full = full && by < L.full_by && L.full[by * L.full_bx + (i0 >> 6)] != 0;
+    }
     // the per-cell loads are issued before the tile barrier so that their
     // latency overlaps the tile load
     uint8_t mk[R];
@@ -266,7 +274,7 @@ __device__ __forceinline__ void jacobi_tile(const LevelArgs &L, const T *__restr
         const int j = j0 + r0 + k;
         const bool in = i < L.nx && j < L.ny;
         const size_t id = pidx(L, in ? i : 0, in ? j : 0);
-        mk[k] = in ? mask[id] : 0;
+        mk[k] = full ? (uint8_t)1 : (in ? mask[id] : (uint8_t)0);
         bv[k] = b[id];
     }
     const T wod = (T)L.omega_over_d;

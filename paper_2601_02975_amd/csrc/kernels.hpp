@@ -17,6 +17,11 @@ struct LevelArgs {
     // enter through the right-hand side), device array gw[(side * 2 + depth - 1) * 4 + k],
     // sides bottom, right, top, left, k = steps inward
     const double *gw;
+    // per block of 64 x 8 cells (row-major, full_bx x full_by blocks): 1 when
+    // every cell of the block is an SFV cell, so that tiles made of such
+    // blocks need not read the class bytes
+    const uint8_t *full;
+    int full_bx, full_by;
     int mixed;                  // b != 0
 };
 
