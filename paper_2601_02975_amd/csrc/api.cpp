@@ -300,6 +300,9 @@ void upload_level(mg_handle h, int l, bool last, hipStream_t st) {
     int *seg_start = h->upload(S.seg_start);
     long long *inv_off = h->upload(G.inv_off), *ft_off = h->upload(G.ft_off), *sj_off = h->upload(G.sj_off);
     int *fcols_ptr = h->upload(S.fcols_ptr);
+    int *fcols = h->upload(S.fcols);
+    int nblk2_seg = 0;
+    for (auto &b : G.blk2) nblk2_seg += b.kind == 0 ? 1 : 0;
     int *ce_ptr = h->upload(G.ce_ptr), *ce_row = h->upload(G.ce_row), *ce_slot = h->upload(G.ce_slot);
     auto fill = [&](auto &P, auto *a21v, auto *inv, auto *cev, auto *FT, auto *SJ, auto *sinv, auto *t, auto *y,
                     auto *contrib) {
@@ -312,6 +315,7 @@ void upload_level(mg_handle h, int l, bool last, hipStream_t st) {
         P.ce_ptr = ce_ptr; P.ce_row = ce_row; P.ce_slot = ce_slot; P.ce_val = cev;
         P.nblk2 = (int)G.blk2.size(); P.blk2 = blk2;
         P.ft_off = ft_off; P.FT = FT; P.fcols_ptr = fcols_ptr; P.sj_off = sj_off; P.SJ = SJ; P.sinv = sinv;
+        P.fcols = fcols; P.nblk2_seg = nblk2_seg;
         P.t = t; P.y = y; P.contrib = contrib;
     };
     const size_t nslot = (size_t)S.nsep * ELL_W;

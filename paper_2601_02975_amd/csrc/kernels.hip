@@ -451,13 +451,17 @@ __global__ __launch_bounds__(NT) void k_smooth_tiles(LevelArgs L, const T *__res
 // Launch B: r_S = t_S - A_SB y (every block forms all of it in LDS), then
 // either x_S = S'^{-1} r_S on a run of separator rows, or, for a segment
 // slice, x_S on the segment's separator columns and x_B = y - F_j x_S.
-template <typename T>
+// MODE 0 runs all blocks; on levels with many separators launch B is split:
+// MODE 1 runs the separator-row blocks (x_S into u), then MODE 2 the segment
+// slices, which read their x_S columns from u instead of forming r_S and
+// re-reading rows of S'^{-1} slice by slice.
+template <typename T, int MODE>
 __global__ __launch_bounds__(NT) void k_smooth_b(PlgDev<T> P, T *__restrict__ u) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int ns = P.nsep, nsp = (ns + 3) & ~3;          // dense rows have stride nsp
     T *rs = reinterpret_cast<T *>(smem_raw);
-    T *xk = rs + nsp;
-    const PlgBlkB bk = P.blk2[blockIdx.x];
+    T *xk = MODE == 2 ? rs : rs + nsp;                  // MODE 2 holds only x_S's columns
+    const PlgBlkB bk = P.blk2[blockIdx.x + (MODE == 1 ? P.nblk2_seg : 0)];
     const bool seprows = bk.kind == 1;
     // segment slice: this thread's row of F_j^T and y, loaded before the
     // separator solve (one row per thread: slices have at most NT rows)
@@ -473,7 +477,11 @@ __global__ __launch_bounds__(NT) void k_smooth_b(PlgDev<T> P, T *__restrict__ u)
         yr = P.y[r];
         cr = P.cell[r];
     }
-    for (int s = threadIdx.x; s < nsp; s += NT) {
+    if (MODE == 2) {
+        const int *fc = P.fcols + P.fcols_ptr[bk.j];
+        for (int kk = threadIdx.x; kk < bk.kj; kk += NT) xk[kk] = u[P.cell[P.sep_begin + fc[kk]]];
+    }
+    for (int s = threadIdx.x; MODE != 2 && s < nsp; s += NT) {
         T v = 0;
         if (s < ns) {
             v = P.t[P.sep_begin + s];
@@ -487,7 +495,7 @@ __global__ __launch_bounds__(NT) void k_smooth_b(PlgDev<T> P, T *__restrict__ u)
     // dense rows times r_S: rows of S'^{-1} (separator block), or the rows
     // of S'^{-1} at the segment's separator columns
     const T *A = seprows ? P.sinv + (size_t)bk.r0 * nsp : P.SJ + bk.sj_off;
-    const int nr = seprows ? bk.r1 - bk.r0 : bk.kj;
+    const int nr = MODE == 2 ? 0 : seprows ? bk.r1 - bk.r0 : bk.kj;
     for (int rb = wave * 8; rb < nr; rb += 32) {
         T out[8];
         wave_rows8<T, rows_unroll<T>()>(A + (size_t)rb * nsp, nsp, min(8, nr - rb), rs, lane, out);
@@ -895,11 +903,19 @@ void launch_smooth_a(const LevelArgs &L, const T *uold, const T *b, T *unew, con
 #undef MG_SA
 }
 
+// launch B in two kernels from this many separator rows on
+constexpr int SPLIT_B_SEP = 768;
+
 template <typename T>
 void launch_smooth_b(const PlgDev<T> &P, T *unew, hipStream_t st) {
-    if (P.nblk2)
-        hipLaunchKernelGGL((k_smooth_b<T>), dim3(P.nblk2), dim3(NT), sizeof(T) * (((P.nsep + 3) & ~3) + PLG_KMAX), st,
-                           P, unew);
+    if (!P.nblk2) return;
+    const size_t lds = sizeof(T) * (((P.nsep + 3) & ~3) + PLG_KMAX);
+    if (P.nsep >= SPLIT_B_SEP && P.nblk2_seg > 0 && P.nblk2_seg < P.nblk2) {
+        hipLaunchKernelGGL((k_smooth_b<T, 1>), dim3(P.nblk2 - P.nblk2_seg), dim3(NT), lds, st, P, unew);
+        hipLaunchKernelGGL((k_smooth_b<T, 2>), dim3(P.nblk2_seg), dim3(NT), sizeof(T) * PLG_KMAX, st, P, unew);
+        return;
+    }
+    hipLaunchKernelGGL((k_smooth_b<T, 0>), dim3(P.nblk2), dim3(NT), lds, st, P, unew);
 }
 
 template <typename T>

@@ -69,6 +69,8 @@ struct PlgDev {
     const long long *ft_off = nullptr;  // F_j^T = (B_j^{-1} A_{j,S})^T, row-major k_j x L_j
     const T *FT = nullptr;
     const int *fcols_ptr = nullptr;     // k_j = fcols_ptr[j + 1] - fcols_ptr[j]
+    const int *fcols = nullptr;         // separator index of each of those columns
+    int nblk2_seg = 0;                  // launch B blocks of segment slices (they come first)
     const long long *sj_off = nullptr;  // rows of S'^{-1} at segment j's separator columns, k_j x nsep
     const T *SJ = nullptr;
     const T *sinv = nullptr;            // row-major nsep x nsep
