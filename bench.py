@@ -10,7 +10,7 @@ reported beside it, the same solve with the FMG cycle of Algorithm 4 and with
 nu = (3, 3) as variants, and the 4096^2 star workload (Robin hole, cross
 term) as a second line with its own roofline figure.
 
-Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus above 1 is refused: the solver runs on one GPU.
 """
 import argparse
 import hashlib
@@ -228,7 +228,7 @@ def main():
                          "(references for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d refused)" % args.gpus,
+        print("bench.py measures one GPU: the library has no multi-GPU path (--gpus %d refused)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
