@@ -12,7 +12,7 @@ Steps, in the paper's order:
     beta = W M^T (M W M^T)^{-1} phibar (eq. (4.16), Lemma 4.4)
   * the global system and its block form (eqs. (4.19)-(4.21))
 
-Readings of points the paper leaves open (each also listed in the design doc):
+Readings of points the paper leaves open:
   * the outer boundary is the grid box; every box face must be extendable on
     every level (otherwise that level is rejected);
   * positions of S_i outside the box in both coordinates (reached only by
