@@ -411,6 +411,15 @@ constexpr long long small_grid_cells() {
     return sizeof(T) == 4 ? 512 * 512 : 256 * 256;
 }
 
+// Tile of block bid in a launch whose first n blocks are tiles.  Blocks are
+// dealt to the 8 XCDs in turn (block b to XCD b mod 8), so this hands each
+// XCD a run of consecutive tiles: neighbouring tiles then share the cache
+// lines of their common halo in one L2.
+__device__ __forceinline__ int xcd_tile(int bid, int n) {
+    const int x = bid & 7, k = bid >> 3, q = n >> 3, r = n & 7;
+    return x * q + min(x, r) + k;
+}
+
 template <typename T, bool MIXED, int TYv>
 __global__ __launch_bounds__(NT) void k_smooth_a(LevelArgs L, const T *__restrict__ uold, const T *__restrict__ b,
                                                  T *__restrict__ unew, const uint8_t *__restrict__ mask, int tiles_x,
@@ -419,7 +428,8 @@ __global__ __launch_bounds__(NT) void k_smooth_a(LevelArgs L, const T *__restric
     __shared__ double gws[32];
     const int bid = blockIdx.x;
     if (bid < ntile) {
-        jacobi_tile<T, MIXED, TYv>(L, uold, b, unew, mask, uzero != 0, (bid % tiles_x) * TX, (bid / tiles_x) * TYv,
+        const int t = xcd_tile(bid, ntile);
+        jacobi_tile<T, MIXED, TYv>(L, uold, b, unew, mask, uzero != 0, (t % tiles_x) * TX, (t / tiles_x) * TYv,
                                    reinterpret_cast<T(*)[HX]>(smem), gws);
         return;
     }
@@ -443,8 +453,8 @@ __global__ __launch_bounds__(NT) void k_smooth_tiles(LevelArgs L, const T *__res
                                                      const uint8_t *__restrict__ mask, int tiles_x, int uzero) {
     __shared__ __align__(16) T smem[(TYv + 4) * HX];
     __shared__ double gws[32];
-    const int bid = blockIdx.x;
-    jacobi_tile<T, MIXED, TYv>(L, uold, b, unew, mask, uzero != 0, (bid % tiles_x) * TX, (bid / tiles_x) * TYv,
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    jacobi_tile<T, MIXED, TYv>(L, uold, b, unew, mask, uzero != 0, (t % tiles_x) * TX, (t / tiles_x) * TYv,
                                reinterpret_cast<T(*)[HX]>(smem), gws);
 }
 
@@ -574,7 +584,8 @@ __global__ __launch_bounds__(NT) void k_restrict(LevelArgs L, LevelArgs C, int t
         if (uc) uc[ex_target[t]] = 0;
         return;
     }
-    const int bx = blockIdx.x % tiles_x, by = blockIdx.x / tiles_x;
+    const int tile = xcd_tile(blockIdx.x, ntile);
+    const int bx = tile % tiles_x, by = tile / tiles_x;
     const int i0 = bx * TX, j0 = by * TY;
     constexpr int NC = (TX / 2) * (TY / 2) / NT;      // coarse cells per thread
     uint8_t ck[NC], fk[NC][4];
@@ -717,7 +728,8 @@ __global__ __launch_bounds__(NT) void k_residual_norm(LevelArgs L, int tiles_x, 
         }
     } else {
         constexpr int R = TY / (NT / TX);
-        const int i0 = (blockIdx.x % tiles_x) * TX, j0 = (blockIdx.x / tiles_x) * TY;
+        const int tile = xcd_tile(blockIdx.x, ntile);
+        const int i0 = (tile % tiles_x) * TX, j0 = (tile / tiles_x) * TY;
         const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
         const int i = i0 + tx;
         uint8_t mk[R];
