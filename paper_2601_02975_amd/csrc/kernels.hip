@@ -433,7 +433,7 @@ __global__ __launch_bounds__(NT) void k_smooth_a(LevelArgs L, const T *__restric
                                    reinterpret_cast<T(*)[HX]>(smem), gws);
         return;
     }
-    plg_group<T, MIXED>(L, uold, b, unew, uzero != 0, P, bid - ntile, reinterpret_cast<T *>(smem));
+    plg_group<T, MIXED>(L, uold, b, unew, uzero != 0, P, xcd_tile(bid - ntile, P.nblk1), reinterpret_cast<T *>(smem));
 }
 
 // Launch A on large grids, tile role alone: it needs far fewer registers
@@ -471,7 +471,7 @@ __global__ __launch_bounds__(NT) void k_smooth_b(PlgDev<T> P, T *__restrict__ u)
     const int ns = P.nsep, nsp = (ns + 3) & ~3;          // dense rows have stride nsp
     T *rs = reinterpret_cast<T *>(smem_raw);
     T *xk = MODE == 2 ? rs : rs + nsp;                  // MODE 2 holds only x_S's columns
-    const PlgBlkB bk = P.blk2[blockIdx.x + (MODE == 1 ? P.nblk2_seg : 0)];
+    const PlgBlkB bk = P.blk2[xcd_tile(blockIdx.x, gridDim.x) + (MODE == 1 ? P.nblk2_seg : 0)];
     const bool seprows = bk.kind == 1;
     // segment slice: this thread's row of F_j^T and y, loaded before the
     // separator solve (one row per thread: slices have at most NT rows)
