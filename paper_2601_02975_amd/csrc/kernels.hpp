@@ -88,6 +88,6 @@ constexpr int PLG_KMAX = 256;           // separator columns of one segment
 constexpr int PLG_SMAX = 4096;          // separator rows of one level
 constexpr int PLG_SLICE = 32;           // segment rows per block
 constexpr int PLG_B_ROWS = 32;          // segment rows per block of launch B (one per thread)
-constexpr int PLG_SEP_ROWS = 32;        // separator rows per block of launch B
+constexpr int PLG_SEP_ROWS = 16;        // separator rows per block of launch B
 
 }  // namespace mgc
