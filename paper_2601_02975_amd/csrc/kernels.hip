@@ -4,14 +4,17 @@
 // (j + 2) * pitch + (i + 2), pitch = nx + 4.  The halo is never read as data:
 // ghost values are synthesised from interior cells (Section 4.1).
 //
-// One block smoothing sweep (Definition 5.6) is two launches:
-//   A: omega-Jacobi on the SFV cells (eq. (5.5)) in 64 x 32 tiles, and in the
-//      same launch, per group of PLG rows, t = b2 - A21 u1 (eq. (5.6)) from
-//      Jacobi-updated values of the SFV cells those rows couple to
-//      (recomputed from the old iterate, so that the launch needs no grid-wide
-//      ordering), followed by the segment solves y = B^{-1} t;
+// One block smoothing sweep (Definition 5.6) is two steps:
+//   A: omega-Jacobi on the SFV cells (eq. (5.5)) in 64 x 32 (64 x 8 on small
+//      grids) tiles, and, per group of PLG rows, t = b2 - A21 u1 (eq. (5.6))
+//      from Jacobi-updated values of the SFV cells those rows couple to
+//      (recomputed from the old iterate, so that the step needs no grid-wide
+//      ordering), followed by the segment solves y = B^{-1} t.  One launch,
+//      or, from 2048^2 cells, a tile kernel and then the PLG groups;
 //   B: the separator Schur-complement solve and the segment corrections
-//      (only on levels with separators).
+//      (only on levels with separators; two launches from 768 separators).
+// Tiles and PLG blocks are handed to the 8 XCDs in runs of consecutive
+// indices, so that neighbours share cache lines in one L2.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
