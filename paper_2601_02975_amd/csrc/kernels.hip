@@ -7,10 +7,11 @@
 // One block smoothing sweep (Definition 5.6) is two steps:
 //   A: omega-Jacobi on the SFV cells (eq. (5.5)) in 64 x 32 (64 x 8 on small
 //      grids) tiles, and, per group of PLG rows, t = b2 - A21 u1 (eq. (5.6))
-//      from Jacobi-updated values of the SFV cells those rows couple to
-//      (recomputed from the old iterate, so that the step needs no grid-wide
-//      ordering), followed by the segment solves y = B^{-1} t.  One launch,
-//      or, from 2048^2 cells, a tile kernel and then the PLG groups;
+//      from Jacobi-updated values of the SFV cells those rows couple to,
+//      followed by the segment solves y = B^{-1} t.  One launch, in which
+//      the PLG groups recompute those values from the old iterate (so that
+//      the step needs no grid-wide ordering), or, from 2048^2 cells, a tile
+//      kernel and then the PLG groups, which read them from its output;
 //   B: the separator Schur-complement solve and the segment corrections
 //      (only on levels with separators; two launches from 768 separators).
 // Tiles and PLG blocks are handed to the 8 XCDs in runs of consecutive
@@ -315,8 +316,10 @@ __device__ __forceinline__ void jacobi_tile(const LevelArgs &L, const T *__restr
 // Launch A, PLG role: one group of PLG rows (a segment slice, or a run of
 // separator rows).  Dense row-major blocks are applied one wavefront per
 // row, 8 rows at a time: the 64 lanes read consecutive columns and the
-// partial sums are reduced across the wavefront.
-template <typename T, bool MIXED>
+// partial sums are reduced across the wavefront.  HNEW: the tile role has
+// already run (an earlier launch on the same stream), so the Jacobi-updated
+// SFV values are read from unew instead of being recomputed.
+template <typename T, bool MIXED, bool HNEW>
 __device__ __forceinline__ void plg_group(const LevelArgs &L, const T *__restrict__ uold, const T *__restrict__ b,
                                           T *__restrict__ unew, bool uzero, const PlgDev<T> &P, int bi, T *lds) {
     const PlgBlkA bk = P.blk1[bi];
@@ -344,7 +347,9 @@ __device__ __forceinline__ void plg_group(const LevelArgs &L, const T *__restric
     for (int k = threadIdx.x; k < bk.nh; k += NT) {
         const int id = P.hcell[bk.h0 + k];
         T v;
-        if (uzero) {
+        if (HNEW) {
+            v = unew[id];
+        } else if (uzero) {
             v = wod * b[id];
         } else {
             const int j = id / L.pitch - 2, i = id - (j + 2) * L.pitch - 2;
@@ -423,7 +428,7 @@ __device__ __forceinline__ int xcd_tile(int bid, int n) {
     return x * q + min(x, r) + k;
 }
 
-template <typename T, bool MIXED, int TYv>
+template <typename T, bool MIXED, int TYv, bool HNEW = false>
 __global__ __launch_bounds__(NT) void k_smooth_a(LevelArgs L, const T *__restrict__ uold, const T *__restrict__ b,
                                                  T *__restrict__ unew, const uint8_t *__restrict__ mask, int tiles_x,
                                                  int ntile, int uzero, PlgDev<T> P) {
@@ -436,13 +441,15 @@ __global__ __launch_bounds__(NT) void k_smooth_a(LevelArgs L, const T *__restric
                                    reinterpret_cast<T(*)[HX]>(smem), gws);
         return;
     }
-    plg_group<T, MIXED>(L, uold, b, unew, uzero != 0, P, xcd_tile(bid - ntile, P.nblk1), reinterpret_cast<T *>(smem));
+    plg_group<T, MIXED, HNEW>(L, uold, b, unew, uzero != 0, P, xcd_tile(bid - ntile, P.nblk1),
+                              reinterpret_cast<T *>(smem));
 }
 
 // Launch A on large grids, tile role alone: it needs far fewer registers
 // than the PLG role (about 55 against 145 VGPRs in FP32), so a kernel of its
 // own keeps more waves per SIMD in flight to cover the memory latency; the
-// PLG groups follow as k_smooth_a with no tiles.
+// PLG groups follow as k_smooth_a with no tiles, reading the SFV values the
+// tiles wrote.
 constexpr long long SPLIT_CELLS = 2048LL * 2048;
 // tile height of k_smooth_tiles (the shorter FP64 tiles need fewer registers)
 template <typename T>
@@ -892,7 +899,8 @@ void launch_smooth_a(const LevelArgs &L, const T *uold, const T *b, T *unew, con
     const int tiles_x = (L.nx + TX - 1) / TX, ntile = tiles_x * ((L.ny + ty - 1) / ty);
     const int uz = uzero ? 1 : 0;
     if (!small && (long long)L.nx * L.ny >= SPLIT_CELLS) {
-        // the two roles write disjoint cells (SFV tiles, PLG rows)
+        // the tiles write the SFV cells, then the PLG groups read those
+        // of their couplings and write the PLG rows
         constexpr int tys = ty_split<T>();
         const int nts = tiles_x * ((L.ny + tys - 1) / tys);
         if (L.mixed)
@@ -902,12 +910,9 @@ void launch_smooth_a(const LevelArgs &L, const T *uold, const T *b, T *unew, con
             hipLaunchKernelGGL((k_smooth_tiles<T, false, tys>), dim3(nts), dim3(NT), 0, st, L, uold, b, unew,
                                mask, tiles_x, uz);
         if (P.nblk1 == 0) return;
-        if (L.mixed)
-            hipLaunchKernelGGL((k_smooth_a<T, true, TY>), dim3(P.nblk1), dim3(NT), 0, st, L, uold, b, unew, mask,
-                               tiles_x, 0, uz, P);
-        else
-            hipLaunchKernelGGL((k_smooth_a<T, false, TY>), dim3(P.nblk1), dim3(NT), 0, st, L, uold, b, unew, mask,
-                               tiles_x, 0, uz, P);
+        // no stencil is evaluated here, so one instantiation serves b = 0 and b != 0
+        hipLaunchKernelGGL((k_smooth_a<T, false, TY, true>), dim3(P.nblk1), dim3(NT), 0, st, L, uold, b, unew,
+                           mask, tiles_x, 0, uz, P);
         return;
     }
     const dim3 grid(ntile + P.nblk1);

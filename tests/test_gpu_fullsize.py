@@ -163,3 +163,43 @@ def test_star4096_cubic_solution(precision):
         "mixed" if precision else "fp64", tau, it, rel, err, umax, bmax))
     assert tau <= 1e-12 * bmax
     assert err <= 0.1 * 1e-10 * bmax + 1e-9 * umax
+
+
+@pytest.mark.parametrize("which", ["star", "three_disks"])
+def test_split_sweep_2048(which):
+    """At 2048^2 cells launch A runs as two kernels: the SFV tiles, then the
+    PLG groups, which take the Jacobi-updated SFV values they couple to from
+    the tiles' output.  One FP64 sweep from a seeded random state must move
+    every SFV cell by omega/D times its old residual (eq. (5.5)) and leave
+    every PLG row with zero residual, since the A22 solve of Definition 5.6
+    is exact; a PLG group that used other SFV values than the new ones would
+    leave residuals of the size of the old ones there.  The star has b != 0
+    and a Robin hole, the three disks b = 0; both levels have separators."""
+    torch = _torch()
+    import paper_2601_02975_amd as mg
+    P = W.star_config(0, 2048) if which == "star" else W.three_disks_config(0, 2048)
+    S = mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps)
+    assert S.info["n_sep"][0] > 0
+    nx, ny, h = P.grid.nx, P.grid.ny, P.grid.h
+    kind = S.export_level(0)[0]
+    act, sfv, plg = kind != 0, kind == 1, kind == 2
+    rng = np.random.default_rng(21)
+    u0 = S.empty(0)
+    b = S.empty(0)
+    u0[2:ny + 2, 2:nx + 2] = torch.tensor(np.where(act, rng.standard_normal((ny, nx)), 0.0), device="cuda")
+    b[2:ny + 2, 2:nx + 2] = torch.tensor(np.where(act, rng.standard_normal((ny, nx)) / (h * h), 0.0),
+                                         device="cuda")
+    r0, r1 = S.empty(0), S.empty(0)
+    S.residual(0, b, u0, r0)
+    u = u0.clone()
+    S.smooth(0, b, u)
+    S.residual(0, b, u, r1)
+    u0h, uh, r0h, r1h = (t[2:ny + 2, 2:nx + 2].cpu().numpy() for t in (u0, u, r0, r1))
+    wod = 0.5 / (-5.0 * (P.a + P.c) / (2.0 * h * h))
+    want = u0h + wod * r0h
+    e_sfv = float(np.abs(uh - want)[sfv].max() / np.abs(want[sfv]).max())
+    e_plg = float(np.abs(r1h[plg]).max() / np.abs(r0h[act]).max())
+    print("%s 2048: SFV update rel diff %.2e, PLG residual after the sweep %.2e of the old residual" % (
+        which, e_sfv, e_plg))
+    assert e_sfv <= 1e-12
+    assert e_plg <= 1e-9
