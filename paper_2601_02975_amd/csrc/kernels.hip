@@ -428,6 +428,19 @@ __device__ __forceinline__ int xcd_tile(int bid, int n) {
     return x * q + min(x, r) + k;
 }
 
+// Block order of launch A.  In FP32 the tiles come first.  In FP64 fewer
+// blocks are resident at once, so the PLG blocks (the longer dependency
+// chains) come first to start early; their section is padded to a multiple
+// of 8 blocks so that the tiles keep their XCD-aligned order.
+template <typename T>
+constexpr bool plg_first() {
+    return sizeof(T) == 8;
+}
+template <typename T>
+__host__ __device__ __forceinline__ int plg_section(int nblk1) {
+    return plg_first<T>() ? (nblk1 + 7) & ~7 : nblk1;
+}
+
 template <typename T, bool MIXED, int TYv, bool HNEW = false>
 __global__ __launch_bounds__(NT) void k_smooth_a(LevelArgs L, const T *__restrict__ uold, const T *__restrict__ b,
                                                  T *__restrict__ unew, const uint8_t *__restrict__ mask, int tiles_x,
@@ -435,13 +448,16 @@ __global__ __launch_bounds__(NT) void k_smooth_a(LevelArgs L, const T *__restric
     __shared__ __align__(16) unsigned char smem[smooth_a_lds<T, TYv>()];
     __shared__ double gws[32];
     const int bid = blockIdx.x;
-    if (bid < ntile) {
-        const int t = xcd_tile(bid, ntile);
+    const int tile0 = plg_first<T>() ? plg_section<T>(P.nblk1) : 0;         // first tile block
+    const int plg0 = plg_first<T>() ? 0 : ntile;                             // first PLG block
+    if (bid >= tile0 && bid < tile0 + ntile) {
+        const int t = xcd_tile(bid - tile0, ntile);
         jacobi_tile<T, MIXED, TYv>(L, uold, b, unew, mask, uzero != 0, (t % tiles_x) * TX, (t / tiles_x) * TYv,
                                    reinterpret_cast<T(*)[HX]>(smem), gws);
         return;
     }
-    plg_group<T, MIXED, HNEW>(L, uold, b, unew, uzero != 0, P, xcd_tile(bid - ntile, P.nblk1),
+    if (bid - plg0 >= P.nblk1) return;                                       // padding of the PLG section
+    plg_group<T, MIXED, HNEW>(L, uold, b, unew, uzero != 0, P, xcd_tile(bid - plg0, P.nblk1),
                               reinterpret_cast<T *>(smem));
 }
 
@@ -915,7 +931,7 @@ void launch_smooth_a(const LevelArgs &L, const T *uold, const T *b, T *unew, con
                            mask, tiles_x, 0, uz, P);
         return;
     }
-    const dim3 grid(ntile + P.nblk1);
+    const dim3 grid(ntile + plg_section<T>(P.nblk1));
 #define MG_SA(MX, TYV) \
     hipLaunchKernelGGL((k_smooth_a<T, MX, TYV>), grid, dim3(NT), 0, st, L, uold, b, unew, mask, tiles_x, ntile, uz, P)
     if (L.mixed) { if (small) MG_SA(true, TY_SMALL); else MG_SA(true, TY); }
