@@ -1,14 +1,15 @@
 """Solves/s to a 1e-10 relative residual on one MI355X.
 
-Workload: [0,1]^2 minus 3 seeded disks (radius U[0.05, 0.15]), 1024 x 1024
-cells, a=1, b=0.5, c=2, Dirichlet outside, Neumann on the holes, 6 seeded
-sine modes (seed 0).  A step is one whole solve from u = 0 (V-cycles of
-Algorithm 3 with nu = (6, 6) until ||b - A u||_inf <= 1e-10 ||b||_inf) with
-the inputs already resident on the device.  `value` is the mixed-precision
-rate (FP32 V-cycles inside FP64 defect correction); the plain FP64 rate is
-reported beside it, the same solve with the FMG cycle of Algorithm 4 and with
-nu = (3, 3) as variants, and the 4096^2 star workload (Robin hole, cross
-term) as a second line with its own roofline figure.
+Headline workload: [0,1]^2 minus a seeded 8-point star joined to circular
+arcs, 4096 x 4096 cells, a=2, b=-1, c=1, Robin (1, 0.5) on the star,
+Dirichlet outside, 8 seeded sine modes (seed 0).  A step is one whole solve
+from u = 0 (V-cycles of Algorithm 3 with nu = (6, 6) until
+||b - A u||_inf <= 1e-10 ||b||_inf) with the inputs already resident on the
+device.  `value` is the mixed-precision rate (FP32 V-cycles inside FP64
+defect correction); the plain FP64 rate is reported beside it, timed the same
+way (replays of the captured outer iteration).  Further lines: the 1024^2
+three-disk workload, the FMG cycle and nu = (3, 3) as variants, two serving
+traces, and the FP64 oracle on the host cores.
 
 Prints one JSON line.  --gpus above 1 is refused: the solver runs on one GPU.
 """
@@ -16,7 +17,10 @@ import argparse
 import hashlib
 import json
 import math
+import multiprocessing as mp
 import os
+import platform
+import subprocess
 import sys
 import time
 
@@ -24,9 +28,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# smoothing steps (nu1, nu2) of every solve here; the paper's (3, 3) is reported
-# as a variant
+# smoothing steps (nu1, nu2) of every solve here; the paper's (3, 3) is
+# reported as a variant (deep V(3,3)-cycles are not h-independent with the
+# piecewise-constant interpolation of eq. (5.9))
 NU = (6, 6)
+# Gauss points per direction for the cell averages <f> over full cells
+# (exact to degree 2 GP - 1 per variable; the cut cells use the library's
+# own rules): 8 up to 1024^2, 4 above, where the quadrature error of a
+# degree-7 rule on cells of h <= 1/2048 is far below the solver tolerance
+def gauss_points(n):
+    return 8 if n <= 1024 else 4
 
 
 def kernel_source_hash():
@@ -36,31 +47,31 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic_for(name, precision):
-    """HBM bytes per launch of the finest-level smoother launch A of a workload
-    from the committed rocprofv3 counter summary, if it was taken on the
-    current kernel source."""
-    path = os.path.join(ROOT, "profiles", "traffic_smooth_a_%s.json" % name)
+def load_traffic_for(name, kernel):
+    """HBM bytes per launch of `kernel` on a workload's finest level from the
+    committed rocprofv3 counter summary, if it was taken on the current
+    kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % name)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
     if rec.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    return rec.get("bytes_per_launch", {}).get(precision)
+    return rec.get("bytes_per_launch", {}).get(kernel)
 
 
-def timed_solves(torch, S, f, g, steps, warmup, tol, record=False):
+def timed_solves(torch, S, f, g, steps, warmup, tol):
+    """`steps` solves from u = 0 after `warmup` untimed ones; every solve
+    replays the captured outer iteration."""
     u = torch.zeros_like(f)
-    iters = []
     for _ in range(warmup):
         u.zero_()
         it, rel, code = S.solve(f, g, u, tol)
         if code != 0:
             raise RuntimeError("solve did not converge (code %d, rel %.2e after %d)" % (code, rel, it))
     torch.cuda.synchronize()
-    if record:
-        S.kernel_timing(True)
+    iters = []
     t0 = time.perf_counter()
     for _ in range(steps):
         u.zero_()
@@ -69,41 +80,127 @@ def timed_solves(torch, S, f, g, steps, warmup, tol, record=False):
         if code != 0:
             raise RuntimeError("solve did not converge (code %d, rel %.2e after %d)" % (code, rel, it))
     torch.cuda.synchronize()
+    return time.perf_counter() - t0, iters, rel, u
+
+
+def kernel_time(torch, S, f, g, solves, tol):
+    """Average duration of the finest level's SFV tile kernel over `solves`
+    solves that replay graphs with HIP events recorded around that kernel
+    (on the stream it runs on), and the time per solve in that mode."""
+    u = torch.zeros_like(f)
+    S.kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(solves):
+        u.zero_()
+        S.solve(f, g, u, tol)
+    torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    launches, avg_ms = S.kernel_timing(False) if record else (0, 0.0)
-    return dt, iters, rel, u, launches, avg_ms
+    launches, avg_ms = S.kernel_timing(False)
+    return launches, avg_ms, dt / solves
 
 
-def cpu_baseline(P, gpu_iters, sample_cycles, cycle):
-    """The oracle (plain NumPy/SciPy, FP64) on the same workload: time a
-    bounded number of its cycles (FMG on the residual equation, or V-cycles)
-    and scale to one solve with the iteration count the solve needs (the GPU
-    FP64 iteration count: the iterates agree)."""
+def roofline(S, avg_ms, launches, traffic):
+    """k_smooth_tiles<float> on the finest level (the dominant kernel of the
+    mixed solve): algorithmic bytes 3 w per SFV cell (u and b read, u
+    written; w = 4 bytes) over its average duration."""
+    alg_bytes = 12 * S.info["n_sfv"][0]
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None
+    return {"bound": "hbm", "kernel": "k_smooth_tiles<float> (finest level: omega-Jacobi on the SFV cells)",
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+            "launches_timed": launches, "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": alg_bytes,
+            "sfv_cells": S.info["n_sfv"][0]}
+
+
+def fp64_floor(torch, S, f, g, cycles):
+    """The FP64 relative residual the GPU's FP64 iteration stagnates at: the
+    smallest over `cycles` V-cycles from u = 0 (tolerance below reach)."""
+    import paper_2601_02975_amd as mg
+    u = torch.zeros_like(f)
+    it, rel, code = S.solve(f, g, u, 1e-17)
+    return {"min_rel_residual": rel, "cycles": it, "status": mg.STATUS.get(code, code)}
+
+
+# --------------------------------------------------------------------------
+# the oracle on the host cores
+def _oracle_cycles(H, b, seconds, out):
+    import numpy as np
+    A = H.levels[0].A
+    u = np.zeros_like(b)
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        u = H.vcycle(0, u, b)
+        _ = float(np.abs(b - A @ u).max())
+        n += 1
+    out.put((n, time.perf_counter() - t0))
+
+
+_ORACLE = {}
+
+
+def _oracle_worker(seconds, q):
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(1):
+        _oracle_cycles(_ORACLE["H"], _ORACLE["b"], seconds, q)
+
+
+def cpu_baseline(n_sample, gpu_iters, n_cells_headline, seconds):
+    """The FP64 oracle (plain NumPy/SciPy, as it stands): V-cycles with NU on
+    the three-disk workload at n_sample^2 (the same 25-point operator as the
+    headline's, b != 0; the oracle sets it up in about a minute, the star
+    at that size takes several) for `seconds` on one core, then one process
+    per core (at most 16) for the same time; scaled to the headline's cells
+    (the V-cycle is linear in the cells) and the GPU's iteration count."""
     from threadpoolctl import threadpool_limits
 
+    import workloads as W
     from oracle.multigrid import Hierarchy
     from oracle.rhs import rhs
+    P = W.three_disks_config(0, n_sample)
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        H = Hierarchy(P.grid, P.curves, P.a, P.b, P.c, P.eps, nu=NU,
-                      progress=lambda msg: print("oracle setup: " + msg, file=sys.stderr, flush=True))
+        H = Hierarchy(P.grid, P.curves, P.a, P.b, P.c, P.eps, nu=NU)
         t_setup = time.perf_counter() - t0
         b, _, _ = rhs(H.levels[0], P.solution)
-        A = H.levels[0].A
-        u = b * 0.0
-        t0 = time.perf_counter()
-        for _ in range(sample_cycles):
-            u = u + H.fmg(0, b - A @ u) if cycle == "FMG" else H.vcycle(0, u, b)
-            r = b - A @ u
-            _ = float(abs(r).max())
-        t_cycle = (time.perf_counter() - t0) / sample_cycles
-    per_solve = gpu_iters * t_cycle
-    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": "%d %s-cycles, nu = (6, 6), (with residual norms) of the FP64 oracle on the same 1024^2 workload, "
-                      "%.3f s each, scaled by the %d cycles a solve to 1e-10 takes; oracle setup %.1f s "
-                      "not included" % (sample_cycles, cycle, t_cycle, gpu_iters, t_setup)}
+    _ORACLE["H"], _ORACLE["b"] = H, b
+    ctx = mp.get_context("fork")
+    q = ctx.Queue()
+    _oracle_worker(seconds, q)
+    n1, t1 = q.get()
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = min(cores, 16)            # the host share of one GPU
+    procs = [ctx.Process(target=_oracle_worker, args=(seconds, q)) for _ in range(cores)]
+    for p in procs:
+        p.start()
+    res = [q.get() for _ in procs]
+    for p in procs:
+        p.join()
+    cyc_all = sum(n for n, _ in res) / max(t for _, t in res)
+    scale = n_cells_headline / float(P.grid.nx * P.grid.ny)
+    t_cycle_1 = t1 / n1
+    per_solve_1 = gpu_iters * t_cycle_1 * scale
+    per_solve_all = gpu_iters * scale / cyc_all
+    try:
+        lscpu = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        model = next((l.split(":", 1)[1].strip() for l in lscpu.splitlines() if l.startswith("Model name")), "")
+    except Exception:
+        model = platform.processor()
+    return {"value": 1.0 / per_solve_all, "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "one_core": {"value": 1.0 / per_solve_1, "unit": "solves/s", "cores": 1},
+            "host": {"cpu": model, "cores_available": cores, "nproc": os.cpu_count()},
+            "sample": "FP64 oracle V-cycles (nu = %s, residual norm each) on the three-disk workload at %d^2 "
+                      "(oracle setup %.1f s, not timed): %d cycles in %.1f s on 1 core (%.3f s each); "
+                      "%d processes, one per core, %.1f cycles/s together; scaled by the cells (x%.0f) and the "
+                      "%d cycles of the GPU's solve" % (NU, n_sample, t_setup, n1, t1, t_cycle_1, cores,
+                                                         cyc_all, scale, gpu_iters)}
 
 
+# --------------------------------------------------------------------------
 def serving_leg(torch, mg, W, geoms, n_rhs, qps, slots, tol, label):
     """Serving with resident hierarchies: every geometry is set up in the
     server by one warm-up request; then n_rhs right-hand sides per geometry
@@ -118,10 +215,7 @@ def serving_leg(torch, mg, W, geoms, n_rhs, qps, slots, tol, label):
     gaps = rng.exponential(1.0 / qps, size=len(reqs))
     seq = {p: [mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=p, max_iters=1000, nu=NU)
                for P in geoms] for p in (mg.FP64, mg.MIXED)}
-    inputs = []
-    for k, P in reqs:
-        f, g = seq[mg.FP64][k].project(P.solution)
-        inputs.append((torch.tensor(f, device="cuda"), torch.tensor(g, device="cuda")))
+    inputs = [seq[mg.FP64][k].project(P.solution, gauss_points(P.grid.nx)) for k, P in reqs]
     seq_rate = {}
     for p, name in ((mg.FP64, "fp64"), (mg.MIXED, "mixed")):
         torch.cuda.synchronize()
@@ -163,51 +257,36 @@ def serving_leg(torch, mg, W, geoms, n_rhs, qps, slots, tol, label):
             "setup_latency_s_max": max(setup_lat)}
 
 
-def roofline(S, n_cells, avg_ms, launches, traffic, kernel="k_smooth_a<float> (finest level: SFV Jacobi tiles + "
-                                                                 "PLG segment solves)"):
-    """Finest-level FP32 launch A: u, b read and u written on the SFV cells,
-    the PLG segment inverses read once, b read and u/y written on the PLG rows
-    (words of 4 bytes), plus one byte of class mask per cell."""
-    alg_bytes = 4 * S.info["sweep_words"][0] + n_cells
-    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None
-    return {"bound": "hbm", "kernel": kernel,
-            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
-            "launches_timed": launches, "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": alg_bytes}
-
-
-def star_leg(torch, mg, W, steps, warmup, tol):
-    """The 4096^2 star workload (Robin star hole, a=2, b=-1, c=1): V-cycles
-    with NU in mixed precision and FP64."""
-    P = W.star_config(0, 4096)
+def solve_leg(torch, mg, P, steps, warmup, tol, timing_solves, label):
+    """Mixed and FP64 solves of one workload, both replaying graphs; the
+    tile kernel's duration from a separate pass with in-graph events."""
+    n = P.grid.nx
     t0 = time.perf_counter()
     S32 = mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=mg.MIXED, max_iters=1000, nu=NU)
     t_setup = time.perf_counter() - t0
     S64 = mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=mg.FP64, max_iters=1000, nu=NU)
-    fh, gh = S32.project(P.solution)
-    f = torch.tensor(fh, device="cuda")
-    g = torch.tensor(gh, device="cuda")
-    print("star 4096: setup %.1f s, levels %s, PLG cells %s" % (t_setup, S32.info["nx"], S32.info["n_plg"]),
-          file=sys.stderr, flush=True)
-    dt64, it64, rel64, u64, _, _ = timed_solves(torch, S64, f, g, steps, warmup, tol)
-    print("star 4096 fp64: %.4f s/solve, %d iterations" % (dt64 / steps, it64[-1]), file=sys.stderr, flush=True)
-    dt32, it32, rel32, u32, nl, avg_ms = timed_solves(torch, S32, f, g, steps, warmup, tol, True)
-    print("star 4096 mixed: %.4f s/solve, %d iterations" % (dt32 / steps, it32[-1]), file=sys.stderr, flush=True)
+    f, g = S32.project(P.solution, gauss_points(n))
+    print("%s: setup %.1f s, levels %s, PLG cells %s, separators %s" % (
+        label, t_setup, S32.info["nx"], S32.info["n_plg"], S32.info["n_sep"]), file=sys.stderr, flush=True)
+    dt64, it64, rel64, u64 = timed_solves(torch, S64, f, g, steps, warmup, tol)
+    print("%s fp64: %.4f s/solve, %d iterations" % (label, dt64 / steps, it64[-1]), file=sys.stderr, flush=True)
+    dt32, it32, rel32, u32 = timed_solves(torch, S32, f, g, steps, warmup, tol)
+    print("%s mixed: %.4f s/solve, %d iterations" % (label, dt32 / steps, it32[-1]), file=sys.stderr, flush=True)
+    launches, avg_ms, t_timed = kernel_time(torch, S32, f, g, timing_solves, tol)
+    print("%s tile kernel: %d launches, %.2f us each" % (label, launches, 1e3 * avg_ms), file=sys.stderr, flush=True)
     diff = float((u32 - u64).abs().max() / u64.abs().max())
-    n_cells = P.grid.nx * P.grid.ny
-    out = {"workload": "star_4096x4096_seed0 (8-point star with arcs, Robin (1, 0.5) on the star, Dirichlet box; "
-                       "a=2, b=-1, c=1; 8 sine modes)", "levels": S32.info["nx"], "plg_cells": S32.info["n_plg"],
-           "solver": "V-cycles (Algorithm 3), nu = %s" % (NU,),
-           "mixed": {"value": steps / dt32, "unit": "solves/s", "iterations": it32[-1], "rel_residual": rel32,
-                     "max_rel_diff_vs_fp64": diff},
-           "fp64": {"value": steps / dt64, "unit": "solves/s", "iterations": it64[-1], "rel_residual": rel64},
+    out = {"levels": S32.info["nx"], "plg_cells": S32.info["n_plg"], "separators": S32.info["n_sep"],
+           "sfv_cells": S32.info["n_sfv"], "setup_s": t_setup,
+           "setup_stage_s": dict(zip(("cut_cells", "classification_lattices_moments", "fits", "plg_solver",
+                                      "bottom_inverse", "other"), S32.info["setup_stage_seconds"])),
+           "cond_A22": S32.info["cond_A22"],
+           "mixed": {"value": steps / dt32, "unit": "solves/s", "ms_per_solve": 1e3 * dt32 / steps,
+                     "iterations": it32[-1], "rel_residual": rel32, "max_rel_diff_vs_fp64": diff},
+           "fp64": {"value": steps / dt64, "unit": "solves/s", "ms_per_solve": 1e3 * dt64 / steps,
+                    "iterations": it64[-1], "rel_residual": rel64},
            "speedup_mixed_over_fp64": dt64 / dt32,
-           "roofline": roofline(S32, n_cells, avg_ms, nl, load_traffic_for("star4096", "fp32"),
-                                "launch A on the finest level: k_smooth_tiles<float> (SFV Jacobi tiles) then "
-                                "k_smooth_a<float> (PLG segment solves)")}
-    S32.close()
-    S64.close()
-    return out
+           "ms_per_solve_with_kernel_events": 1e3 * t_timed}
+    return out, S32, S64, f, g, dt32, it64, (launches, avg_ms)
 
 
 def main():
@@ -215,18 +294,25 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--tol", type=float, default=1e-10)
-    ap.add_argument("--cpu-cycles", type=int, default=3)
+    ap.add_argument("--timing-solves", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=8.0)
+    ap.add_argument("--cpu-n", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--no-star", action="store_true")
-    ap.add_argument("--only-star", action="store_true", help="run only the 4096^2 star leg")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the 1024^2 three-disk line")
+    ap.add_argument("--only-headline", action="store_true", help="the 4096^2 star line only")
+    ap.add_argument("--cpu-baseline-worker", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-iters", type=int, default=0, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-cells", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also move 256 MiB with the runtime's copy kernel and with an elementwise kernel "
                          "(references for HBM byte counters)")
     args = ap.parse_args()
+    if args.cpu_baseline_worker:
+        print(json.dumps(cpu_baseline(args.cpu_n, args.cpu_iters, args.cpu_cells, args.cpu_seconds)))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (--gpus %d refused)" % args.gpus,
               file=sys.stderr)
@@ -243,33 +329,15 @@ def main():
         dst_t = torch.empty_like(src_t)
         for _ in range(3):
             dst_t.copy_(src_t)
-        # the same bytes through an ordinary elementwise kernel (plain loads
-        # and stores, unlike the runtime's copy kernel)
         for _ in range(3):
             torch.mul(src_t, 2.0, out=dst_t)
         torch.cuda.synchronize()
         print("calibration copy: 3 + 3 x %d bytes read and written" % (src_t.numel() * 8), file=sys.stderr)
         del src_t, dst_t
-    if args.only_star:
-        print(json.dumps({"star4096": star_leg(torch, mg, W, args.steps, args.warmup, args.tol)}))
-        return
 
-    P = W.three_disks_config(0, args.n)
-    t0 = time.perf_counter()
-    S32 = mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=mg.MIXED, max_iters=1000, nu=NU)
-    t_setup = time.perf_counter() - t0
-    S64 = mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=mg.FP64, max_iters=1000, nu=NU)
-    fh, gh = S64.project(P.solution)
-    f = torch.tensor(fh, device="cuda")
-    g = torch.tensor(gh, device="cuda")
-    print("setup %.2f s, levels %s, PLG cells %s, separators %s" % (
-        t_setup, S64.info["nx"], S64.info["n_plg"], S64.info["n_sep"]), file=sys.stderr, flush=True)
-
-    dt64, it64, rel64, u64, _, _ = timed_solves(torch, S64, f, g, args.steps, args.warmup, args.tol)
-    print("fp64: %.4f s/solve, %d iterations" % (dt64 / args.steps, it64[-1]), file=sys.stderr, flush=True)
-    dt32, it32, rel32, u32, nl, avg_ms = timed_solves(torch, S32, f, g, args.steps, args.warmup, args.tol, True)
-    print("mixed: %.4f s/solve, %d iterations" % (dt32 / args.steps, it32[-1]), file=sys.stderr, flush=True)
-    diff = float((u32 - u64).abs().max() / u64.abs().max())
+    P = W.star_config(0, 4096)
+    head, S32, S64, f, g, dt32, it64, (launches, avg_ms) = solve_leg(
+        torch, mg, P, args.steps, args.warmup, args.tol, args.timing_solves, "star 4096")
     n_cells = P.grid.nx * P.grid.ny
     out = {
         "metric": "solves/s to 1e-10 rel. residual (mixed vs FP64 GPU), HBM GB/s; p50/p99 latency",
@@ -284,51 +352,89 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 V-cycles in f64 defect correction",
         "data": "synthetic",
-        "config": {"workload": "three_disks_1024x1024_seed0 (a=1, b=0.5, c=2; Dirichlet box, Neumann holes; "
-                               "6 sine modes)", "tol": args.tol, "cells": n_cells,
-                   "solver": "V-cycles (Algorithm 3), nu = %s, omega = 1/2" % (NU,),
-                   "levels": S64.info["nx"], "plg_cells": S64.info["n_plg"]},
-        "fp64": {"value": args.steps / dt64, "unit": "solves/s", "iterations": it64[-1], "rel_residual": rel64},
-        "mixed": {"iterations": it32[-1], "rel_residual": rel32, "max_rel_diff_vs_fp64": diff},
-        "speedup_mixed_over_fp64": dt64 / dt32,
-        "roofline": roofline(S32, n_cells, avg_ms, nl, load_traffic_for("three_disks1024", "fp32")),
+        "config": {"workload": "star_4096x4096_seed0: [0,1]^2 minus an 8-point star joined to circular arcs; "
+                               "a=2, b=-1, c=1; Robin (1, 0.5) on the star, Dirichlet box; 8 sine modes",
+                   "tol": args.tol, "cells": n_cells,
+                   "solver": "V-cycles (Algorithm 3), nu = %s, omega = 1/2; graph replay" % (NU,)},
     }
+    out.update(head)
+    out["roofline"] = roofline(S32, avg_ms, launches, load_traffic_for("star4096", "k_smooth_tiles_fp32"))
+    out["fp64_floor"] = fp64_floor(torch, S64, f, g, 60)
+    print("fp64 floor: %s" % out["fp64_floor"], file=sys.stderr, flush=True)
     S32.close()
     S64.close()
-    if not args.no_variants:
-        # the same solve with the paper's FMG cycle and with nu = (3, 3)
+    if not args.no_variants and not args.only_headline:
+        # the same solve with the FMG cycle, fewer sweeps, and the
+        # multicolour smoother
         var = {}
-        for cyc, nu, name in ((mg.CYCLE_FMG, NU, "fmg_nu%d%d" % NU), (mg.CYCLE_V, (3, 3), "v_nu33"),
-                              (mg.CYCLE_FMG, (3, 3), "fmg_nu33")):
-            S = mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=mg.MIXED, max_iters=1000,
-                          nu=nu, cycle=cyc)
-            dt, it, rel, _, _, _ = timed_solves(torch, S, f, g, args.steps, args.warmup, args.tol)
+        for kw, name in ((dict(cycle=mg.CYCLE_FMG), "fmg_nu66"), (dict(nu=(4, 4)), "v_nu44"),
+                         (dict(colouring=mg.SMOOTH_MULTICOLOUR), "v_nu66_multicolour"),
+                         (dict(colouring=mg.SMOOTH_MULTICOLOUR, nu=(4, 4)), "v_nu44_multicolour")):
+            opts = dict(eps=P.eps, precision=mg.MIXED, max_iters=1000, nu=NU)
+            opts.update(kw)
+            S = mg.Solver(P.grid, P.curves, P.a, P.b, P.c, **opts)
+            try:
+                dt, it, rel, _ = timed_solves(torch, S, f, g, args.steps, args.warmup, args.tol)
+                var[name] = {"value": args.steps / dt, "unit": "solves/s", "iterations": it[-1],
+                             "rel_residual": rel, "precision": "mixed"}
+                print("star variant %s: %.4f s/solve, %d iterations" % (name, dt / args.steps, it[-1]),
+                      file=sys.stderr, flush=True)
+            except (RuntimeError, mg.MGError) as e:
+                var[name] = {"error": str(e)}
             S.close()
-            var[name] = {"value": args.steps / dt, "unit": "solves/s", "iterations": it[-1], "rel_residual": rel,
-                         "precision": "mixed"}
-            print("variant %s: %.4f s/solve, %d iterations" % (name, dt / args.steps, it[-1]), file=sys.stderr,
-                  flush=True)
         out["variants"] = var
-    if not args.no_star:
-        out["star4096"] = star_leg(torch, mg, W, args.steps, args.warmup, args.tol)
-    if not args.no_serving:
-        out["serving"] = serving_leg(torch, mg, W, [W.three_disks_config(s, 512) for s in range(1, 5)], 8, 400.0, 4,
-                                     args.tol, "4 three-disk geometries (seeds 1-4) at 512^2")
-        print("serving: p50 %.3f s, p99 %.3f s, %.1f solves/s" % (
-            out["serving"]["p50_latency_s"], out["serving"]["p99_latency_s"], out["serving"]["solves_per_s"]),
-            file=sys.stderr, flush=True)
-        # the request distribution of the serving trace: grids of 128^2 to
-        # 2048^2, 1-5 holes with mixed boundary conditions, seeded (a, b, c)
-        mix = [W.serving_request(0, k) for k in range(8)]
-        out["serving_mix"] = serving_leg(torch, mg, W, mix, 4, 200.0, 4, args.tol,
-                                         "the first 8 requests of serving trace 0 as geometries (grids %s; 1-5 "
-                                         "holes, mixed boundary conditions, seeded a, b, c)"
-                                         % "/".join(str(P.grid.nx) for P in mix))
-        print("serving mix: p50 %.3f s, p99 %.3f s, %.1f solves/s" % (
-            out["serving_mix"]["p50_latency_s"], out["serving_mix"]["p99_latency_s"],
-            out["serving_mix"]["solves_per_s"]), file=sys.stderr, flush=True)
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(P, it64[-1], args.cpu_cycles, "V")
+    del f, g
+    if not args.only_headline:
+        if not args.no_secondary:
+            P2 = W.three_disks_config(0, 1024)
+            sec, S32b, S64b, f2, g2, _, _, (nl2, ms2) = solve_leg(
+                torch, mg, P2, args.steps, args.warmup, args.tol, args.timing_solves, "three disks 1024")
+            sec["workload"] = ("three_disks_1024x1024_seed0: [0,1]^2 minus 3 seeded disks; a=1, b=0.5, c=2; "
+                               "Dirichlet box, Neumann holes; 6 sine modes")
+            sec["roofline"] = roofline(S32b, ms2, nl2, load_traffic_for("three_disks1024", "k_smooth_a_fp32"))
+            sec["roofline"]["kernel"] = "k_smooth_a<float> (finest level: SFV tiles and PLG groups, one kernel)"
+            S32b.close()
+            S64b.close()
+            if not args.no_variants:
+                var = {}
+                for cyc, nu, name in ((mg.CYCLE_FMG, NU, "fmg_nu%d%d" % NU), (mg.CYCLE_V, (3, 3), "v_nu33"),
+                                      (mg.CYCLE_FMG, (3, 3), "fmg_nu33")):
+                    S = mg.Solver(P2.grid, P2.curves, P2.a, P2.b, P2.c, eps=P2.eps, precision=mg.MIXED,
+                                  max_iters=1000, nu=nu, cycle=cyc)
+                    dt, it, rel, _ = timed_solves(torch, S, f2, g2, args.steps, args.warmup, args.tol)
+                    S.close()
+                    var[name] = {"value": args.steps / dt, "unit": "solves/s", "iterations": it[-1],
+                                 "rel_residual": rel, "precision": "mixed"}
+                    print("variant %s: %.4f s/solve, %d iterations" % (name, dt / args.steps, it[-1]),
+                          file=sys.stderr, flush=True)
+                sec["variants"] = var
+            out["three_disks1024"] = sec
+            del f2, g2
+        if not args.no_serving:
+            out["serving"] = serving_leg(torch, mg, W, [W.three_disks_config(s, 512) for s in range(1, 5)], 8,
+                                         400.0, 4, args.tol, "4 three-disk geometries (seeds 1-4) at 512^2")
+            print("serving: p50 %.3f s, p99 %.3f s, %.1f solves/s" % (
+                out["serving"]["p50_latency_s"], out["serving"]["p99_latency_s"], out["serving"]["solves_per_s"]),
+                file=sys.stderr, flush=True)
+            mix = [W.serving_request(0, k) for k in range(8)]
+            out["serving_mix"] = serving_leg(torch, mg, W, mix, 4, 200.0, 4, args.tol,
+                                             "the first 8 requests of serving trace 0 as geometries (grids %s; "
+                                             "1-5 holes, mixed boundary conditions, seeded a, b, c)"
+                                             % "/".join(str(Q.grid.nx) for Q in mix))
+            print("serving mix: p50 %.3f s, p99 %.3f s, %.1f solves/s" % (
+                out["serving_mix"]["p50_latency_s"], out["serving_mix"]["p99_latency_s"],
+                out["serving_mix"]["solves_per_s"]), file=sys.stderr, flush=True)
+        if not args.no_cpu:
+            # in a fresh interpreter that never touches the GPU (its worker
+            # processes are forked from it)
+            r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-worker",
+                                "--cpu-n", str(args.cpu_n), "--cpu-seconds", str(args.cpu_seconds),
+                                "--cpu-iters", str(it64[-1]), "--cpu-cells", str(n_cells)],
+                               capture_output=True, text=True, timeout=900)
+            if r.returncode != 0:
+                raise RuntimeError("cpu baseline failed: " + r.stderr[-2000:])
+            out["cpu_baseline"] = json.loads(r.stdout.strip().splitlines()[-1])
+            print("cpu baseline: %s" % out["cpu_baseline"]["sample"], file=sys.stderr, flush=True)
     print(json.dumps(out))
 
 

@@ -85,6 +85,8 @@ typedef enum { MG_FP64 = 0, MG_MIXED = 1 } mg_precision;
  * (Algorithm 4) on the residual equation, u <- u + FMG(b - A u) (Sec. 5.4). */
 typedef enum { MG_CYCLE_V = 0, MG_CYCLE_FMG = 1 } mg_cycle;
 
+typedef enum { MG_SMOOTH_JACOBI = 0, MG_SMOOTH_MULTICOLOUR = 1 } mg_colouring;
+
 typedef struct {
     double eps;        /* volume-fraction threshold of Algorithm 1 (default 0.08) */
     double omega;      /* Jacobi weight of eq. (5.5) (default 0.5) */
@@ -94,6 +96,23 @@ typedef struct {
     int precision;     /* mg_precision (default MG_FP64) */
     int max_iters;     /* outer iterations of mg_solve (default 100) */
     int cycle;         /* mg_cycle (default MG_CYCLE_V) */
+    int degree;        /* degree n of the PLG fits, Sec. 4.2 (default 4: lattices of 15 cells;
+                          other values return MG_ERR_UNSUPPORTED) */
+    double w_min;      /* smallest weight of eq. (4.17): W^{-1} = diag(max(|d_k|, w_min)), and the
+                          weight of the boundary term (default 0.5) */
+    int colouring;     /* mg_colouring of the SFV half of the smoother (default MG_SMOOTH_JACOBI, the
+                          omega-Jacobi of eq. (5.5); MG_SMOOTH_MULTICOLOUR is an extension, see
+                          mg_setup) */
+    /* Launch shapes of the smoother (0 = the library's choice by grid size;
+     * they change timing only, never results): levels with at least
+     * split_cells cells run the SFV tiles and the PLG groups of launch A as
+     * two kernels (default 2048^2; 1 = every level); levels with at most
+     * small_cells cells use 8-row tiles in the fused kernel (default 512^2
+     * in FP32, 256^2 in FP64; -1 = never); levels with at least split_b_sep
+     * separator unknowns run launch B as two kernels (default 768; 1 =
+     * every level with separators). */
+    long long split_cells, small_cells;
+    int split_b_sep;
 } mg_options;
 
 typedef struct {
@@ -107,10 +126,19 @@ typedef struct {
                                   every PLG segment inverse read once, b read and u (or the
                                   segment solution) written on every PLG row; times the word
                                   size (8 FP64, 4 FP32), plus nx*ny bytes of the class mask */
+    long long n_sfv[16];       /* SFV cells per level */
     int n_face, n_irr;         /* boundary-data layout sizes (finest level) */
     long long nnz_plg;         /* nonzeros of the PLG rows, all levels */
     long long device_bytes;    /* device memory held by the handle */
-    double setup_seconds;
+    double setup_seconds;      /* wall time of mg_setup */
+    double cond_A22[16];       /* 1-norm condition number of A22 per level (Hager's estimate, a
+                                  lower bound that is usually exact; 0 without PLG cells) */
+    /* wall time of the setup stages, summed over levels (cf. Table 6):
+     * [0] cut cells and merging (Algorithm 1), [1] classification and
+     * lattices, [2] moments and the fits of the linear system, [3] the PLG
+     * block solver (ordering, factors) and its device layout, [4] the bottom
+     * inverse, [5] everything else (uploads, right-hand-side tables) */
+    double setup_stage_seconds[6];
 } mg_info;
 
 /* Defaults listed in mg_options. */
@@ -142,6 +170,20 @@ mg_status mg_vcycle(mg_handle h, const double *b_dev, double *u_dev, void *strea
 /* One block-smoother sweep (Definition 5.6) on level `level`; u_dev, b_dev
  * use that level's padded layout (nx_l + 4 columns). */
 mg_status mg_smooth(mg_handle h, int level, const double *b_dev, double *u_dev, void *stream);
+
+/* The same sweep in FP32 (the smoother of the mixed-precision V-cycle). */
+mg_status mg_smooth32(mg_handle h, int level, const float *b_dev, float *u_dev, void *stream);
+
+/* Residual restriction of Algorithm 3 (eq. (5.8)): bc_dev (level + 1's
+ * layout) = R (b - A u) on level `level`, every residual computed (also on
+ * PLG rows); precision MG_FP64 (double arrays) or MG_MIXED (float arrays). */
+mg_status mg_restrict(mg_handle h, int level, int precision, const void *b_dev, const void *u_dev, void *bc_dev,
+                      void *stream);
+
+/* Correction of Algorithm 3 (eq. (5.9)): u_dev (level `level`) += the
+ * piecewise-constant interpolation of ec_dev (level + 1); precision as for
+ * mg_restrict. */
+mg_status mg_prolong(mg_handle h, int level, int precision, const void *ec_dev, void *u_dev, void *stream);
 
 /* r_dev = b - A u on level `level` (r_dev may be NULL) and *rnorm = ||r||_inf
  * over active cells (rnorm may be NULL). */
@@ -175,18 +217,43 @@ mg_status mg_boundary_quadrature(mg_handle h, int *n, long long *nnodes, long lo
                                  double *x, double *y, double *w, double *nx, double *ny,
                                  int *bc, double *alpha1, double *alpha2);
 
+/* Forms the inputs of mg_solve from functions of the caller (host side,
+ * outside the solve; cf. eqs. (4.1)-(4.2)): f_dev receives the cell
+ * averages <f>_i and g_dev the boundary averages of the data, in the layouts
+ * of mg_solve.  The callbacks evaluate batches of n points:
+ *   f(n, x, y, out, ctx): out[k] = f(x[k], y[k]);
+ *   g(n, x, y, curve, seg, nx, ny, out, ctx): out[k] = the boundary datum
+ *   (N u)(x[k], y[k]) on segment seg of curve curve (box faces: curve 0, seg =
+ *   side 0 bottom, 1 right, 2 top, 3 left), (nx, ny) the outward unit normal.
+ * Full cells use a gauss_points x gauss_points Gauss-Legendre rule (1..16,
+ * exact for polynomials of degree 2 gauss_points - 1 in each variable); cut
+ * cells and the boundary use the rules of mg_cell_quadrature and
+ * mg_boundary_quadrature.  g may be NULL only when the layout of g is empty.
+ * Synchronises `stream`. */
+typedef void (*mg_f_batch)(long long n, const double *x, const double *y, double *out, void *ctx);
+typedef void (*mg_g_batch)(long long n, const double *x, const double *y, const int *curve, const int *seg,
+                           const double *nx, const double *ny, double *out, void *ctx);
+mg_status mg_project_rhs(mg_handle h, mg_f_batch f, mg_g_batch g, void *ctx, int gauss_points, double *f_dev,
+                         double *g_dev, void *stream);
+
 mg_status mg_destroy(mg_handle h);
 const char *mg_error_string(mg_status s);
 
-/* Kernel timing for measurement: enable = 1 clears and starts recording a
- * pair of HIP events around every finest-level launch of the smoother's
- * first kernel (the SFV Jacobi sweep of eq. (5.5) fused with the PLG
- * right-hand sides and segment solves of eq. (5.6); the dominant kernel) on
- * the stream it is launched on, and makes mg_solve launch eagerly;
- * enable = 0 stops recording, synchronises, and returns the number of
- * recorded launches and their average duration in milliseconds.  At most
- * 8192 launches are recorded. */
+/* Kernel timing for measurement: enable = 1 clears the record and makes
+ * mg_solve launch its outer iterations eagerly (instead of replaying its
+ * captured graphs) with a pair of HIP events recorded on the launch stream
+ * around every finest-level launch of the smoother's SFV tile kernel (the
+ * dominant kernel: the omega-Jacobi sweep of eq. (5.5); on levels where
+ * launch A is one kernel, that whole kernel).  enable = 0 stops recording
+ * and returns the number of recorded launches and their average duration in
+ * milliseconds. */
 mg_status mg_kernel_timing(mg_handle h, int enable, int *launches, double *avg_ms);
+
+/* eager = 1 makes mg_solve launch its kernels one by one on the caller's
+ * stream instead of replaying its captured HIP graphs (the same kernels and
+ * arguments; for checking the graphs against eager launches); eager = 0
+ * (the default) replays graphs. */
+mg_status mg_set_eager(mg_handle h, int eager);
 
 /* ---------------------------------------------------------------------------
  * Solve server (an extension; the paper has no serving layer).

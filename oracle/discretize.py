@@ -156,9 +156,11 @@ def row_dominance(beta):
 class Level:
     """Cut cells, classification and the assembled system of one grid."""
 
-    def __init__(self, grid, curves, a, b, c, eps, omega=0.5, progress=None):
-        """progress: optional callable(str) told when each stage is done."""
+    def __init__(self, grid, curves, a, b, c, eps, omega=0.5, progress=None, w_min=W_MIN):
+        """progress: optional callable(str) told when each stage is done;
+        w_min: the smallest weight of eq. (4.17) and the boundary weight."""
         self.grid = grid
+        self.w_min = float(w_min)
         self.a, self.b, self.c = float(a), float(b), float(c)
         self.h, self.nx, self.ny = grid.h, grid.nx, grid.ny
         self.curves = curves
@@ -393,12 +395,12 @@ class Level:
         M = np.empty((NBASIS, len(lat)))
         for k, d in enumerate(lat):
             M[:, k] = self._avg_monomials((i + d[0], j + d[1]), d)
-        wk = np.array([max(math.hypot(d[0], d[1]), W_MIN) for d in lat])
+        wk = np.array([max(math.hypot(d[0], d[1]), self.w_min) for d in lat])
         phibar = self._lphi(i, j)
         if self.cg.regular[j, i]:
             return np.linalg.solve(M, phibar), None
         M = np.hstack([M, self.boundary_average_of_basis(i, j)[:, None]])
-        wk = np.append(wk, W_MIN)
+        wk = np.append(wk, self.w_min)
         sq = 1.0 / np.sqrt(wk)                  # W^{1/2}, W = diag(1/w_k)
         gamma = np.linalg.lstsq(M * sq[None, :], phibar, rcond=None)[0]
         beta = sq * gamma

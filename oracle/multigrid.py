@@ -43,10 +43,12 @@ class _Grid:
 
 class Hierarchy:
     def __init__(self, grid, curves, a, b, c, eps, n_levels=0, omega=0.5, nu=(3, 3), min_cells=16,
-                 progress=None):
+                 progress=None, w_min=0.5, colouring=False, block=(64, 16)):
         self.omega = float(omega)
+        self.colouring = bool(colouring)
+        self.block = block
         self.nu1, self.nu2 = nu
-        self.levels = [Level(grid, curves, a, b, c, eps, progress=progress)]
+        self.levels = [Level(grid, curves, a, b, c, eps, progress=progress, w_min=w_min)]
         while n_levels == 0 or len(self.levels) < n_levels:
             g = self.levels[-1].grid
             if g.nx % 2 or g.ny % 2 or g.nx // 2 < min_cells or g.ny // 2 < min_cells:
@@ -55,7 +57,7 @@ class Hierarchy:
                 break
             cg = _Grid(g.x0, g.y0, 2 * g.h, g.nx // 2, g.ny // 2)
             try:
-                self.levels.append(Level(cg, curves, a, b, c, eps, progress=progress))
+                self.levels.append(Level(cg, curves, a, b, c, eps, progress=progress, w_min=w_min))
             except GeometryError:
                 if n_levels:
                     raise
@@ -89,14 +91,54 @@ class Hierarchy:
             # diagonal after ghost elimination does not.
             d11 = np.full(A11.shape[0], -2.5 * (L.a + L.c) / (L.h * L.h))
             lu22 = spla.splu(A22.tocsc()) if A22.shape[0] else None
-            self.sm.append((A11, A12, A21, A22, d11, lu22, ~L.is_plg, L.is_plg))
+            # colours of the SFV cells for the multicolour variant: (i + j)
+            # mod 3 for the plus-shaped stencil (b = 0), (i + 3 j) mod 9 for
+            # the 5 x 5 box (b != 0); no two cells of one colour are within
+            # each other's stencil
+            s_cells = ~L.is_plg
+            ci, cj = L.cells_i[s_cells], L.cells_j[s_cells]
+            colour = (ci + cj) % 3 if L.b == 0.0 else (ci + 3 * cj) % 9
+            a_in = self._block_part(L, ci, cj) if self.colouring else None
+            self.sm.append((A11, A12, A21, A22, d11, lu22, s_cells, L.is_plg, colour, a_in))
+
+    def _block_part(self, L, ci, cj):
+        """The part of A11 that the multicolour variant takes from the current
+        values: the stencil weights of eq. (4.7) (and the mixed term) between
+        SFV cells of the same block of self.block cells; everything else
+        (other blocks, ghost values) comes from the sweep's starting values."""
+        from .stencil import operator_terms
+        bx, by = self.block
+        pos = -np.ones((L.ny, L.nx), dtype=np.int64)
+        pos[cj, ci] = np.arange(len(ci))
+        rows, cols, vals = [], [], []
+        for (m1, m2), w in operator_terms(L.a, L.b, L.c, L.h):
+            ni, nj = ci + m1, cj + m2
+            ok = (ni >= 0) & (ni < L.nx) & (nj >= 0) & (nj < L.ny)
+            ok &= (ni // bx == ci // bx) & (nj // by == cj // by)
+            k = np.nonzero(ok)[0]
+            tgt = pos[nj[k], ni[k]]
+            keep = tgt >= 0
+            rows.append(k[keep]); cols.append(tgt[keep]); vals.append(np.full(int(keep.sum()), w))
+        n = len(ci)
+        return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
 
     # -- Definition 5.6 ---------------------------------------------------------
     def smooth(self, l, u, b):
-        A11, A12, A21, A22, d11, lu22, s, p = self.sm[l]
+        A11, A12, A21, A22, d11, lu22, s, p, colour, a_in = self.sm[l]
         u = u.copy()
         u1, u2 = u[s], u[p]
-        u1 = u1 + self.omega * (b[s] - A11 @ u1 - A12 @ u2) / d11        # eq. (5.5)
+        if self.colouring:
+            # multicolour variant (an extension): the update of eq. (5.5)
+            # applied colour by colour; within a block each colour sees the
+            # values the previous colours left, across blocks and through
+            # ghost cells the values at the start of the sweep
+            r_rest = b[s] - (A11 - a_in) @ u1 - A12 @ u2
+            for k in range(int(colour.max()) + 1 if len(colour) else 0):
+                sel = colour == k
+                r = r_rest - a_in @ u1
+                u1[sel] = u1[sel] + self.omega * r[sel] / d11[sel]
+        else:
+            u1 = u1 + self.omega * (b[s] - A11 @ u1 - A12 @ u2) / d11    # eq. (5.5)
         if lu22 is not None:
             u2 = lu22.solve(b[p] - A21 @ u1)                                # eq. (5.6)
         u[s], u[p] = u1, u2

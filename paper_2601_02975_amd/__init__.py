@@ -47,14 +47,27 @@ class mg_grid(ctypes.Structure):
 class mg_options(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("omega", ctypes.c_double), ("nu1", ctypes.c_int),
                 ("nu2", ctypes.c_int), ("n_levels", ctypes.c_int), ("min_coarse", ctypes.c_int),
-                ("precision", ctypes.c_int), ("max_iters", ctypes.c_int), ("cycle", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("max_iters", ctypes.c_int), ("cycle", ctypes.c_int),
+                ("degree", ctypes.c_int), ("w_min", ctypes.c_double), ("colouring", ctypes.c_int),
+                ("split_cells", ctypes.c_longlong), ("small_cells", ctypes.c_longlong),
+                ("split_b_sep", ctypes.c_int)]
 
 
 class mg_info(ctypes.Structure):
     _fields_ = [("n_levels", ctypes.c_int), ("nx", ctypes.c_int * 16), ("ny", ctypes.c_int * 16),
                 ("n_active", ctypes.c_int * 16), ("n_plg", ctypes.c_int * 16), ("n_sep", ctypes.c_int * 16),
-                ("sweep_words", ctypes.c_longlong * 16), ("n_face", ctypes.c_int), ("n_irr", ctypes.c_int), ("nnz_plg", ctypes.c_longlong),
-                ("device_bytes", ctypes.c_longlong), ("setup_seconds", ctypes.c_double)]
+                ("sweep_words", ctypes.c_longlong * 16), ("n_sfv", ctypes.c_longlong * 16),
+                ("n_face", ctypes.c_int), ("n_irr", ctypes.c_int), ("nnz_plg", ctypes.c_longlong),
+                ("device_bytes", ctypes.c_longlong), ("setup_seconds", ctypes.c_double),
+                ("cond_A22", ctypes.c_double * 16), ("setup_stage_seconds", ctypes.c_double * 6)]
+
+
+F_BATCH = ctypes.CFUNCTYPE(None, ctypes.c_longlong, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                           ctypes.POINTER(ctypes.c_double), ctypes.c_void_p)
+G_BATCH = ctypes.CFUNCTYPE(None, ctypes.c_longlong, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                           ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
+                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), ctypes.c_void_p)
+SMOOTH_JACOBI, SMOOTH_MULTICOLOUR = 0, 1
 
 
 class mg_server_options(ctypes.Structure):
@@ -91,13 +104,18 @@ def load_library():
         "mg_rhs": [P, P, P, P, P],
         "mg_vcycle": [P, P, P, P],
         "mg_smooth": [P, I, P, P, P],
+        "mg_smooth32": [P, I, P, P, P],
+        "mg_restrict": [P, I, I, P, P, P, P],
+        "mg_prolong": [P, I, I, P, P, P],
         "mg_residual": [P, I, P, P, P, pD, P],
         "mg_query": [P, ctypes.POINTER(mg_info)],
         "mg_export_level": [P, I, pI, pI, pLL, pI, pI, pD, pD],
         "mg_cell_quadrature": [P, pI, pLL, pI, pLL, pD, pD, pD],
         "mg_boundary_quadrature": [P, pI, pLL, pLL, pD, pD, pD, pD, pD, pI, pD, pD],
         "mg_destroy": [P],
+        "mg_project_rhs": [P, F_BATCH, G_BATCH, P, I, P, P, P],
         "mg_kernel_timing": [P, I, pI, pD],
+        "mg_set_eager": [P, I],
         "mg_server_create": [ctypes.POINTER(mg_server_options), ctypes.POINTER(P)],
         "mg_server_add_problem": [P, ctypes.POINTER(mg_grid), I, ctypes.POINTER(mg_curve), D, D, D,
                                   ctypes.POINTER(mg_options), pI],
@@ -176,12 +194,17 @@ def _curves(curves):
     return carr, keep
 
 
-def _options(eps, omega, nu, n_levels, min_coarse, precision, max_iters, cycle=0):
+def _options(eps, omega, nu, n_levels, min_coarse, precision, max_iters, cycle=0, **extra):
+    """mg_options from the library's defaults; extra: degree, w_min,
+    colouring, split_cells, small_cells, split_b_sep."""
     opt = mg_options()
     lib().mg_default_options(ctypes.byref(opt))
     opt.eps, opt.omega, opt.nu1, opt.nu2 = eps, omega, nu[0], nu[1]
     opt.n_levels, opt.min_coarse, opt.precision, opt.max_iters = n_levels, min_coarse, precision, max_iters
     opt.cycle = cycle
+    for k, v in extra.items():
+        if v is not None:
+            setattr(opt, k, v)
     return opt
 
 
@@ -189,12 +212,13 @@ class Solver:
     """A handle of the C library for one problem (grid, curves, a, b, c)."""
 
     def __init__(self, grid, curves, a, b, c, eps=0.08, omega=0.5, nu=(3, 3), n_levels=0, min_coarse=16,
-                 precision=FP64, max_iters=100, cycle=0):
+                 precision=FP64, max_iters=100, cycle=0, **extra):
         L = lib()
         carr, self._segs = _curves(curves)
         g = mg_grid(grid.x0, grid.y0, grid.h, grid.nx, grid.ny)
-        opt = _options(eps, omega, nu, n_levels, min_coarse, precision, max_iters, cycle)
+        opt = _options(eps, omega, nu, n_levels, min_coarse, precision, max_iters, cycle, **extra)
         self.grid = grid
+        self.curves = curves
         self.nx, self.ny = grid.nx, grid.ny
         h = ctypes.c_void_p()
         _check(L.mg_setup(ctypes.byref(g), len(curves), carr, a, b, c, ctypes.byref(opt), _stream(),
@@ -239,6 +263,21 @@ class Solver:
     def smooth(self, level, b, u):
         _check(lib().mg_smooth(self.h, level, _ptr(b), _ptr(u), _stream()), "mg_smooth")
 
+    def smooth32(self, level, b, u):
+        _check(lib().mg_smooth32(self.h, level, _ptr(b), _ptr(u), _stream()), "mg_smooth32")
+
+    def restrict(self, level, b, u, bc):
+        """bc (level + 1) = R (b - A u) (level); FP64 or FP32 tensors."""
+        import torch
+        prec = FP64 if b.dtype == torch.float64 else MIXED
+        _check(lib().mg_restrict(self.h, level, prec, _ptr(b), _ptr(u), _ptr(bc), _stream()), "mg_restrict")
+
+    def prolong(self, level, ec, u):
+        """u (level) += P ec (level + 1); FP64 or FP32 tensors."""
+        import torch
+        prec = FP64 if u.dtype == torch.float64 else MIXED
+        _check(lib().mg_prolong(self.h, level, prec, _ptr(ec), _ptr(u), _stream()), "mg_prolong")
+
     def residual(self, level, b, u, r=None):
         nrm = ctypes.c_double()
         _check(lib().mg_residual(self.h, level, _ptr(b), _ptr(u), _ptr(r), ctypes.byref(nrm), _stream()),
@@ -253,7 +292,8 @@ class Solver:
                 "n_plg": list(inf.n_plg[:n]), "n_sep": list(inf.n_sep[:n]),
                 "sweep_words": list(inf.sweep_words[:n]), "n_face": inf.n_face,
                 "n_irr": inf.n_irr, "nnz_plg": inf.nnz_plg, "device_bytes": inf.device_bytes,
-                "setup_seconds": inf.setup_seconds}
+                "setup_seconds": inf.setup_seconds, "n_sfv": list(inf.n_sfv[:n]),
+                "cond_A22": list(inf.cond_A22[:n]), "setup_stage_seconds": list(inf.setup_stage_seconds)}
 
     def export_level(self, level):
         nx, ny = self.info["nx"][level], self.info["ny"][level]
@@ -296,6 +336,9 @@ class Solver:
         k = nn.value
         return ptr, x[:k], y[:k], w[:k], nxv[:k], nyv[:k], bc[:k], a1[:k], a2[:k]
 
+    def set_eager(self, eager):
+        _check(lib().mg_set_eager(self.h, 1 if eager else 0), "mg_set_eager")
+
     def kernel_timing(self, enable):
         n = ctypes.c_int()
         avg = ctypes.c_double()
@@ -304,35 +347,53 @@ class Solver:
         return n.value, avg.value
 
     # -- inputs ------------------------------------------------------------------
-    def project(self, sol):
-        """Host arrays (f, g) of cell averages of sol.f and boundary averages of
-        N sol.u in the library's layout, from its quadrature rules (regular
-        cells: tensor Gauss-Legendre)."""
-        g0 = self.grid
-        nx, ny, h = g0.nx, g0.ny, g0.h
-        f = np.zeros((ny + 4, nx + 4))
-        npts = 8 if max(nx, ny) <= 1024 else 4
-        s, w = np.polynomial.legendre.leggauss(npts)
-        kind, _, _, _, _ = self.export_level(0)
-        xs = g0.x0 + (np.arange(nx)[:, None] + 0.5 + 0.5 * s[None, :]) * h          # nx x npts
-        chunk = max(1, (1 << 22) // (nx * npts * npts))
-        for j0 in range(0, ny, chunk):
-            j1 = min(ny, j0 + chunk)
-            ys = g0.y0 + (np.arange(j0, j1)[:, None] + 0.5 + 0.5 * s[None, :]) * h  # rows x npts
-            vals = sol.f(xs[None, :, :, None], ys[:, None, None, :])                # rows x nx x a x b
-            f[j0 + 2:j1 + 2, 2:nx + 2] = 0.25 * np.einsum("a,b,rnab->rn", w, w, vals)
-        cell, ptr, qx, qy, qw = self.cell_quadrature()
-        if len(cell):
-            v = sol.f(qx, qy) * qw
-            avg = np.add.reduceat(v, ptr[:-1]) if len(v) else np.zeros(0)
-            f[cell // nx + 2, cell % nx + 2] = avg
-        f[2:ny + 2, 2:nx + 2][kind == 0] = 0.0
-        ptr, bx, by, bw, bnx, bny, bc, a1, a2 = self.boundary_quadrature()
-        u = sol.u(bx, by)
-        dn = sol.ux(bx, by) * bnx + sol.uy(bx, by) * bny
-        val = np.where(bc == 0, u, np.where(bc == 1, dn, a1 * u + a2 * dn))
-        g = np.add.reduceat(val * bw, ptr[:-1])
-        return f, g
+    def project_rhs(self, f, g, gauss_points=8):
+        """Device tensors (f_dev, g_dev) from mg_project_rhs.  f(x, y) and
+        g(x, y, curve, seg, nx, ny) evaluate NumPy arrays of points (g returns
+        the boundary datum N u); the library chooses the points and forms the
+        averages."""
+        import torch
+
+        def fcb(n, x, y, out, ctx):
+            xv = np.ctypeslib.as_array(x, (n,))
+            yv = np.ctypeslib.as_array(y, (n,))
+            np.ctypeslib.as_array(out, (n,))[:] = f(xv, yv)
+
+        def gcb(n, x, y, curve, seg, nx, ny, out, ctx):
+            arr = lambda p, t=np.float64: np.ctypeslib.as_array(p, (n,))
+            np.ctypeslib.as_array(out, (n,))[:] = g(arr(x), arr(y), arr(curve), arr(seg), arr(nx), arr(ny))
+
+        fd = self.empty()
+        gd = torch.zeros(max(self.info["n_face"] + self.info["n_irr"], 1), dtype=torch.float64, device="cuda")
+        fc, gc = F_BATCH(fcb), G_BATCH(gcb)
+        _check(lib().mg_project_rhs(self.h, fc, gc, None, int(gauss_points), _ptr(fd), _ptr(gd), _stream()),
+               "mg_project_rhs")
+        return fd, gd
+
+    def project(self, sol, gauss_points=8):
+        """Device tensors (f, g) for a manufactured solution sol (sol.f, sol.u
+        and its gradient): the boundary datum of each segment is its boundary
+        condition applied to sol.u."""
+        kinds = [[(BC[sg.bc], float(sg.alpha1), float(sg.alpha2)) for sg in cv] for cv in self.curves]
+        tab = {}
+        for ci, cv in enumerate(kinds):
+            for si, k in enumerate(cv):
+                tab[(ci, si)] = k
+
+        def g(x, y, curve, seg, nx, ny):
+            key = curve.astype(np.int64) * 4096 + seg.astype(np.int64)
+            bc = np.empty(len(x), np.int32)
+            a1 = np.empty(len(x))
+            a2 = np.empty(len(x))
+            for kk in np.unique(key):
+                sel = key == kk
+                b0, b1, b2 = tab[(int(kk) // 4096, int(kk) % 4096)]
+                bc[sel], a1[sel], a2[sel] = b0, b1, b2
+            u = sol.u(x, y)
+            dn = sol.ux(x, y) * nx + sol.uy(x, y) * ny
+            return np.where(bc == 0, u, np.where(bc == 1, dn, a1 * u + a2 * dn))
+
+        return self.project_rhs(sol.f, g, gauss_points)
 
 
 def to_padded(grid_vals, nx, ny):

@@ -1,8 +1,6 @@
 // C ABI of the cut-cell multigrid library: setup orchestration, device data,
 // the V-cycle driver (Algorithm 3) and the outer iteration.
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
-#include <rocsolver/rocsolver.h>
 
 #include <algorithm>
 #include <chrono>
@@ -36,7 +34,7 @@ std::mutex g_capture_mu;
 constexpr int SEG_MAX = 256;       // longest PLG segment (dense inverse per segment)
 constexpr int SEG_WHOLE = 768;     // a level whose hole chains fit in segments this long needs no separators
 constexpr int ITER_CHUNK = 8;      // most outer iterations per launch (chunks of 1, 2, 4, 8)
-constexpr int BOTTOM_MAX = 8192;   // largest dense bottom inverse (right-hand side staged in 64 KiB of LDS)
+constexpr int BOTTOM_MAX = 4096;   // largest dense bottom inverse (128 MiB; right-hand side staged in 32 KiB of LDS)
 
 struct DevLevel {
     LevelArgs args{};
@@ -63,6 +61,7 @@ struct DevLevel {
     double *ainv = nullptr;
     int cur = 0;
     long long sweep_words = 0;    // words moved by one smoother launch A (algorithmic)
+    long long nsfv = 0;
     // finest level, FP64 FMG: residual equation right-hand side and its iterate
     double *r64 = nullptr, *e64[2] = {nullptr, nullptr};
 };
@@ -92,10 +91,19 @@ struct mg_handle_s {
     hipGraphExec_t iter_exec[3][4] = {};
     hipGraph_t iter_graph[3][4] = {};
     int upar = 0;                 // mixed precision: which FP64 buffer holds the iterate
-    // timing of the finest-level SFV sweep
+    // timing of the finest-level SFV tile kernel: in timing mode the outer
+    // iterations are launched eagerly with an event pair around each such
+    // launch, read after each synchronisation
     bool timing = false;
-    std::vector<hipEvent_t> ev;
+    std::vector<hipEvent_t> ev;          // pool, 2 per recorded launch of one graph
+    int ev_next = 0;                     // next free pair while capturing
+    int tim_last = 0;                    // pairs recorded by the last replay, not yet read
+    bool tim_capture = false;
+    bool eager = false;                  // mg_set_eager: launch instead of replaying graphs
     int nrec = 0;
+    double tim_total_ms = 0.0;
+    std::vector<double> cond_a22;
+    double stage[6] = {0, 0, 0, 0, 0, 0};
 
     template <typename T>
     T *alloc(size_t n) {
@@ -124,7 +132,8 @@ namespace {
 
 size_t padded_index(int nx, int cell) { return (size_t)(cell / nx + 2) * (nx + 4) + (cell % nx + 2); }
 
-LevelArgs make_args(const Level &L, double omega) {
+LevelArgs make_args(const Level &L, const mg_options &o) {
+    const double omega = o.omega;
     LevelArgs a{};
     a.nx = L.g.nx;
     a.ny = L.g.ny;
@@ -136,6 +145,11 @@ LevelArgs make_args(const Level &L, double omega) {
     a.cyy = L.c / h2;
     a.omega_over_d = omega / (-2.5 * (L.a + L.c) / h2);
     a.mixed = L.b != 0.0;
+    const long long cells = (long long)L.g.nx * L.g.ny;
+    a.split_a = cells >= (o.split_cells > 0 ? o.split_cells : 2048LL * 2048) ? 1 : 0;
+    a.small32 = o.small_cells < 0 ? 0 : cells <= (o.small_cells > 0 ? o.small_cells : 512LL * 512) ? 1 : 0;
+    a.small64 = o.small_cells < 0 ? 0 : cells <= (o.small_cells > 0 ? o.small_cells : 256LL * 256) ? 1 : 0;
+    a.colouring = o.colouring == MG_SMOOTH_MULTICOLOUR ? 1 : 0;
     return a;
 }
 
@@ -143,13 +157,22 @@ LevelArgs make_args(const Level &L, double omega) {
 void fit_level(mg_handle h, Level &L, hipStream_t st) {
     std::vector<double> M, phi, w;
     std::vector<int> ncol;
+    auto t0 = std::chrono::steady_clock::now();
     L.fit_inputs(M, phi, w, ncol);
+    auto t1 = std::chrono::steady_clock::now();
+    h->stage[1] += std::chrono::duration<double>(t1 - t0).count();
+    struct StageClock {
+        double &acc;
+        std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+        ~StageClock() { acc += std::chrono::duration<double>(std::chrono::steady_clock::now() - t).count(); }
+    } fit_clock{h->stage[2]};
     const int m = (int)L.plg_cells.size();
     L.row_ptr.assign(m + 1, 0);
     L.col.clear();
     L.val.clear();
     L.beta_b.assign(m, 0.0);
     if (m == 0) return;
+    std::lock_guard<std::mutex> lk(g_capture_mu);
     double *dM, *dphi, *dw, *dwork, *dbeta;
     int *dncol, *dstat;
     HIPCHECK(hipMalloc(&dM, M.size() * 8));
@@ -185,35 +208,52 @@ void fit_level(mg_handle h, Level &L, hipStream_t st) {
     }
 }
 
-// dense inverse of a row-major n x n matrix on the GPU (rocSOLVER)
+// dense inverse of a row-major n x n matrix on the GPU: Gauss-Jordan with
+// partial pivoting (launch_gj_step), FP64; a pivot column whose largest
+// entry is below 1e-13 of the matrix's largest entry is reported singular
 std::vector<double> gpu_inverse(int n, const std::vector<double> &A, hipStream_t st) {
-    rocblas_handle rb;
-    if (rocblas_create_handle(&rb) != rocblas_status_success) fail(MG_ERR_HIP, "rocblas_create_handle failed");
-    rocblas_set_stream(rb, st);
-    double *dA;
-    rocblas_int *ipiv, *info;
-    HIPCHECK(hipMalloc(&dA, (size_t)n * n * 8));
-    HIPCHECK(hipMalloc(&ipiv, (size_t)n * sizeof(rocblas_int)));
-    HIPCHECK(hipMalloc(&info, sizeof(rocblas_int)));
-    HIPCHECK(hipMemcpy(dA, A.data(), (size_t)n * n * 8, hipMemcpyHostToDevice));
-    // a row-major matrix is its transpose in column-major storage; the inverse
-    // of the transpose is the transpose of the inverse, so the result read
-    // back row-major is A^{-1}
-    rocsolver_dgetrf(rb, n, n, dA, n, ipiv, info);
-    HIPCHECK(hipStreamSynchronize(st));
-    rocblas_int hinfo = 0;
-    HIPCHECK(hipMemcpy(&hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost));
-    if (hinfo != 0) {
-        (void)hipFree(dA); (void)hipFree(ipiv); (void)hipFree(info);
-        rocblas_destroy_handle(rb);
-        fail(MG_ERR_SINGULAR, "the bottom-level matrix is singular");
+    const size_t ld = 2 * (size_t)n;
+    std::vector<double> W((size_t)n * ld, 0.0);
+    double amax = 0.0;
+    for (int i = 0; i < n; ++i) {
+        for (int j = 0; j < n; ++j) {
+            const double v = A[(size_t)i * n + j];
+            if (!std::isfinite(v)) fail(MG_ERR_SINGULAR, "the bottom-level matrix has a non-finite entry");
+            W[(size_t)i * ld + j] = v;
+            amax = std::max(amax, std::fabs(v));
+        }
+        W[(size_t)i * ld + n + i] = 1.0;
     }
-    rocsolver_dgetri(rb, n, dA, n, ipiv, info);
+    if (!(amax > 0.0)) fail(MG_ERR_SINGULAR, "the bottom-level matrix is zero");
+    double *dW = nullptr, *df = nullptr;
+    int *dstat = nullptr;
+    auto release = [&]() {
+        if (dW) (void)hipFree(dW);
+        if (df) (void)hipFree(df);
+        if (dstat) (void)hipFree(dstat);
+    };
+    try {
+        HIPCHECK(hipMalloc(&dW, W.size() * 8));
+        HIPCHECK(hipMalloc(&df, (size_t)n * 8));
+        HIPCHECK(hipMalloc(&dstat, sizeof(int)));
+        HIPCHECK(hipMemcpy(dW, W.data(), W.size() * 8, hipMemcpyHostToDevice));
+        HIPCHECK(hipMemset(dstat, 0, sizeof(int)));
+        for (int k = 0; k < n; ++k) launch_gj_step(n, k, dW, df, dstat, 1e-13 * amax, st);
+        HIPCHECK(hipGetLastError());
+        HIPCHECK(hipStreamSynchronize(st));
+        int stat = 0;
+        HIPCHECK(hipMemcpy(&stat, dstat, sizeof(int), hipMemcpyDeviceToHost));
+        if (stat != 0) fail(MG_ERR_SINGULAR, "the bottom-level matrix is singular (pivot column " +
+                                                 std::to_string(stat - 1) + ")");
+        HIPCHECK(hipMemcpy(W.data(), dW, W.size() * 8, hipMemcpyDeviceToHost));
+    } catch (...) {
+        release();
+        throw;
+    }
+    release();
     std::vector<double> out((size_t)n * n);
-    HIPCHECK(hipStreamSynchronize(st));
-    HIPCHECK(hipMemcpy(out.data(), dA, (size_t)n * n * 8, hipMemcpyDeviceToHost));
-    (void)hipFree(dA); (void)hipFree(ipiv); (void)hipFree(info);
-    rocblas_destroy_handle(rb);
+    for (int i = 0; i < n; ++i)
+        std::copy(W.begin() + (size_t)i * ld + n, W.begin() + (size_t)(i + 1) * ld, out.begin() + (size_t)i * n);
     return out;
 }
 
@@ -222,7 +262,7 @@ void upload_level(mg_handle h, int l, bool last, hipStream_t st) {
     const PlgSolver &S = h->solvers[l];
     DevLevel &D = h->dev[l];
     const int nx = L.g.nx, ny = L.g.ny;
-    D.args = make_args(L, h->opt.omega);
+    D.args = make_args(L, h->opt);
     // ghost weights of the four box sides on this level (h-dependent for Robin)
     std::vector<double> gw(32);
     for (int side = 0; side < 4; ++side)
@@ -290,7 +330,9 @@ void upload_level(mg_handle h, int l, bool last, hipStream_t st) {
     D.rplg64 = h->alloc<double>(S.m);
     D.rplg32 = h->alloc<float>(S.m);
     PlgPlan G;
+    auto p0 = std::chrono::steady_clock::now();
     build_plg_plan(L, S, nx, PLG_SLICE, PLG_B_ROWS, PLG_LMAX, PLG_SEP_ROWS, G);
+    h->stage[3] += std::chrono::duration<double>(std::chrono::steady_clock::now() - p0).count();
     if (G.hmax > PLG_HMAX || G.lmax > PLG_LMAX || G.kmax > PLG_KMAX || S.nsep > PLG_SMAX)
         fail(MG_ERR_UNSUPPORTED, "PLG block partition exceeds the LDS staging limits");
     int *grp_start = h->upload(G.grp_start), *hptr = h->upload(G.hptr), *hcell = h->upload(G.hcell);
@@ -316,6 +358,7 @@ void upload_level(mg_handle h, int l, bool last, hipStream_t st) {
         P.nblk2 = (int)G.blk2.size(); P.blk2 = blk2;
         P.ft_off = ft_off; P.FT = FT; P.fcols_ptr = fcols_ptr; P.sj_off = sj_off; P.SJ = SJ; P.sinv = sinv;
         P.fcols = fcols; P.nblk2_seg = nblk2_seg;
+        P.split_b = S.nsep >= (h->opt.split_b_sep > 0 ? h->opt.split_b_sep : 768) ? 1 : 0;
         P.t = t; P.y = y; P.contrib = contrib;
     };
     const size_t nslot = (size_t)S.nsep * ELL_W;
@@ -330,6 +373,7 @@ void upload_level(mg_handle h, int l, bool last, hipStream_t st) {
     long long nsfv = 0;
     for (int cl = 0; cl < nx * ny; ++cl) nsfv += L.kind[cl] == 1;
     D.sweep_words = 3 * nsfv + (long long)S.inv.size() + 2LL * S.m;
+    D.nsfv = nsfv;
     // transfers to the next level
     if (!last) {
         const Level &C = *h->levels[l + 1];
@@ -401,7 +445,9 @@ void upload_level(mg_handle h, int l, bool last, hipStream_t st) {
                 for (int e = L.row_ptr[pr]; e < L.row_ptr[pr + 1]; ++e) A[(size_t)r * n + pos[L.col[e]]] += L.val[e];
             }
         }
+        auto b0 = std::chrono::steady_clock::now();
         std::vector<double> inv = gpu_inverse(n, A, st);
+        h->stage[4] += std::chrono::duration<double>(std::chrono::steady_clock::now() - b0).count();
         std::vector<int> bc(n);
         for (int r = 0; r < n; ++r) bc[r] = (int)padded_index(nx, act[r]);
         D.nbot = n;
@@ -467,13 +513,11 @@ template <typename T>
 void smooth(mg_handle h, int l, bool uzero, hipStream_t st) {
     DevLevel &D = h->dev[l];
     T *uo = Prec<T>::u(D, D.cur), *un = Prec<T>::u(D, 1 - D.cur);
-    const bool rec = h->timing && l == 0 && 2 * h->nrec + 1 < (int)h->ev.size();
-    if (rec) HIPCHECK(hipEventRecord(h->ev[2 * h->nrec], st));
-    launch_smooth_a<T>(D.args, uo, Prec<T>::b(D), un, D.mask, uzero, Prec<T>::P(D), st);
-    if (rec) {
-        HIPCHECK(hipEventRecord(h->ev[2 * h->nrec + 1], st));
-        ++h->nrec;
-    }
+    // in timing mode: events around the finest level's tile kernel
+    const bool rec = h->tim_capture && l == 0 && 2 * h->ev_next + 1 < (int)h->ev.size();
+    hipEvent_t e0 = rec ? h->ev[2 * h->ev_next] : nullptr, e1 = rec ? h->ev[2 * h->ev_next + 1] : nullptr;
+    if (rec) ++h->ev_next;
+    launch_smooth_a<T>(D.args, uo, Prec<T>::b(D), un, D.mask, uzero, Prec<T>::P(D), st, e0, e1);
     launch_smooth_b<T>(Prec<T>::P(D), un, st);
     D.cur = 1 - D.cur;
 }
@@ -606,20 +650,40 @@ void run_iterations(mg_handle h, int k, hipStream_t st) {
     auto enqueue = [&](hipStream_t s) {
         for (int i = 0; i < k; ++i) enqueue_iteration(h, corr ? (par + i) & 1 : 0, i, s);
     };
-    if (h->timing) {                     // eager launches (events around the sweeps)
+    if (h->eager || h->timing) {
+        // kernel timing: eager launches with an event pair around each
+        // finest-level tile kernel (HIP events recorded inside graphs cannot
+        // be timed)
+        h->ev_next = 0;
+        h->tim_capture = h->timing;
         enqueue(st);
-    } else {
-        if (!h->iter_exec[p][c]) {
-            std::lock_guard<std::mutex> lk(g_capture_mu);
-            if (!h->cap_stream) HIPCHECK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
-            HIPCHECK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-            enqueue(h->cap_stream);
-            HIPCHECK(hipStreamEndCapture(h->cap_stream, &h->iter_graph[p][c]));
-            HIPCHECK(hipGraphInstantiate(&h->iter_exec[p][c], h->iter_graph[p][c], nullptr, nullptr, 0));
-        }
-        HIPCHECK(hipGraphLaunch(h->iter_exec[p][c], st));
+        h->tim_capture = false;
+        h->tim_last = h->timing ? h->ev_next : 0;
+        if (corr && (k & 1)) h->upar = 1 - h->upar;
+        return;
     }
+    if (!h->iter_exec[p][c]) {
+        std::lock_guard<std::mutex> lk(g_capture_mu);
+        if (!h->cap_stream) HIPCHECK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+        HIPCHECK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+        enqueue(h->cap_stream);
+        HIPCHECK(hipStreamEndCapture(h->cap_stream, &h->iter_graph[p][c]));
+        HIPCHECK(hipGraphInstantiate(&h->iter_exec[p][c], h->iter_graph[p][c], nullptr, nullptr, 0));
+    }
+    HIPCHECK(hipGraphLaunch(h->iter_exec[p][c], st));
     if (corr && (k & 1)) h->upar = 1 - h->upar;
+}
+
+// after the stream has been synchronised: add the durations recorded by the
+// last timing replay
+void collect_timing(mg_handle h) {
+    for (int q = 0; q < h->tim_last; ++q) {
+        float ms = 0.f;
+        HIPCHECK(hipEventElapsedTime(&ms, h->ev[2 * q], h->ev[2 * q + 1]));
+        h->tim_total_ms += ms;
+        ++h->nrec;
+    }
+    h->tim_last = 0;
 }
 
 thread_local std::string g_last_error;
@@ -642,6 +706,124 @@ mg_status guard(mg_handle h, const std::function<void()> &fn) {
     }
 }
 
+// Nodes and weights (divided by the cell volume) of the cut-cell quadrature:
+// cell(c0, first) is called before the nodes of each active irregular cell,
+// node(x, y, w) for every node.
+template <typename CellFn, typename NodeFn>
+void cut_cell_nodes(mg_handle h, CellFn cell, NodeFn node) {
+    const Level &L = *h->levels[0];
+    const CutGrid &cg = L.cg;
+    std::vector<double> g16x, g16w, g8x, g8w;
+    gauss_legendre(16, g16x, g16w);
+    gauss_legendre(8, g8x, g8w);
+    const double hh = L.g.h;
+    for (size_t s = 0; s < cg.irr_cells.size(); ++s) {
+        const int c0 = cg.irr_cells[s];
+        const CellData &d = cg.irr[s];
+        if (!cg.active[c0]) continue;
+        const double vol = d.mom[0] * hh * hh;
+        cell(c0, true);
+        auto emit = [&](double px, double py, double pw) { node(px, py, pw / vol); };
+        for (int ci : d.members) {
+            const Comp &c = cg.comps[ci];
+            const double X0 = L.g.x0 + c.ci * hh, Y0 = L.g.y0 + c.cj * hh, xr = X0 + 0.5 * hh;
+            if (c.full) {
+                for (int a = 0; a < 8; ++a)
+                    for (int b = 0; b < 8; ++b)
+                        emit(X0 + (0.5 + 0.5 * g8x[a]) * hh, Y0 + (0.5 + 0.5 * g8x[b]) * hh, 0.25 * hh * hh * g8w[a] * g8w[b]);
+                continue;
+            }
+            for (const LoopItem &it : c.items) {
+                if (!it.is_edge) {
+                    const Seg &sg = h->curves.c[it.piece.curve][it.piece.seg];
+                    for (int k = 0; k < 16; ++k) {
+                        double t = 0.5 * (it.piece.tb - it.piece.ta) * g16x[k] + 0.5 * (it.piece.ta + it.piece.tb);
+                        double px, py, dx, dy;
+                        sg.point(t, px, py);
+                        sg.deriv(t, dx, dy);
+                        double ow = 0.5 * (it.piece.tb - it.piece.ta) * g16w[k] * dy;
+                        double half = 0.5 * (px - xr);
+                        for (int q = 0; q < 16; ++q) emit(xr + half * (1.0 + g16x[q]), py, ow * g16w[q] * half);
+                    }
+                } else if (it.side == 1 || it.side == 3) {
+                    double px = it.side == 1 ? X0 + hh : X0;
+                    double ya = it.side == 1 ? Y0 + it.s0 * hh : Y0 + (1.0 - it.s0) * hh;
+                    double yb = it.side == 1 ? Y0 + it.s1 * hh : Y0 + (1.0 - it.s1) * hh;
+                    for (int k = 0; k < 8; ++k) {
+                        double py = 0.5 * (yb - ya) * g8x[k] + 0.5 * (ya + yb);
+                        double ow = 0.5 * (yb - ya) * g8w[k];
+                        double half = 0.5 * (px - xr);
+                        for (int q = 0; q < 16; ++q) emit(xr + half * (1.0 + g16x[q]), py, ow * g16w[q] * half);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Nodes of the boundary data in the layout of g: entry() before each entry
+// (box faces bottom, top, left, right, then irregular cells), node(x, y, w,
+// nx, ny, curve, seg) with weights summing to 1 per entry and the outward
+// unit normal.
+template <typename EntryFn, typename NodeFn>
+void boundary_nodes(mg_handle h, EntryFn entry, NodeFn node) {
+    const Level &L = *h->levels[0];
+    const CutGrid &cg = L.cg;
+    const int nx = L.g.nx, ny = L.g.ny;
+    const double hh = L.g.h;
+    std::vector<double> g16x, g16w, g8x, g8w;
+    gauss_legendre(16, g16x, g16w);
+    gauss_legendre(8, g8x, g8w);
+    const double x1 = L.g.x0 + nx * hh, y1 = L.g.y0 + ny * hh;
+    for (int side : {0, 2, 3, 1}) {
+        const int m = (side == 0 || side == 2) ? nx : ny;
+        for (int k = 0; k < m; ++k) {
+            entry();
+            for (int q = 0; q < 8; ++q) {
+                double s = L.g.x0 + (k + 0.5 + 0.5 * g8x[q]) * hh, tt = L.g.y0 + (k + 0.5 + 0.5 * g8x[q]) * hh;
+                if (side == 0) node(s, L.g.y0, 0.5 * g8w[q], 0.0, -1.0, 0, side);
+                else if (side == 2) node(s, y1, 0.5 * g8w[q], 0.0, 1.0, 0, side);
+                else if (side == 3) node(L.g.x0, tt, 0.5 * g8w[q], -1.0, 0.0, 0, side);
+                else node(x1, tt, 0.5 * g8w[q], 1.0, 0.0, 0, side);
+            }
+        }
+    }
+    for (int cl = 0; cl < nx * ny; ++cl) {
+        if (L.g_of_cell[cl] < 0) continue;
+        const CellData &d = cg.irr[cg.irr_slot[cl]];
+        entry();
+        double len = 0.0;
+        for (auto &bp : d.bp) {
+            const Seg &sg = h->curves.c[bp.curve][bp.seg];
+            for (int q = 0; q < 16; ++q) {
+                double t = 0.5 * (bp.tb - bp.ta) * g16x[q] + 0.5 * (bp.ta + bp.tb), dx, dy;
+                sg.deriv(t, dx, dy);
+                len += 0.5 * (bp.tb - bp.ta) * g16w[q] * std::hypot(dx, dy);
+            }
+        }
+        for (auto &bp : d.bp) {
+            const Seg &sg = h->curves.c[bp.curve][bp.seg];
+            for (int q = 0; q < 16; ++q) {
+                double t = 0.5 * (bp.tb - bp.ta) * g16x[q] + 0.5 * (bp.ta + bp.tb), px, py, dx, dy;
+                sg.point(t, px, py);
+                sg.deriv(t, dx, dy);
+                double sp = std::hypot(dx, dy);
+                node(px, py, 0.5 * (bp.tb - bp.ta) * g16w[q] * sp / len, dy / sp, -dx / sp, bp.curve, bp.seg);
+            }
+        }
+    }
+}
+
+// b_{l+1} = R (b - A u) on level l with every residual computed (also on PLG rows)
+template <typename T>
+void restrict_step(mg_handle h, int level, const T *b, const T *u, T *bc, hipStream_t st) {
+    DevLevel &D = h->dev[level], &C = h->dev[level + 1];
+    T *rplg = Prec<T>::rplg(D);
+    launch_plg_residual<T>(D.m, D.plg_cell, D.full_ptr, D.full_col, Prec<T>::fval(D), b, u, rplg, st);
+    launch_restrict<T>(D.args, C.args, u, b, D.mask, D.plgidx, rplg, D.rmask, bc, nullptr, D.ex_nt, D.ex_ptr,
+                       D.ex_target, D.ex_child, st);
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -658,6 +840,12 @@ mg_status mg_default_options(mg_options *opt) {
     opt->precision = MG_FP64;
     opt->max_iters = 100;
     opt->cycle = MG_CYCLE_V;
+    opt->degree = 4;
+    opt->w_min = 0.5;
+    opt->colouring = MG_SMOOTH_JACOBI;
+    opt->split_cells = 0;
+    opt->small_cells = 0;
+    opt->split_b_sep = 0;
     return MG_OK;
 }
 
@@ -674,8 +862,14 @@ mg_status mg_setup(const mg_grid *grid, int n_curves, const mg_curve *curves, do
     if (opt) o = *opt;
     if (!(o.eps > 0 && o.eps < 1) || o.nu1 < 0 || o.nu2 < 0 || o.max_iters < 1 || o.min_coarse < 4 ||
         (o.precision != MG_FP64 && o.precision != MG_MIXED) || o.n_levels < 0 || o.n_levels > 16 ||
-        (o.cycle != MG_CYCLE_V && o.cycle != MG_CYCLE_FMG))
+        (o.cycle != MG_CYCLE_V && o.cycle != MG_CYCLE_FMG) || !(o.omega > 0 && o.omega < 2) ||
+        !(o.w_min > 0 && o.w_min < 1e6) || (o.colouring != MG_SMOOTH_JACOBI && o.colouring != MG_SMOOTH_MULTICOLOUR) ||
+        o.split_cells < 0 || o.small_cells < -1 || o.split_b_sep < 0)
         return MG_ERR_INVALID_ARG;
+    if (o.degree != 4) {
+        g_last_error = "only degree-4 fits (lattices of 15 cells) are built";
+        return MG_ERR_UNSUPPORTED;
+    }
     for (int k = 0; k < n_curves; ++k) {
         if (curves[k].n_seg < 1 || !curves[k].seg) return MG_ERR_INVALID_ARG;
         for (int s = 0; s < curves[k].n_seg; ++s) {
@@ -688,7 +882,8 @@ mg_status mg_setup(const mg_grid *grid, int n_curves, const mg_curve *curves, do
     auto h = std::make_unique<mg_handle_s>();
     hipStream_t st = (hipStream_t)stream;
     mg_status rc = guard(h.get(), [&]() {
-        std::lock_guard<std::mutex> lk(g_capture_mu);
+        // the host-side geometry, lattice and solver work runs without the
+        // capture lock; device allocations, copies and the fits take it
         auto t0 = std::chrono::steady_clock::now();
         HIPCHECK(hipGetDevice(&h->device));
         h->opt = o;
@@ -713,9 +908,14 @@ mg_status mg_setup(const mg_grid *grid, int n_curves, const mg_curve *curves, do
             L->g = g;
             L->a = a; L->b = b; L->c = c;
             L->curves = &h->curves;
+            L->w_min = o.w_min;
             try {
+                auto c0 = std::chrono::steady_clock::now();
                 build_cutgrid(h->curves, g, o.eps, L->cg);
+                auto c1 = std::chrono::steady_clock::now();
+                h->stage[0] += std::chrono::duration<double>(c1 - c0).count();
                 L->classify();
+                h->stage[1] += std::chrono::duration<double>(std::chrono::steady_clock::now() - c1).count();
                 fit_level(h.get(), *L, st);
             } catch (const status_error &e) {
                 if (h->levels.empty() || e.code != MG_ERR_GEOMETRY || o.n_levels) throw;
@@ -733,13 +933,18 @@ mg_status mg_setup(const mg_grid *grid, int n_curves, const mg_curve *curves, do
             g.ny /= 2;
         }
         const int nl = (int)h->levels.size();
+        auto s0 = std::chrono::steady_clock::now();
         h->solvers.resize(nl);
+        h->cond_a22.assign(nl, 0.0);
         for (int l = 0; l < nl; ++l) {
             // whole chains as segments when that leaves no separators (one
             // smoother launch per sweep), else short segments
             build_plg_solver(*h->levels[l], SEG_WHOLE, h->solvers[l]);
             if (h->solvers[l].nsep > 0) build_plg_solver(*h->levels[l], SEG_MAX, h->solvers[l]);
+            h->cond_a22[l] = cond1_estimate(*h->levels[l], h->solvers[l]);
         }
+        h->stage[3] += std::chrono::duration<double>(std::chrono::steady_clock::now() - s0).count();
+        std::lock_guard<std::mutex> lk(g_capture_mu);
         h->dev.resize(nl);
         for (int l = 0; l < nl; ++l) upload_level(h.get(), l, l == nl - 1, st);
         upload_rhs(h.get());
@@ -759,6 +964,8 @@ mg_status mg_setup(const mg_grid *grid, int n_curves, const mg_curve *curves, do
         HIPCHECK(hipHostGetDevicePointer((void **)&h->host_scalar_dev, h->host_scalar, 0));
         HIPCHECK(hipStreamSynchronize(st));
         h->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        h->stage[5] = std::max(0.0, h->setup_seconds - (h->stage[0] + h->stage[1] + h->stage[2] + h->stage[3] +
+                                                        h->stage[4]));
     });
     if (rc != MG_OK) {
         mg_destroy(h.release());
@@ -808,6 +1015,50 @@ mg_status mg_smooth(mg_handle h, int level, const double *b_dev, double *u_dev, 
     });
 }
 
+mg_status mg_smooth32(mg_handle h, int level, const float *b_dev, float *u_dev, void *stream) {
+    if (!h || !b_dev || !u_dev || level < 0 || level >= (int)h->dev.size()) return MG_ERR_INVALID_ARG;
+    return guard(h, [&]() {
+        hipStream_t st = (hipStream_t)stream;
+        DevLevel &D = h->dev[level];
+        launch_smooth_a<float>(D.args, u_dev, b_dev, D.u32[1], D.mask, false, D.P32, st);
+        launch_smooth_b<float>(D.P32, D.u32[1], st);
+        HIPCHECK(hipMemcpyAsync(u_dev, D.u32[1], D.ncells * 4, hipMemcpyDeviceToDevice, st));
+        HIPCHECK(hipGetLastError());
+    });
+}
+
+mg_status mg_restrict(mg_handle h, int level, int precision, const void *b_dev, const void *u_dev, void *bc_dev,
+                      void *stream) {
+    if (!h || !b_dev || !u_dev || !bc_dev || level < 0 || level + 1 >= (int)h->dev.size() ||
+        (precision != MG_FP64 && precision != MG_MIXED))
+        return MG_ERR_INVALID_ARG;
+    return guard(h, [&]() {
+        hipStream_t st = (hipStream_t)stream;
+        if (precision == MG_FP64)
+            restrict_step<double>(h, level, (const double *)b_dev, (const double *)u_dev, (double *)bc_dev, st);
+        else
+            restrict_step<float>(h, level, (const float *)b_dev, (const float *)u_dev, (float *)bc_dev, st);
+        HIPCHECK(hipGetLastError());
+    });
+}
+
+mg_status mg_prolong(mg_handle h, int level, int precision, const void *ec_dev, void *u_dev, void *stream) {
+    if (!h || !ec_dev || !u_dev || level < 0 || level + 1 >= (int)h->dev.size() ||
+        (precision != MG_FP64 && precision != MG_MIXED))
+        return MG_ERR_INVALID_ARG;
+    return guard(h, [&]() {
+        hipStream_t st = (hipStream_t)stream;
+        DevLevel &D = h->dev[level], &C = h->dev[level + 1];
+        if (precision == MG_FP64)
+            launch_prolong<double>(D.args, C.args, D.mask, C.mask, (const double *)ec_dev, (double *)u_dev, D.pex_n,
+                                   D.pex_fine, D.pex_coarse, false, st);
+        else
+            launch_prolong<float>(D.args, C.args, D.mask, C.mask, (const float *)ec_dev, (float *)u_dev, D.pex_n,
+                                  D.pex_fine, D.pex_coarse, false, st);
+        HIPCHECK(hipGetLastError());
+    });
+}
+
 mg_status mg_residual(mg_handle h, int level, const double *b_dev, const double *u_dev, double *r_dev, double *rnorm,
                       void *stream) {
     if (!h || !b_dev || !u_dev || level < 0 || level >= (int)h->dev.size()) return MG_ERR_INVALID_ARG;
@@ -852,6 +1103,7 @@ mg_status mg_solve(mg_handle h, const double *f_dev, const double *g_dev, double
             }
             run_iterations(h, k, st);
             HIPCHECK(hipStreamSynchronize(st));
+            if (h->timing) collect_timing(h);
             for (int i = 0; i < k && !stop; ++i) {
                 ++it;
                 rel = h->host_scalar[i] / bnorm;
@@ -889,12 +1141,15 @@ mg_status mg_query(mg_handle h, mg_info *info) {
         info->n_plg[l] = (int)L.plg_cells.size();
         info->n_sep[l] = h->solvers[l].nsep;
         info->sweep_words[l] = h->dev[l].sweep_words;
+        info->n_sfv[l] = h->dev[l].nsfv;
+        info->cond_A22[l] = l < (int)h->cond_a22.size() ? h->cond_a22[l] : 0.0;
         info->nnz_plg += (long long)L.col.size();
     }
     info->n_face = h->levels[0]->n_face;
     info->n_irr = h->levels[0]->n_irr;
     info->device_bytes = h->bytes;
     info->setup_seconds = h->setup_seconds;
+    for (int k = 0; k < 6; ++k) info->setup_stage_seconds[k] = h->stage[k];
     return MG_OK;
 }
 
@@ -925,65 +1180,22 @@ mg_status mg_export_level(mg_handle h, int level, int *kind, int *n_plg, long lo
 mg_status mg_cell_quadrature(mg_handle h, int *n, long long *nnodes, int *cell, long long *ptr, double *x, double *y,
                              double *w) {
     if (!h || !n || !nnodes) return MG_ERR_INVALID_ARG;
-    const Level &L = *h->levels[0];
-    const CutGrid &cg = L.cg;
-    std::vector<double> g16x, g16w, g8x, g8w;
-    gauss_legendre(16, g16x, g16w);
-    gauss_legendre(8, g8x, g8w);
-    const double hh = L.g.h;
     long long cnt = 0;
     int ncell = 0;
-    for (size_t s = 0; s < cg.irr_cells.size(); ++s) {
-        const int c0 = cg.irr_cells[s];
-        const CellData &d = cg.irr[s];
-        if (!cg.active[c0]) continue;
-        const double vol = d.mom[0] * hh * hh;
-        if (ptr && x) ptr[ncell] = cnt;
-        if (cell && x) cell[ncell] = c0;
-        auto emit = [&](double px, double py, double pw) {
-            if (x) {
-                x[cnt] = px;
-                y[cnt] = py;
-                w[cnt] = pw / vol;
-            }
-            ++cnt;
-        };
-        for (int ci : d.members) {
-            const Comp &c = cg.comps[ci];
-            const double X0 = L.g.x0 + c.ci * hh, Y0 = L.g.y0 + c.cj * hh, xr = X0 + 0.5 * hh;
-            if (c.full) {
-                for (int a = 0; a < 8; ++a)
-                    for (int b = 0; b < 8; ++b)
-                        emit(X0 + (0.5 + 0.5 * g8x[a]) * hh, Y0 + (0.5 + 0.5 * g8x[b]) * hh, 0.25 * hh * hh * g8w[a] * g8w[b]);
-                continue;
-            }
-            for (const LoopItem &it : c.items) {
-                if (!it.is_edge) {
-                    const Seg &sg = h->curves.c[it.piece.curve][it.piece.seg];
-                    for (int k = 0; k < 16; ++k) {
-                        double t = 0.5 * (it.piece.tb - it.piece.ta) * g16x[k] + 0.5 * (it.piece.ta + it.piece.tb);
-                        double px, py, dx, dy;
-                        sg.point(t, px, py);
-                        sg.deriv(t, dx, dy);
-                        double ow = 0.5 * (it.piece.tb - it.piece.ta) * g16w[k] * dy;
-                        double half = 0.5 * (px - xr);
-                        for (int q = 0; q < 16; ++q) emit(xr + half * (1.0 + g16x[q]), py, ow * g16w[q] * half);
-                    }
-                } else if (it.side == 1 || it.side == 3) {
-                    double px = it.side == 1 ? X0 + hh : X0;
-                    double ya = it.side == 1 ? Y0 + it.s0 * hh : Y0 + (1.0 - it.s0) * hh;
-                    double yb = it.side == 1 ? Y0 + it.s1 * hh : Y0 + (1.0 - it.s1) * hh;
-                    for (int k = 0; k < 8; ++k) {
-                        double py = 0.5 * (yb - ya) * g8x[k] + 0.5 * (ya + yb);
-                        double ow = 0.5 * (yb - ya) * g8w[k];
-                        double half = 0.5 * (px - xr);
-                        for (int q = 0; q < 16; ++q) emit(xr + half * (1.0 + g16x[q]), py, ow * g16w[q] * half);
-                    }
-                }
-            }
+    cut_cell_nodes(h, [&](int c0, bool first) {
+        if (first) {
+            if (ptr && x) ptr[ncell] = cnt;
+            if (cell && x) cell[ncell] = c0;
+            ++ncell;
         }
-        ++ncell;
-    }
+    }, [&](double px, double py, double pw) {
+        if (x) {
+            x[cnt] = px;
+            y[cnt] = py;
+            w[cnt] = pw;
+        }
+        ++cnt;
+    });
     if (ptr && x) ptr[ncell] = cnt;
     *n = ncell;
     *nnodes = cnt;
@@ -995,93 +1207,134 @@ mg_status mg_cell_quadrature(mg_handle h, int *n, long long *nnodes, int *cell, 
 mg_status mg_boundary_quadrature(mg_handle h, int *n, long long *nnodes, long long *ptr, double *x, double *y,
                                  double *w, double *nxo, double *nyo, int *bc, double *alpha1, double *alpha2) {
     if (!h || !n || !nnodes) return MG_ERR_INVALID_ARG;
-    const Level &L = *h->levels[0];
-    const CutGrid &cg = L.cg;
-    const int nx = L.g.nx, ny = L.g.ny;
-    const double hh = L.g.h;
-    std::vector<double> g16x, g16w, g8x, g8w;
-    gauss_legendre(16, g16x, g16w);
-    gauss_legendre(8, g8x, g8w);
     long long cnt = 0;
     int entry = 0;
-    auto emit = [&](double px, double py, double pw, double n0, double n1, int b, double a1, double a2) {
+    boundary_nodes(h, [&]() {
+        if (ptr && x) ptr[entry] = cnt;
+        ++entry;
+    }, [&](double px, double py, double pw, double n0, double n1, int curve, int seg) {
         if (x) {
+            const Seg &sg = h->curves.c[curve][seg];
             x[cnt] = px; y[cnt] = py; w[cnt] = pw; nxo[cnt] = n0; nyo[cnt] = n1;
-            bc[cnt] = b; alpha1[cnt] = a1; alpha2[cnt] = a2;
+            bc[cnt] = sg.bc; alpha1[cnt] = sg.al1; alpha2[cnt] = sg.al2;
         }
         ++cnt;
-    };
-    const double x1 = L.g.x0 + nx * hh, y1 = L.g.y0 + ny * hh;
-    // bottom, top, left, right faces
-    for (int side : {0, 2, 3, 1}) {
-        const Seg &sg = h->curves.c[0][side];
-        int m = (side == 0 || side == 2) ? nx : ny;
-        for (int k = 0; k < m; ++k) {
-            if (ptr && x) ptr[entry] = cnt;
-            for (int q = 0; q < 8; ++q) {
-                double s = L.g.x0 + (k + 0.5 + 0.5 * g8x[q]) * hh, tt = L.g.y0 + (k + 0.5 + 0.5 * g8x[q]) * hh;
-                if (side == 0) emit(s, L.g.y0, 0.5 * g8w[q], 0.0, -1.0, sg.bc, sg.al1, sg.al2);
-                else if (side == 2) emit(s, y1, 0.5 * g8w[q], 0.0, 1.0, sg.bc, sg.al1, sg.al2);
-                else if (side == 3) emit(L.g.x0, tt, 0.5 * g8w[q], -1.0, 0.0, sg.bc, sg.al1, sg.al2);
-                else emit(x1, tt, 0.5 * g8w[q], 1.0, 0.0, sg.bc, sg.al1, sg.al2);
-            }
-            ++entry;
-        }
-    }
-    for (int cl = 0; cl < nx * ny; ++cl) {
-        if (L.g_of_cell[cl] < 0) continue;
-        const CellData &d = cg.irr[cg.irr_slot[cl]];
-        if (ptr && x) ptr[entry] = cnt;
-        double len = 0.0;
-        for (auto &bp : d.bp) {
-            const Seg &sg = h->curves.c[bp.curve][bp.seg];
-            for (int q = 0; q < 16; ++q) {
-                double t = 0.5 * (bp.tb - bp.ta) * g16x[q] + 0.5 * (bp.ta + bp.tb), dx, dy;
-                sg.deriv(t, dx, dy);
-                len += 0.5 * (bp.tb - bp.ta) * g16w[q] * std::hypot(dx, dy);
-            }
-        }
-        for (auto &bp : d.bp) {
-            const Seg &sg = h->curves.c[bp.curve][bp.seg];
-            for (int q = 0; q < 16; ++q) {
-                double t = 0.5 * (bp.tb - bp.ta) * g16x[q] + 0.5 * (bp.ta + bp.tb), px, py, dx, dy;
-                sg.point(t, px, py);
-                sg.deriv(t, dx, dy);
-                double sp = std::hypot(dx, dy);
-                emit(px, py, 0.5 * (bp.tb - bp.ta) * g16w[q] * sp / len, dy / sp, -dx / sp, sg.bc, sg.al1, sg.al2);
-            }
-        }
-        ++entry;
-    }
+    });
     if (ptr && x) ptr[entry] = cnt;
     *n = entry;
     *nnodes = cnt;
     return MG_OK;
 }
 
+mg_status mg_project_rhs(mg_handle h, mg_f_batch f, mg_g_batch g, void *ctx, int gauss_points, double *f_dev,
+                         double *g_dev, void *stream) {
+    if (!h || !f || !f_dev || gauss_points < 1 || gauss_points > 16) return MG_ERR_INVALID_ARG;
+    if (h->levels[0]->n_face + h->levels[0]->n_irr > 0 && (!g || !g_dev)) return MG_ERR_INVALID_ARG;
+    return guard(h, [&]() {
+        const Level &L = *h->levels[0];
+        const int nx = L.g.nx, ny = L.g.ny;
+        const double hh = L.g.h;
+        const size_t pitch = (size_t)nx + 4;
+        std::vector<double> fh((size_t)(ny + 4) * pitch, 0.0);
+        constexpr long long CHUNK = 1 << 20;
+        std::vector<double> bx, by, bw, bo;
+        std::vector<long long> dst;        // padded cell (f) or entry (g) per node
+        std::vector<int> bcv, bsg;
+        std::vector<double> bnx, bny;
+        // f: tensor Gauss-Legendre on full cells, the library's cut-cell rule
+        // on the others
+        auto flush_f = [&]() {
+            if (bx.empty()) return;
+            bo.assign(bx.size(), 0.0);
+            f((long long)bx.size(), bx.data(), by.data(), bo.data(), ctx);
+            for (size_t k = 0; k < bx.size(); ++k) fh[dst[k]] += bw[k] * bo[k];
+            bx.clear(); by.clear(); bw.clear(); dst.clear();
+        };
+        std::vector<double> gx, gw;
+        gauss_legendre(gauss_points, gx, gw);
+        std::vector<char> cut((size_t)nx * ny, 0);
+        for (size_t s = 0; s < L.cg.irr_cells.size(); ++s) cut[L.cg.irr_cells[s]] = 1;
+        for (int cl = 0; cl < nx * ny; ++cl) {
+            if (!L.cg.active[cl] || cut[cl]) continue;
+            const double X0 = L.g.x0 + (cl % nx) * hh, Y0 = L.g.y0 + (cl / nx) * hh;
+            const long long pc = (long long)padded_index(nx, cl);
+            for (int a = 0; a < gauss_points; ++a)
+                for (int b = 0; b < gauss_points; ++b) {
+                    bx.push_back(X0 + (0.5 + 0.5 * gx[a]) * hh);
+                    by.push_back(Y0 + (0.5 + 0.5 * gx[b]) * hh);
+                    bw.push_back(0.25 * gw[a] * gw[b]);
+                    dst.push_back(pc);
+                }
+            if ((long long)bx.size() >= CHUNK) flush_f();
+        }
+        long long cur_cell = 0;
+        cut_cell_nodes(h, [&](int c0, bool first) {
+            if (first) cur_cell = (long long)padded_index(nx, c0);
+        }, [&](double px, double py, double pw) {
+            bx.push_back(px);
+            by.push_back(py);
+            bw.push_back(pw);
+            dst.push_back(cur_cell);
+            if ((long long)bx.size() >= CHUNK) flush_f();
+        });
+        flush_f();
+        // g: boundary averages of the data in the library's layout
+        const int nent = L.n_face + L.n_irr;
+        std::vector<double> gh(std::max(nent, 1), 0.0);
+        auto flush_g = [&]() {
+            if (bx.empty()) return;
+            bo.assign(bx.size(), 0.0);
+            g((long long)bx.size(), bx.data(), by.data(), bcv.data(), bsg.data(), bnx.data(), bny.data(), bo.data(),
+              ctx);
+            for (size_t k = 0; k < bx.size(); ++k) gh[dst[k]] += bw[k] * bo[k];
+            bx.clear(); by.clear(); bw.clear(); dst.clear(); bcv.clear(); bsg.clear(); bnx.clear(); bny.clear();
+        };
+        long long entry = -1;
+        if (g) {
+            boundary_nodes(h, [&]() { ++entry; }, [&](double px, double py, double pw, double n0, double n1, int curve,
+                                                     int seg) {
+                bx.push_back(px); by.push_back(py); bw.push_back(pw); dst.push_back(entry);
+                bcv.push_back(curve); bsg.push_back(seg); bnx.push_back(n0); bny.push_back(n1);
+                if ((long long)bx.size() >= CHUNK) flush_g();
+            });
+            flush_g();
+        }
+        hipStream_t st = (hipStream_t)stream;
+        HIPCHECK(hipMemcpyAsync(f_dev, fh.data(), fh.size() * 8, hipMemcpyHostToDevice, st));
+        if (g && nent > 0) HIPCHECK(hipMemcpyAsync(g_dev, gh.data(), (size_t)nent * 8, hipMemcpyHostToDevice, st));
+        HIPCHECK(hipStreamSynchronize(st));
+    });
+}
+
 mg_status mg_kernel_timing(mg_handle h, int enable, int *launches, double *avg_ms) {
     if (!h) return MG_ERR_INVALID_ARG;
     return guard(h, [&]() {
         if (enable) {
-            if (h->ev.empty()) {
-                h->ev.resize(2 * 8192);
-                for (auto &e : h->ev) HIPCHECK(hipEventCreate(&e));
+            const int pairs = ITER_CHUNK * std::max(1, h->opt.nu1 + h->opt.nu2);
+            if ((int)h->ev.size() < 2 * pairs) {
+                std::lock_guard<std::mutex> lk(g_capture_mu);
+                while ((int)h->ev.size() < 2 * pairs) {
+                    hipEvent_t e;
+                    HIPCHECK(hipEventCreate(&e));
+                    h->ev.push_back(e);
+                }
             }
             h->nrec = 0;
+            h->tim_total_ms = 0.0;
+            h->tim_last = 0;
             h->timing = true;
             return;
         }
         h->timing = false;
-        double tot = 0.0;
-        for (int k = 0; k < h->nrec; ++k) {
-            HIPCHECK(hipEventSynchronize(h->ev[2 * k + 1]));
-            float ms = 0.f;
-            HIPCHECK(hipEventElapsedTime(&ms, h->ev[2 * k], h->ev[2 * k + 1]));
-            tot += ms;
-        }
         if (launches) *launches = h->nrec;
-        if (avg_ms) *avg_ms = h->nrec ? tot / h->nrec : 0.0;
+        if (avg_ms) *avg_ms = h->nrec ? h->tim_total_ms / h->nrec : 0.0;
     });
+}
+
+mg_status mg_set_eager(mg_handle h, int eager) {
+    if (!h) return MG_ERR_INVALID_ARG;
+    h->eager = eager != 0;
+    return MG_OK;
 }
 
 mg_status mg_destroy(mg_handle h) {

@@ -462,7 +462,7 @@ void Level::fit_inputs(std::vector<double> &Mall, std::vector<double> &phi, std:
                 }
             }
             for (int q = 0; q < NB; ++q) M[(size_t)NB * NB + q] = tot[q] / len;
-            w[NB] = 0.5;
+            w[NB] = w_min;
             ncol[r] = NB + 1;
         }
         // rank the candidates by their fitted rows
@@ -473,7 +473,7 @@ void Level::fit_inputs(std::vector<double> &Mall, std::vector<double> &phi, std:
                 cell_moments(cg, qi, qj, mk);
                 shift_moments(mk, lat[k][0], lat[k][1], sh);
                 for (int q = 0; q < NB; ++q) M[(size_t)k * NB + q] = sh[q] / mk[0];
-                w[k] = std::max(std::hypot((double)lat[k][0], (double)lat[k][1]), 0.5);
+                w[k] = std::max(std::hypot((double)lat[k][0], (double)lat[k][1]), w_min);
             }
         };
         const auto &cands = found[cand_of[r]];

@@ -313,6 +313,46 @@ __device__ __forceinline__ void jacobi_tile(const LevelArgs &L, const T *__restr
     }
 }
 
+// Launch A, tile role of the multicolour variant (an extension of eq.
+// (5.5)): the tile with its halo is loaded into LDS from the old iterate
+// (ghosts included), then the SFV cells are updated colour by colour in LDS,
+// each colour from the values the previous colours left.  Colours: (i + j)
+// mod 3 for the plus-shaped stencil, (i + 3 j) mod 9 for the 5 x 5 box, so
+// that no two cells of one colour are in each other's stencil and a colour
+// is updated in place without races.  Cells in other tiles keep their old
+// values for the whole launch (Jacobi across tiles).  In each colour pass
+// the threads take consecutive cells of that colour, so every lane works.
+template <typename T, bool MIXED, int TYv>
+__device__ __forceinline__ void multicolour_tile(const LevelArgs &L, const T *__restrict__ uold,
+                                                 const T *__restrict__ b, T *__restrict__ unew,
+                                                 const uint8_t *__restrict__ mask, bool uzero, int i0, int j0,
+                                                 T (*s)[HX], double *gws) {
+    constexpr int NC = MIXED ? 9 : 3, MULT = MIXED ? 3 : 1;
+    constexpr int PER_ROW = (TX + NC - 1) / NC;          // cells of one colour per tile row, at most
+    auto uat = [&](int a, int c) { return uzero ? (T)0 : uold[pidx(L, a, c)]; };
+    load_tile<T, decltype(uat), TYv>(s, gws, uat, L, i0, j0);
+    __syncthreads();
+    const T wod = (T)L.omega_over_d;
+    for (int k = 0; k < NC; ++k) {
+        for (int q = threadIdx.x; q < TYv * PER_ROW; q += NT) {
+            const int r = q / PER_ROW, m = q - r * PER_ROW;
+            const int j = j0 + r;
+            int c0 = (k - i0 - MULT * j) % NC;
+            if (c0 < 0) c0 += NC;
+            const int lx = c0 + NC * m, i = i0 + lx;
+            if (lx >= TX || i >= L.nx || j >= L.ny) continue;
+            const size_t id = pidx(L, i, j);
+            if (mask[id] != 1) continue;
+            const int ly = r + 2, cx = lx + 2;
+            const T au = apply_sfv<T, MIXED>(L, [&](int dx, int dy) { return s[ly + dy][cx + dx]; });
+            const T v = s[ly][cx] + wod * (b[id] - au);
+            s[ly][cx] = v;
+            unew[id] = v;
+        }
+        __syncthreads();
+    }
+}
+
 // Launch A, PLG role: one group of PLG rows (a segment slice, or a run of
 // separator rows).  Dense row-major blocks are applied one wavefront per
 // row, 8 rows at a time: the 64 lanes read consecutive columns and the
@@ -414,10 +454,6 @@ constexpr size_t smooth_a_lds() {
 // tile heights of launch A: short tiles on small grids (more blocks, shorter
 // per-thread chains), tall tiles on large grids (less halo traffic)
 constexpr int TY_SMALL = 8;
-template <typename T>
-constexpr long long small_grid_cells() {
-    return sizeof(T) == 4 ? 512 * 512 : 256 * 256;
-}
 
 // Tile of block bid in a launch whose first n blocks are tiles.  Blocks are
 // dealt to the 8 XCDs in turn (block b to XCD b mod 8), so this hands each
@@ -466,7 +502,6 @@ __global__ __launch_bounds__(NT) void k_smooth_a(LevelArgs L, const T *__restric
 // own keeps more waves per SIMD in flight to cover the memory latency; the
 // PLG groups follow as k_smooth_a with no tiles, reading the SFV values the
 // tiles wrote.
-constexpr long long SPLIT_CELLS = 2048LL * 2048;
 // tile height of k_smooth_tiles (the shorter FP64 tiles need fewer registers)
 template <typename T>
 constexpr int ty_split() {
@@ -482,6 +517,17 @@ __global__ __launch_bounds__(NT) void k_smooth_tiles(LevelArgs L, const T *__res
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     jacobi_tile<T, MIXED, TYv>(L, uold, b, unew, mask, uzero != 0, (t % tiles_x) * TX, (t / tiles_x) * TYv,
                                reinterpret_cast<T(*)[HX]>(smem), gws);
+}
+
+template <typename T, bool MIXED, int TYv>
+__global__ __launch_bounds__(NT) void k_smooth_tiles_mc(LevelArgs L, const T *__restrict__ uold,
+                                                        const T *__restrict__ b, T *__restrict__ unew,
+                                                        const uint8_t *__restrict__ mask, int tiles_x, int uzero) {
+    __shared__ __align__(16) T smem[(TYv + 4) * HX];
+    __shared__ double gws[32];
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    multicolour_tile<T, MIXED, TYv>(L, uold, b, unew, mask, uzero != 0, (t % tiles_x) * TX, (t / tiles_x) * TYv,
+                                    reinterpret_cast<T(*)[HX]>(smem), gws);
 }
 
 // Launch B: r_S = t_S - A_SB y (every block forms all of it in LDS), then
@@ -721,6 +767,77 @@ __global__ __launch_bounds__(64 * BOT_WAVES) void k_bottom(int n, const int *__r
 }
 
 // ---------------------------------------------------------------------------
+// Dense FP64 inverse of the coarsest level's matrix (setup only): Gauss-Jordan
+// elimination with partial pivoting on the augmented n x 2n row-major array
+// W = [A | I], one pivot column per step, two launches per step.  On exit
+// the right half holds A^{-1}.  status != 0 (set by the pivot kernel: the
+// 1-based step whose best pivot is below `tiny` or not finite) makes every
+// later launch return at once.
+__global__ __launch_bounds__(1024) void k_gj_pivot(int n, int k, double *__restrict__ W, double *__restrict__ f,
+                                                   int *__restrict__ status, double tiny) {
+    __shared__ double vmax[16];
+    __shared__ int imax[16];
+    __shared__ int piv_row;
+    __shared__ double piv_inv;
+    if (*status) return;
+    const size_t ld = 2 * (size_t)n;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double best = -1.0;
+    int bi = k;
+    for (int i = k + threadIdx.x; i < n; i += blockDim.x) {
+        const double v = fabs(W[(size_t)i * ld + k]);
+        if (v > best) { best = v; bi = i; }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_down(best, off, 64);
+        const int oi = __shfl_down(bi, off, 64);
+        if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+    }
+    if (lane == 0) { vmax[wave] = best; imax[wave] = bi; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double bv = vmax[0];
+        int b = imax[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+            if (vmax[w] > bv || (vmax[w] == bv && imax[w] < b)) { bv = vmax[w]; b = imax[w]; }
+        const bool ok = bv > tiny && bv <= 1.7976931348623157e308;
+        if (!ok) *status = k + 1;
+        piv_row = ok ? b : -1;
+        piv_inv = ok ? 1.0 / W[(size_t)b * ld + k] : 0.0;
+    }
+    __syncthreads();
+    const int p = piv_row;
+    if (p < 0) return;
+    const double s = piv_inv;
+    // swap rows k and p, scale the pivot row (columns below k are zero in
+    // both rows' left halves)
+    for (size_t j = (size_t)k + threadIdx.x; j < ld; j += blockDim.x) {
+        const double vk = W[(size_t)k * ld + j], vp = W[(size_t)p * ld + j];
+        W[(size_t)p * ld + j] = vk;
+        W[(size_t)k * ld + j] = vp * s;
+    }
+    __syncthreads();
+    // multipliers of the elimination: column k of the other rows
+    for (int i = threadIdx.x; i < n; i += blockDim.x) f[i] = i == k ? 0.0 : W[(size_t)i * ld + k];
+}
+
+// W[i][j] -= f[i] W[k][j] for rows i != k and columns j >= k; each block
+// takes 4 rows and 256 consecutive columns.
+__global__ __launch_bounds__(256) void k_gj_eliminate(int n, int k, double *__restrict__ W,
+                                                      const double *__restrict__ f, const int *__restrict__ status) {
+    if (*status) return;
+    const size_t ld = 2 * (size_t)n;
+    const size_t j = (size_t)k + (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= ld) return;
+    const double pk = W[(size_t)k * ld + j];
+    for (int r = 0; r < 4; ++r) {
+        const int i = blockIdx.y * 4 + r;
+        if (i >= n || i == k) continue;
+        W[(size_t)i * ld + j] -= f[i] * pk;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Residual max-norm over the active cells, FP64: tiles compute the SFV rows
 // by the stencil; blocks after the tiles compute the PLG rows from their
 // fixed-width rows (one thread per row).  CORRECT: the iterate is u + e (e
@@ -909,12 +1026,30 @@ inline dim3 tile_grid(const LevelArgs &L) { return dim3((L.nx + TX - 1) / TX, (L
 
 template <typename T>
 void launch_smooth_a(const LevelArgs &L, const T *uold, const T *b, T *unew, const uint8_t *mask, bool uzero,
-                     const PlgDev<T> &P, hipStream_t st) {
-    const bool small = (long long)L.nx * L.ny <= small_grid_cells<T>();
+                     const PlgDev<T> &P, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+    const bool small = (sizeof(T) == 4 ? L.small32 : L.small64) != 0;
     const int ty = small ? TY_SMALL : TY;
     const int tiles_x = (L.nx + TX - 1) / TX, ntile = tiles_x * ((L.ny + ty - 1) / ty);
     const int uz = uzero ? 1 : 0;
-    if (!small && (long long)L.nx * L.ny >= SPLIT_CELLS) {
+    if (ev0) (void)hipEventRecord(ev0, st);
+    if (L.colouring) {
+        // the PLG groups read the SFV values the tiles wrote (they cannot
+        // recompute a multicolour sweep)
+        constexpr int tys = ty_split<T>();
+        const int nts = tiles_x * ((L.ny + tys - 1) / tys);
+        if (L.mixed)
+            hipLaunchKernelGGL((k_smooth_tiles_mc<T, true, tys>), dim3(nts), dim3(NT), 0, st, L, uold, b, unew, mask,
+                               tiles_x, uz);
+        else
+            hipLaunchKernelGGL((k_smooth_tiles_mc<T, false, tys>), dim3(nts), dim3(NT), 0, st, L, uold, b, unew,
+                               mask, tiles_x, uz);
+        if (ev1) (void)hipEventRecord(ev1, st);
+        if (P.nblk1 == 0) return;
+        hipLaunchKernelGGL((k_smooth_a<T, false, TY, true>), dim3(P.nblk1), dim3(NT), 0, st, L, uold, b, unew,
+                           mask, tiles_x, 0, uz, P);
+        return;
+    }
+    if (L.split_a) {
         // the tiles write the SFV cells, then the PLG groups read those
         // of their couplings and write the PLG rows
         constexpr int tys = ty_split<T>();
@@ -925,6 +1060,7 @@ void launch_smooth_a(const LevelArgs &L, const T *uold, const T *b, T *unew, con
         else
             hipLaunchKernelGGL((k_smooth_tiles<T, false, tys>), dim3(nts), dim3(NT), 0, st, L, uold, b, unew,
                                mask, tiles_x, uz);
+        if (ev1) (void)hipEventRecord(ev1, st);
         if (P.nblk1 == 0) return;
         // no stencil is evaluated here, so one instantiation serves b = 0 and b != 0
         hipLaunchKernelGGL((k_smooth_a<T, false, TY, true>), dim3(P.nblk1), dim3(NT), 0, st, L, uold, b, unew,
@@ -936,17 +1072,15 @@ void launch_smooth_a(const LevelArgs &L, const T *uold, const T *b, T *unew, con
     hipLaunchKernelGGL((k_smooth_a<T, MX, TYV>), grid, dim3(NT), 0, st, L, uold, b, unew, mask, tiles_x, ntile, uz, P)
     if (L.mixed) { if (small) MG_SA(true, TY_SMALL); else MG_SA(true, TY); }
     else { if (small) MG_SA(false, TY_SMALL); else MG_SA(false, TY); }
+    if (ev1) (void)hipEventRecord(ev1, st);
 #undef MG_SA
 }
-
-// launch B in two kernels from this many separator rows on
-constexpr int SPLIT_B_SEP = 768;
 
 template <typename T>
 void launch_smooth_b(const PlgDev<T> &P, T *unew, hipStream_t st) {
     if (!P.nblk2) return;
     const size_t lds = sizeof(T) * (((P.nsep + 3) & ~3) + PLG_KMAX);
-    if (P.nsep >= SPLIT_B_SEP && P.nblk2_seg > 0 && P.nblk2_seg < P.nblk2) {
+    if (P.split_b && P.nblk2_seg > 0 && P.nblk2_seg < P.nblk2) {
         hipLaunchKernelGGL((k_smooth_b<T, 1>), dim3(P.nblk2 - P.nblk2_seg), dim3(NT), lds, st, P, unew);
         hipLaunchKernelGGL((k_smooth_b<T, 2>), dim3(P.nblk2_seg), dim3(NT), sizeof(T) * PLG_KMAX, st, P, unew);
         return;
@@ -1043,15 +1177,22 @@ void launch_zero_inactive(size_t n, const uint8_t *mask, double *u, hipStream_t 
     hipLaunchKernelGGL(k_zero_inactive, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, mask, u);
 }
 
+void launch_gj_step(int n, int k, double *W, double *f, int *status, double tiny, hipStream_t st) {
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(1024), 0, st, n, k, W, f, status, tiny);
+    const size_t cols = 2 * (size_t)n - (size_t)k;
+    hipLaunchKernelGGL(k_gj_eliminate, dim3((unsigned)((cols + 255) / 256), (unsigned)((n + 3) / 4)), dim3(256), 0, st,
+                       n, k, W, (const double *)f, (const int *)status);
+}
+
 void launch_fit(int m, const double *M, const double *phi, const double *w, const int *ncol, double *work,
                 double *beta, int *status, hipStream_t st) {
     hipLaunchKernelGGL(k_fit, dim3((m + 63) / 64), dim3(64), 0, st, m, M, phi, w, ncol, work, beta, status);
 }
 
 template void launch_smooth_a<double>(const LevelArgs &, const double *, const double *, double *, const uint8_t *,
-                                      bool, const PlgDev<double> &, hipStream_t);
+                                      bool, const PlgDev<double> &, hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_smooth_a<float>(const LevelArgs &, const float *, const float *, float *, const uint8_t *, bool,
-                                     const PlgDev<float> &, hipStream_t);
+                                     const PlgDev<float> &, hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_smooth_b<double>(const PlgDev<double> &, double *, hipStream_t);
 template void launch_smooth_b<float>(const PlgDev<float> &, float *, hipStream_t);
 template void launch_fill_zero<double>(size_t, double *, hipStream_t);

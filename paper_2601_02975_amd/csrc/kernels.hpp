@@ -23,6 +23,12 @@ struct LevelArgs {
     const uint8_t *full;
     int full_bx, full_by;
     int mixed;                  // b != 0
+    // launch shape of the smoother's launch A on this level (chosen at setup
+    // from the grid size, or forced by the options): split_a = 1 runs the
+    // SFV tiles and the PLG groups as two kernels; small32 / small64 = 1
+    // selects 8-row tiles for the fused kernel in FP32 / FP64
+    int split_a, small32, small64;
+    int colouring;              // 1: the multicolour variant of the SFV half of the smoother
 };
 
 // Launch A PLG block: rows [r0, r1) of group g (rows [gs, gs + n) in solve
@@ -71,6 +77,7 @@ struct PlgDev {
     const int *fcols_ptr = nullptr;     // k_j = fcols_ptr[j + 1] - fcols_ptr[j]
     const int *fcols = nullptr;         // separator index of each of those columns
     int nblk2_seg = 0;                  // launch B blocks of segment slices (they come first)
+    int split_b = 0;                    // launch B as two kernels (separator rows, then segment slices)
     const long long *sj_off = nullptr;  // rows of S'^{-1} at segment j's separator columns, k_j x nsep
     const T *SJ = nullptr;
     const T *sinv = nullptr;            // row-major nsep x nsep

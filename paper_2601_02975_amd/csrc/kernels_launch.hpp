@@ -9,10 +9,12 @@ namespace mgc {
 
 // one block-smoother sweep (Definition 5.6), uold -> unew: launch A (SFV
 // tiles, PLG gathers and segment solves), then launch B (separators and
-// segment corrections; nothing on levels without separators)
+// segment corrections; nothing on levels without separators);
+// ev0/ev1 (may be null) are recorded around the SFV tile kernel (the whole
+// launch A where it is one kernel)
 template <typename T>
 void launch_smooth_a(const LevelArgs &L, const T *uold, const T *b, T *unew, const uint8_t *mask, bool uzero,
-                     const PlgDev<T> &P, hipStream_t st);
+                     const PlgDev<T> &P, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 template <typename T>
 void launch_smooth_b(const PlgDev<T> &P, T *unew, hipStream_t st);
 template <typename T>
@@ -41,6 +43,10 @@ void launch_absmax(int n, const double *v, const uint8_t *mask, double *partial,
 void launch_rhs(size_t n, const uint8_t *mask, const double *f, double *b, int nrows, const int *ptr, const int *cell,
                 const int *gidx, const double *coef, const double *g, hipStream_t st);
 void launch_zero_inactive(size_t n, const uint8_t *mask, double *u, hipStream_t st);
+// one Gauss-Jordan step (pivot column k) on the augmented n x 2n array W
+// (row-major, [A | I] at the start); f holds n multipliers, status one int
+// (0 on entry)
+void launch_gj_step(int n, int k, double *W, double *f, int *status, double tiny, hipStream_t st);
 void launch_fit(int m, const double *M, const double *phi, const double *w, const int *ncol, double *work,
                 double *beta, int *status, hipStream_t st);
 

@@ -18,6 +18,7 @@ void corner_weights(const CutGrid &cg, int xside, int yside, int m, int k, doubl
 struct Level {
     mg_grid g{};
     double a = 0, b = 0, c = 0;
+    double w_min = 0.5;                           // smallest weight of eq. (4.17), boundary weight
     const Curves *curves = nullptr;
     CutGrid cg;
     std::vector<uint8_t> kind;                    // 0 inactive, 1 SFV, 2 PLG (row-major)

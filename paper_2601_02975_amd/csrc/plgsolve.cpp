@@ -439,4 +439,113 @@ void build_plg_plan(const Level &L, const PlgSolver &S, int nx, int slice, int b
     }
 }
 
+namespace {
+
+// x = A22^{-1} t (transpose = false) or x = A22^{-T} t, both in solve order:
+// A22 = [B E; C D] with B the segment blocks, E = A_BS, C = A_SB (the
+// separator rows' couplings), S' = D - C B^{-1} E, F = B^{-1} E.
+//   A22 x = t:   y = B^{-1} t_B, x_S = S'^{-1} (t_S - C y), x_B = y - F x_S
+//   A22^T z = w: z_S = S'^{-T} (w_S - F^T w_B), z_B = B^{-T} (w_B - C^T z_S)
+std::vector<double> plg_apply_inverse(const PlgSolver &S, const std::vector<double> &t, bool transpose) {
+    const int m = S.m, sb = S.sep_begin, ns = S.nsep;
+    std::vector<double> x(m, 0.0), xs(ns, 0.0), rs(ns, 0.0);
+    auto seg_mul = [&](int j, const double *in, double *out, bool tr) {
+        const int s0 = S.seg_start[j], Lj = S.seg_start[j + 1] - s0;
+        const double *B = &S.inv[S.inv_off[j]];
+        for (int r = 0; r < Lj; ++r) out[r] = 0.0;
+        for (int r = 0; r < Lj; ++r)
+            for (int c = 0; c < Lj; ++c) {
+                if (tr) out[c] += B[(size_t)r * Lj + c] * in[r];
+                else out[r] += B[(size_t)r * Lj + c] * in[c];
+            }
+    };
+    if (!transpose) {
+        for (int j = 0; j < S.nseg; ++j) seg_mul(j, &t[S.seg_start[j]], &x[S.seg_start[j]], false);
+        for (int s = 0; s < ns; ++s) {
+            double v = t[sb + s];
+            for (int e = S.sb_ptr[s]; e < S.sb_ptr[s + 1]; ++e) v -= S.sb_val[e] * x[S.sb_col[e]];
+            rs[s] = v;
+        }
+        for (int s = 0; s < ns; ++s) {
+            double v = 0.0;
+            for (int c = 0; c < ns; ++c) v += S.sinv[(size_t)s * ns + c] * rs[c];
+            xs[s] = v;
+        }
+        for (int j = 0; j < S.nseg; ++j) {
+            const int s0 = S.seg_start[j], Lj = S.seg_start[j + 1] - s0, k = S.fcols_ptr[j + 1] - S.fcols_ptr[j];
+            const double *F = &S.F[S.f_off[j]];
+            for (int r = 0; r < Lj; ++r)
+                for (int kk = 0; kk < k; ++kk) x[s0 + r] -= F[(size_t)r * k + kk] * xs[S.fcols[S.fcols_ptr[j] + kk]];
+        }
+        for (int s = 0; s < ns; ++s) x[sb + s] = xs[s];
+        return x;
+    }
+    for (int s = 0; s < ns; ++s) rs[s] = t[sb + s];
+    for (int j = 0; j < S.nseg; ++j) {
+        const int s0 = S.seg_start[j], Lj = S.seg_start[j + 1] - s0, k = S.fcols_ptr[j + 1] - S.fcols_ptr[j];
+        const double *F = &S.F[S.f_off[j]];
+        for (int r = 0; r < Lj; ++r)
+            for (int kk = 0; kk < k; ++kk) rs[S.fcols[S.fcols_ptr[j] + kk]] -= F[(size_t)r * k + kk] * t[s0 + r];
+    }
+    for (int c = 0; c < ns; ++c) {
+        double v = 0.0;
+        for (int s = 0; s < ns; ++s) v += S.sinv[(size_t)s * ns + c] * rs[s];
+        xs[c] = v;
+    }
+    std::vector<double> g(t.begin(), t.begin() + sb);
+    for (int s = 0; s < ns; ++s)
+        for (int e = S.sb_ptr[s]; e < S.sb_ptr[s + 1]; ++e) g[S.sb_col[e]] -= S.sb_val[e] * xs[s];
+    for (int j = 0; j < S.nseg; ++j) seg_mul(j, &g[S.seg_start[j]], &x[S.seg_start[j]], true);
+    for (int s = 0; s < ns; ++s) x[sb + s] = xs[s];
+    return x;
+}
+
+}  // namespace
+
+double cond1_estimate(const Level &L, const PlgSolver &S) {
+    const int m = S.m;
+    if (m == 0) return 0.0;
+    std::vector<int> pos(m);
+    for (int q = 0; q < m; ++q) pos[S.order[q]] = q;
+    std::vector<double> colsum(m, 0.0);
+    for (int r = 0; r < m; ++r)
+        for (int e = L.row_ptr[r]; e < L.row_ptr[r + 1]; ++e) {
+            const int pr = L.plg_row[L.col[e]];
+            if (pr >= 0) colsum[pos[pr]] += std::fabs(L.val[e]);
+        }
+    const double anorm = *std::max_element(colsum.begin(), colsum.end());
+    auto norm1 = [](const std::vector<double> &v) {
+        double s = 0.0;
+        for (double x : v) s += std::fabs(x);
+        return s;
+    };
+    std::vector<double> x(m, 1.0 / m);
+    double est = 0.0;
+    int last = -1;
+    for (int it = 0; it < 5; ++it) {
+        std::vector<double> y = plg_apply_inverse(S, x, false);
+        const double e = norm1(y);
+        if (it > 0 && e <= est) break;
+        est = e;
+        std::vector<double> xi(m);
+        for (int q = 0; q < m; ++q) xi[q] = y[q] >= 0.0 ? 1.0 : -1.0;
+        std::vector<double> z = plg_apply_inverse(S, xi, true);
+        int jmax = 0;
+        double zt = 0.0;
+        for (int q = 0; q < m; ++q) {
+            if (std::fabs(z[q]) > std::fabs(z[jmax])) jmax = q;
+            zt += z[q] * x[q];
+        }
+        if (std::fabs(z[jmax]) <= zt || jmax == last) break;
+        last = jmax;
+        std::fill(x.begin(), x.end(), 0.0);
+        x[jmax] = 1.0;
+    }
+    // Higham's extra test vector guards against the estimator's bad cases
+    std::vector<double> alt(m);
+    for (int q = 0; q < m; ++q) alt[q] = (q % 2 ? -1.0 : 1.0) * (1.0 + (m > 1 ? (double)q / (m - 1) : 0.0));
+    est = std::max(est, 2.0 * norm1(plg_apply_inverse(S, alt, false)) / (3.0 * m));
+    return anorm * est;
+}
+
 }  // namespace mgc

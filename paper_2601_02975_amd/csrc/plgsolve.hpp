@@ -26,6 +26,12 @@ struct PlgSolver {
 
 void build_plg_solver(const Level &L, int seg_max, PlgSolver &S);
 
+// 1-norm condition number ||A22||_1 ||A22^{-1}||_1 of the PLG block, the
+// second factor by Hager's estimator in Higham's form (a lower bound, exact
+// in most cases) from exact solves with A22 and its transpose through the
+// solver's factors; 0 when there are no PLG cells.
+double cond1_estimate(const Level &L, const PlgSolver &S);
+
 // Work layout of the two smoother launches on the GPU.
 //
 // Launch A computes, per "group" of PLG rows (each segment is a group; the

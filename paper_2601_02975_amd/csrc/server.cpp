@@ -78,15 +78,27 @@ struct mg_server_s {
     std::vector<std::thread> workers;
 
     // A request that can start now: its problem is idle and either resident
-    // or admissible (after evicting idle resident hierarchies, least recently
-    // used first).  Called with mu held.
-    bool pick(unsigned long long &ticket) {
+    // or admissible, possibly after evicting idle resident hierarchies (least
+    // recently used first).  Admission is decided before anything is
+    // evicted: hierarchies are evicted only when that makes the request fit
+    // (or when nothing else would stay resident, so that a request larger
+    // than the budget still runs alone).  The evicted handles are returned
+    // in `victims`, to be destroyed after mu is released.  Called with mu
+    // held.
+    bool pick(unsigned long long &ticket, std::vector<mg_handle> &victims) {
         for (auto it = queue.begin(); it != queue.end(); ++it) {
             Request &r = reqs[*it];
             Problem &p = problems[r.problem];
             if (p.busy) continue;
             if (!p.h && !p.failed) {
                 const long long need = footprint_estimate(p.grid);
+                long long idle = 0;
+                for (const Problem &q : problems)
+                    if (q.h && !q.busy) idle += q.bytes;
+                const long long busy_bytes = resident_bytes - idle;
+                const bool fits_after_eviction = busy_bytes + need <= opt.hbm_budget;
+                const bool runs_alone = busy_bytes == 0;
+                if (!fits_after_eviction && !runs_alone) continue;
                 while (resident_bytes + need > opt.hbm_budget) {
                     int victim = -1;
                     for (int k = 0; k < (int)problems.size(); ++k) {
@@ -94,13 +106,12 @@ struct mg_server_s {
                         if (q.h && !q.busy && (victim < 0 || q.last_used < problems[victim].last_used)) victim = k;
                     }
                     if (victim < 0) break;
-                    mg_destroy(problems[victim].h);
+                    victims.push_back(problems[victim].h);
                     problems[victim].h = nullptr;
                     resident_bytes -= problems[victim].bytes;
+                    problems[victim].bytes = 0;
                     ++evictions;
                 }
-                // with nothing else resident a request always starts (progress)
-                if (resident_bytes + need > opt.hbm_budget && resident_bytes > 0) continue;
                 resident_bytes += need;
                 p.bytes = need;
             }
@@ -117,7 +128,8 @@ struct mg_server_s {
         std::unique_lock<std::mutex> lk(mu);
         while (true) {
             unsigned long long ticket = 0;
-            cv_work.wait(lk, [&] { return stopping || pick(ticket); });
+            std::vector<mg_handle> victims;
+            cv_work.wait(lk, [&] { return stopping || pick(ticket, victims); });
             if (!ticket) return;                       // stopping with nothing to start
             Request &r = reqs[ticket];
             Problem &p = problems[r.problem];
@@ -126,6 +138,7 @@ struct mg_server_s {
             ++active;
             r.t_start = Clock::now();
             lk.unlock();
+            for (mg_handle v : victims) mg_destroy(v);
             mg_status rc = MG_OK;
             std::string err;
             if (p.failed) {

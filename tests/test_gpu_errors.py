@@ -1,0 +1,62 @@
+"""Failure paths of mg_setup and mg_solve through the C ABI.
+
+Each case is forced from the host: a weight that the paper reports as
+divergent, an iteration cap, a hole the grid cannot see.  Every kernel runs
+to completion as usual; only the returned status is checked."""
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def test_omega_four_fifths_diverges():
+    """Sec. 5.2: omega = 4/5 in eq. (5.5) diverges even on the unit square;
+    mg_solve stops with MG_ERR_DIVERGED once the residual grows three times."""
+    torch = _torch()
+    import paper_2601_02975_amd as mg
+    P = W.unit_square_config(64, 1.0, 0.0, 2.0)
+    S = mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, omega=0.8)
+    f, g = S.project(P.solution)
+    u = torch.zeros_like(f)
+    with pytest.raises(mg.MGError) as e:
+        S.solve(f, g, u, 1e-10)
+    print("omega 0.8:", e.value)
+    assert e.value.code == -5
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_iteration_cap_reports_no_convergence(precision):
+    """max_iters = 2: MG_ERR_NO_CONVERGENCE with the iteration count and the
+    relative residual of the last iterate, which u holds."""
+    torch = _torch()
+    import paper_2601_02975_amd as mg
+    P = W.unit_disk_config(0, 64)
+    S = mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=precision, max_iters=2)
+    f, g = S.project(P.solution)
+    u = torch.zeros_like(f)
+    it, rel, code = S.solve(f, g, u, 1e-10)
+    assert code == -4 and it == 2 and 1e-10 < rel < 1.0
+    b = torch.zeros_like(f)
+    S.rhs(f, g, b)
+    r = S.residual(0, b, u)
+    assert abs(r / float(b.abs().max()) - rel) <= 1e-6 * rel
+
+
+def test_unresolved_hole_is_a_geometry_error():
+    """A hole inside a single cell is not resolved by the grid (Algorithm 1
+    needs every cell's boundary crossings): MG_ERR_GEOMETRY."""
+    _torch()
+    import paper_2601_02975_amd as mg
+    h = 1.0 / 64
+    curves = [W.box_curve(0.0, 0.0, 1.0, 1.0), W.disk_hole(0.5 + 0.5 * h, 0.5 + 0.5 * h, 0.3 * h)]
+    with pytest.raises(mg.MGError) as e:
+        mg.Solver(W.Grid(0.0, 0.0, h, 64, 64), curves, 1.0, 0.0, 1.0)
+    assert e.value.code == -2

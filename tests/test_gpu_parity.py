@@ -72,11 +72,33 @@ def rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
+# FP64 parity of the V-cycle path (sweeps, transfers, iterates): 1e-12
+# relative, the target the solver is held to; the sums involved are short
+# (<= 25 products per stencil, <= 16 per PLG row) and the PLG block is solved
+# exactly with cond(A22) <= ~1e3 on these cases, so the expected differences
+# are ~1e-13
+FP64_PARITY = 1e-12
+
+
+def fit_condition(L, i, j):
+    """2-norm condition number of the weighted fit of PLG cell (i, j)
+    (eqs. (4.14)-(4.18)): M W^{1/2}, or M for a square regular fit."""
+    import math
+    lat = L.lattice[(i, j)]
+    M = np.array([L._avg_monomials((i + d[0], j + d[1]), d) for d in lat]).T
+    w = np.array([max(math.hypot(*d), L.w_min) for d in lat])
+    if L.beta[(i, j)][1] is not None:
+        M = np.hstack([M, L.boundary_average_of_basis(i, j)[:, None]])
+        w = np.append(w, L.w_min)
+    return np.linalg.cond(M / np.sqrt(w)[None, :])
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_setup_parity(name):
     """Classification (Definition 4.1), lattices and fitted coefficients of
     every PLG row on every level.  Fits are weighted minimum-norm solutions of
-    15 x 16 systems with cond(M W^{1/2}) up to ~1e4: bound 1e-10 relative."""
+    15 x 16 systems solved by different methods (Householder QR here, SVD in
+    the oracle): per row |d beta| <= 64 cond(M W^{1/2}) eps |beta|."""
     P, H = oracle(name)
     S = product(name)
     assert S.info["n_levels"] == len(H.levels)
@@ -92,13 +114,15 @@ def test_setup_parity(name):
             want = [(j + d[1]) * L.nx + i + d[0] for d in lat]
             assert list(col[rp[r]:rp[r + 1]]) == want
             scale = max(np.abs(beta).max(), abs(bbo) if bbo is not None else 0.0)
-            worst = max(worst, np.abs(val[rp[r]:rp[r + 1]] - beta).max() / scale)
+            bound = 64 * fit_condition(L, int(i), int(j)) * np.finfo(float).eps
+            d = np.abs(val[rp[r]:rp[r + 1]] - beta).max() / scale
             if bbo is None:
                 assert bb[r] == 0.0
             else:
-                worst = max(worst, abs(bb[r] - bbo) / scale)
-    print("max relative coefficient difference %.2e" % worst)
-    assert worst <= 1e-10
+                d = max(d, abs(bb[r] - bbo) / scale)
+            worst = max(worst, d / bound)
+    print("max relative coefficient difference / bound %.2e" % worst)
+    assert worst <= 1.0
 
 
 @pytest.mark.parametrize("name", ["disk64", "three_disks128", "square_cross32"])
@@ -136,7 +160,7 @@ def test_smoother_parity_all_levels(name):
         got = from_dev(L, ud)
         err = rel(got, want)
         print("level %d smoother rel diff %.2e" % (l, err))
-        assert err <= 1e-11
+        assert err <= FP64_PARITY
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -180,7 +204,7 @@ def test_vcycle_iterates(name, nu):
         S.vcycle(bd, ud)
         err = rel(from_dev(L, ud), uo)
         print("iterate %d rel diff %.2e" % (k + 1, err))
-        assert err <= 1e-11
+        assert err <= FP64_PARITY
 
 
 @pytest.mark.parametrize("name", ["disk64", "three_disks128", "star128", "disk_robin_box64"])
@@ -196,8 +220,8 @@ def test_solve_matches_oracle(name, precision):
     S = product(name, precision)
     L = H.levels[0]
     f, g = S.project(P.solution)
-    u = torch.zeros_like(torch.tensor(f, device="cuda"))
-    it, relres, code = S.solve(torch.tensor(f, device="cuda"), torch.tensor(g, device="cuda"), u, 1e-10)
+    u = torch.zeros_like(f)
+    it, relres, code = S.solve(f, g, u, 1e-10)
     assert code == 0 and relres <= 1e-10, (code, relres, it)
     from oracle.rhs import rhs
     b, _, _ = rhs(L, P.solution)
@@ -223,8 +247,7 @@ def test_mixed_step_is_fp32_accurate(name):
     L = H.levels[0]
     S64 = product(name, 0)
     S32 = mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=1, max_iters=1)
-    f, g = S64.project(P.solution)
-    ft, gt = torch.tensor(f, device="cuda"), torch.tensor(g, device="cuda")
+    ft, gt = S64.project(P.solution)
     u64 = torch.zeros_like(ft)
     u32 = torch.zeros_like(ft)
     S64f = mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=0, max_iters=1)
@@ -246,11 +269,11 @@ def test_graph_replays_match_eager(name, precision):
     P, H = oracle(name)
     S = mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=precision)
     f, g = S.project(P.solution)
-    ft, gt = torch.tensor(f, device="cuda"), torch.tensor(g, device="cuda")
-    S.kernel_timing(True)                       # eager launches
+    ft, gt = f, g
+    S.set_eager(True)
     ue = torch.zeros_like(ft)
     it_e, rel_e, _ = S.solve(ft, gt, ue, 1e-10)
-    S.kernel_timing(False)
+    S.set_eager(False)
     for k in range(3):
         ug = torch.zeros_like(ft)
         it_g, rel_g, _ = S.solve(ft, gt, ug, 1e-10)
@@ -279,7 +302,7 @@ def test_fmg_iterates(name):
         uo, _, _ = H.solve(b, tol=0.0, max_iters=k, cycle="FMG")
         err = rel(from_dev(L, u), uo)
         print("FMG iterate %d rel diff %.2e" % (k, err))
-        assert err <= 1e-11
+        assert err <= FP64_PARITY
         S.close()
 
 
@@ -294,13 +317,12 @@ def test_fmg_solve(name, precision):
     L = H.levels[0]
     Sv = mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=precision)
     Sf = mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=precision, cycle=mg.CYCLE_FMG)
-    f, g = Sv.project(P.solution)
-    ft, gt = torch.tensor(f, device="cuda"), torch.tensor(g, device="cuda")
+    ft, gt = Sv.project(P.solution)
     uv, uf = torch.zeros_like(ft), torch.zeros_like(ft)
     itv, relv, cv = Sv.solve(ft, gt, uv, 1e-10)
-    Sf.kernel_timing(True)
+    Sf.set_eager(True)
     itf, relf, cf = Sf.solve(ft, gt, uf, 1e-10)
-    Sf.kernel_timing(False)
+    Sf.set_eager(False)
     assert cv == 0 and cf == 0 and relf <= 1e-10
     assert itf < itv
     d = float((uf - uv).abs().max() / uv.abs().max())

@@ -37,8 +37,7 @@ def test_server_results_equal_alone(budget, precision):
     solvers = [mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=precision) for P in base]
     inputs = []
     for k, P in reqs:
-        f, g = solvers[k].project(P.solution)
-        inputs.append((torch.tensor(f, device="cuda"), torch.tensor(g, device="cuda")))
+        inputs.append(solvers[k].project(P.solution))
     alone = []
     for (k, P), (f, g) in zip(reqs, inputs):
         u = torch.zeros_like(f)

@@ -307,3 +307,52 @@ def test_robin_box_vcycle_converges_to_direct_solution():
     u, it, rel = H.solve(b, tol=1e-12, max_iters=100)
     assert rel <= 1e-12
     assert np.abs(u - direct).max() <= 1e-9 * np.abs(direct).max()
+
+
+# -- the multicolour variant of the smoother (an extension, not in the paper) --
+
+@pytest.fixture(scope="module")
+def mc_hierarchies():
+    P = W.three_disks_config(0, 128)
+    H = Hierarchy(P.grid, P.curves, P.a, P.b, P.c, P.eps, n_levels=2, colouring=True, block=(64, 16))
+    Q = W.unit_disk_config(0, 64)
+    G = Hierarchy(Q.grid, Q.curves, Q.a, Q.b, Q.c, Q.eps, n_levels=2, colouring=True, block=(64, 16))
+    return (P, H), (Q, G)
+
+
+def test_multicolour_colours_are_independent(mc_hierarchies):
+    """No two SFV cells of one colour couple through the in-block stencil:
+    (i + 3j) mod 9 for the 5 x 5 box (b != 0), (i + j) mod 3 for the plus
+    shape (b = 0), so each colour is a Jacobi step on independent cells."""
+    for P, H in mc_hierarchies:
+        for l in range(len(H.levels)):
+            colour, a_in = H.sm[l][8], H.sm[l][9]
+            for k in range(int(colour.max()) + 1):
+                sel = np.nonzero(colour == k)[0]
+                blk = a_in[sel][:, sel].tocoo()
+                assert np.all(blk.row == blk.col)
+
+
+def test_multicolour_reduces_to_jacobi_with_one_cell_blocks(mc_hierarchies):
+    """With blocks of a single cell every neighbour comes from the sweep's
+    starting values: the multicolour sweep is the omega-Jacobi sweep of
+    eq. (5.5) (then the PLG solve)."""
+    (P, H), _ = mc_hierarchies
+    J = Hierarchy(P.grid, P.curves, P.a, P.b, P.c, P.eps, n_levels=2)
+    C = Hierarchy(P.grid, P.curves, P.a, P.b, P.c, P.eps, n_levels=2, colouring=True, block=(1, 1))
+    rng = np.random.default_rng(8)
+    n = J.levels[0].n
+    u, b = rng.standard_normal(n), rng.standard_normal(n)
+    assert np.abs(C.smooth(0, u, b) - J.smooth(0, u, b)).max() <= 1e-12 * np.abs(J.smooth(0, u, b)).max()
+
+
+def test_multicolour_fixed_point_is_the_solution(mc_hierarchies):
+    """u* = A^{-1} b is left unchanged by a multicolour sweep (every partial
+    residual it uses is that of u*), and the sweep changes any other u."""
+    for P, H in mc_hierarchies:
+        L = H.levels[0]
+        b = np.random.default_rng(9).standard_normal(L.n)
+        ustar = spla.spsolve(L.A.tocsc(), b)
+        assert np.abs(H.smooth(0, ustar, b) - ustar).max() <= 1e-9 * np.abs(ustar).max()
+        v = ustar + np.random.default_rng(10).standard_normal(L.n)
+        assert np.abs(H.smooth(0, v, b) - v).max() > 1e-3
