@@ -97,7 +97,7 @@ def kernel_time(torch, S, f, g, solves, tol):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     launches, avg_ms = S.kernel_timing(False)
-    return launches, avg_ms, dt / solves
+    return launches, avg_ms, dt / max(solves, 1)
 
 
 def roofline(S, avg_ms, launches, traffic):
@@ -113,13 +113,22 @@ def roofline(S, avg_ms, launches, traffic):
             "sfv_cells": S.info["n_sfv"][0]}
 
 
-def fp64_floor(torch, S, f, g, cycles):
-    """The FP64 relative residual the GPU's FP64 iteration stagnates at: the
-    smallest over `cycles` V-cycles from u = 0 (tolerance below reach)."""
+def fp64_floor(torch, S, f, g, tols=(1e-11, 1e-12, 1e-13, 1e-14)):
+    """Where the GPU's FP64 iteration stagnates: the smallest of `tols` it
+    reaches (V-cycles from u = 0; an iteration whose residual grows three
+    times in a row stops as diverged, which here means stagnation)."""
     import paper_2601_02975_amd as mg
-    u = torch.zeros_like(f)
-    it, rel, code = S.solve(f, g, u, 1e-17)
-    return {"min_rel_residual": rel, "cycles": it, "status": mg.STATUS.get(code, code)}
+    out = {"reached": None, "not_reached": None}
+    for tol in tols:
+        u = torch.zeros_like(f)
+        it, rel, code = S.solve(f, g, u, tol)
+        if code == 0:
+            out["reached"] = {"tol": tol, "cycles": it, "rel_residual": rel}
+        else:
+            out["not_reached"] = {"tol": tol, "status": mg.STATUS.get(code, code), "cycles": it,
+                                  "last_rel_residual": rel}
+            break
+    return out
 
 
 # --------------------------------------------------------------------------
@@ -213,9 +222,17 @@ def serving_leg(torch, mg, W, geoms, n_rhs, qps, slots, tol, label):
     rng = np.random.default_rng(12345)
     order = rng.permutation(len(reqs))
     gaps = rng.exponential(1.0 / qps, size=len(reqs))
-    seq = {p: [mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=p, max_iters=1000, nu=NU)
-               for P in geoms] for p in (mg.FP64, mg.MIXED)}
-    inputs = [seq[mg.FP64][k].project(P.solution, gauss_points(P.grid.nx)) for k, P in reqs]
+    seq = {}
+    for p in (mg.FP64, mg.MIXED):
+        seq[p] = []
+        for k, P in enumerate(geoms):
+            seq[p].append(mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=p, max_iters=1000, nu=NU))
+            print("%s: setup %d/%d (%d^2, precision %d)" % (label[:24], k + 1, n_geom, P.grid.nx, p),
+                  file=sys.stderr, flush=True)
+    inputs = []
+    for k, P in reqs:
+        inputs.append(seq[mg.FP64][k].project(P.solution, gauss_points(P.grid.nx)))
+    print("%s: %d inputs projected" % (label[:24], len(inputs)), file=sys.stderr, flush=True)
     seq_rate = {}
     for p, name in ((mg.FP64, "fp64"), (mg.MIXED, "mixed")):
         torch.cuda.synchronize()
@@ -225,6 +242,7 @@ def serving_leg(torch, mg, W, geoms, n_rhs, qps, slots, tol, label):
             seq[p][k].solve(f, g, u, tol)
         torch.cuda.synchronize()
         seq_rate[name] = len(reqs) / (time.perf_counter() - t0)
+        print("%s: sequential %s %.1f solves/s" % (label[:24], name, seq_rate[name]), file=sys.stderr, flush=True)
         for S in seq[p]:
             S.close()
     srv = mg.Server(max_active=slots, hbm_budget=64 << 30)
@@ -234,7 +252,10 @@ def serving_leg(torch, mg, W, geoms, n_rhs, qps, slots, tol, label):
     for k in range(n_geom):                        # setup of every hierarchy (not timed)
         f, g = inputs[k * n_rhs]
         warm.append(srv.submit(pids[k], f, g, torch.zeros_like(f), tol))
-    setup_lat = [srv.wait(t)["latency_s"] for t in warm]
+    setup_lat = []
+    for t in warm:
+        setup_lat.append(srv.wait(t)["latency_s"])
+        print("%s: server warm-up %d/%d done" % (label[:24], len(setup_lat), n_geom), file=sys.stderr, flush=True)
     outs = [torch.zeros_like(inputs[i][0]) for i in range(len(reqs))]
     torch.cuda.synchronize()
     tickets = []
@@ -255,6 +276,144 @@ def serving_leg(torch, mg, W, geoms, n_rhs, qps, slots, tol, label):
             "p50_latency_s": pct(0.50), "p99_latency_s": pct(0.99), "solves_per_s": len(reqs) / t_all,
             "sequential_mixed_solves_per_s": seq_rate["mixed"], "sequential_fp64_solves_per_s": seq_rate["fp64"],
             "setup_latency_s_max": max(setup_lat)}
+
+
+def _project_all(torch, mg, probs, threads=4):
+    """Device inputs (f, g) of every problem, each projected with a handle of
+    its own (set up in parallel host threads; the library releases the
+    interpreter during setup)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(P):
+        S = mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, max_iters=1000, nu=NU)
+        fg = S.project(P.solution, gauss_points(P.grid.nx))
+        S.close()
+        return fg
+    out = []
+    with ThreadPoolExecutor(threads) as pool:
+        for k, fg in enumerate(pool.map(one, probs)):
+            out.append(fg)
+            if (k + 1) % 8 == 0:
+                print("projected %d/%d" % (k + 1, len(probs)), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    return out
+
+
+def _run_trace(torch, mg, probs, inputs, pids, srv, rate, seed, tol):
+    """Submits request k (problem pids[k], inputs[k]) at Poisson arrival
+    times of the given rate (rate = inf: all at once); returns the per-request
+    results and the wall time from the first submission to the last result."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=len(probs)) if math.isfinite(rate) else np.zeros(len(probs))
+    outs = [torch.zeros_like(f) for f, _ in inputs]
+    torch.cuda.synchronize()
+    tickets = []
+    t0 = time.perf_counter()
+    for k, gap in enumerate(gaps):
+        if gap > 0:
+            time.sleep(float(gap))
+        f, g = inputs[k]
+        tickets.append(srv.submit(pids[k], f, g, outs[k], tol))
+    res = []
+    for t in tickets:
+        res.append(srv.wait(t))
+        if len(res) % 16 == 0:
+            print("trace: %d/%d done" % (len(res), len(tickets)), file=sys.stderr, flush=True)
+    return res, time.perf_counter() - t0
+
+
+def _latency_summary(res, wall):
+    lat = sorted(r["latency_s"] for r in res)
+    pct = lambda q: lat[min(len(lat) - 1, int(math.ceil(q * len(lat))) - 1)]
+    return {"requests": len(res), "failed": sum(r["status"] != 0 for r in res), "p50_latency_s": pct(0.5),
+            "p99_latency_s": pct(0.99), "solves_per_s": len(res) / wall, "wall_s": wall}
+
+
+def serving_fresh_trace(torch, mg, W, n_req, slots, tol):
+    """Requests of the serving trace, each with a geometry of its own (grids
+    128^2 to 2048^2, 1-5 holes, mixed boundary conditions, seeded a, b, c),
+    so every request pays its setup inside its latency.  First all requests
+    at once (saturation), then Poisson arrivals at 25/50/75/100% of that
+    rate, each trace on a fresh server."""
+    probs = [W.serving_request(0, k) for k in range(n_req)]
+    inputs = _project_all(torch, mg, probs)
+    out = {"workload": "%d requests of serving trace 0 (grids %s), a fresh geometry each; mixed precision, "
+                       "V-cycles nu = (6, 6), to %g; %d slots" % (
+                           n_req, "/".join(sorted({str(P.grid.nx) for P in probs}, key=int)), tol, slots)}
+    rate_sat = None
+    for frac in (None, 0.25, 0.5, 0.75, 1.0):
+        srv = mg.Server(max_active=slots, hbm_budget=128 << 30)
+        pids = [srv.add_problem(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=mg.MIXED, max_iters=1000,
+                                nu=NU) for P in probs]
+        rate = float("inf") if frac is None else frac * rate_sat
+        res, wall = _run_trace(torch, mg, probs, inputs, pids, srv, rate, 100 + int(100 * (frac or 0)), tol)
+        srv.close()
+        summ = _latency_summary(res, wall)
+        if frac is None:
+            rate_sat = summ["solves_per_s"]
+            out["saturation"] = summ
+        else:
+            summ["offered_qps"] = rate
+            out["qps_%d%%" % int(100 * frac)] = summ
+        print("fresh trace %s: %s" % (frac, summ), file=sys.stderr, flush=True)
+    return out
+
+
+def serving_resident(torch, mg, W, n_geom, n_rhs, slots, tol, budget):
+    """n_geom seeded 2048^2 geometries (stars and disks, mixed boundary
+    conditions), each receiving n_rhs right-hand sides in a seeded random
+    order at Poisson arrivals of 80% of the saturation rate; hierarchies stay
+    resident within an HBM budget; against the same solves one after another
+    in FP64 on resident hierarchies."""
+    import numpy as np
+    geoms = [W.serving_geometry(s, 2048) for s in range(n_geom)]
+    probs = [W.with_solution(G, 1000 * k + r, 6) for k, G in enumerate(geoms) for r in range(n_rhs)]
+    owner = [k for k in range(n_geom) for _ in range(n_rhs)]
+    order = np.random.default_rng(77).permutation(len(probs))
+    probs = [probs[i] for i in order]
+    owner = [owner[i] for i in order]
+    inputs = _project_all(torch, mg, probs)
+    # sequential FP64 reference on resident hierarchies
+    seq = [mg.Solver(G.grid, G.curves, G.a, G.b, G.c, eps=G.eps, precision=mg.FP64, max_iters=1000, nu=NU)
+           for G in geoms]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k, (f, g) in zip(owner, inputs):
+        u = torch.zeros_like(f)
+        seq[k].solve(f, g, u, tol)
+    torch.cuda.synchronize()
+    seq_rate = len(probs) / (time.perf_counter() - t0)
+    for S in seq:
+        S.close()
+    print("resident: sequential FP64 %.1f solves/s" % seq_rate, file=sys.stderr, flush=True)
+    srv = mg.Server(max_active=slots, hbm_budget=budget)
+    gp = [srv.add_problem(G.grid, G.curves, G.a, G.b, G.c, eps=G.eps, precision=mg.MIXED, max_iters=1000, nu=NU)
+          for G in geoms]
+    pids = [gp[k] for k in owner]
+    # warm-up: one request per geometry sets the hierarchies up (not timed)
+    first = {}
+    for i, k in enumerate(owner):
+        first.setdefault(k, i)
+    warm = [srv.submit(gp[k], inputs[i][0], inputs[i][1], torch.zeros_like(inputs[i][0]), tol)
+            for k, i in sorted(first.items())]
+    for t in warm:
+        srv.wait(t)
+    res, wall = _run_trace(torch, mg, probs, inputs, pids, srv, float("inf"), 5, tol)
+    sat = len(res) / wall
+    res, wall = _run_trace(torch, mg, probs, inputs, pids, srv, 0.8 * sat, 6, tol)
+    st = srv.stats()
+    srv.close()
+    summ = _latency_summary(res, wall)
+    summ.update({"workload": "%d seeded 2048^2 geometries (stars and disks, mixed boundary conditions), %d "
+                             "right-hand sides each in a random order, Poisson arrivals at 80%% of the saturation "
+                             "rate (%.1f solves/s); hierarchies resident within a %.0f GiB budget; mixed "
+                             "precision, V-cycles nu = (6, 6), to %g; %d slots" % (
+                                 n_geom, n_rhs, sat, budget / 2 ** 30, tol, slots),
+                 "sequential_fp64_solves_per_s": seq_rate, "resident_bytes": st["resident_bytes"],
+                 "evictions": st["evictions"]})
+    print("resident: %s" % summ, file=sys.stderr, flush=True)
+    return summ
 
 
 def solve_leg(torch, mg, P, steps, warmup, tol, timing_solves, label):
@@ -297,12 +456,18 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--timing-solves", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=8.0)
-    ap.add_argument("--cpu-n", type=int, default=1024)
+    ap.add_argument("--cpu-n", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the 1024^2 three-disk line")
+    ap.add_argument("--no-floor", action="store_true", help="skip the FP64 floor measurement")
     ap.add_argument("--only-headline", action="store_true", help="the 4096^2 star line only")
+    ap.add_argument("--serving-traces", action="store_true",
+                    help="run only the serving traces with fresh geometries and with resident 2048^2 geometries")
+    ap.add_argument("--trace-requests", type=int, default=64)
+    ap.add_argument("--resident-geometries", type=int, default=16)
+    ap.add_argument("--resident-rhs", type=int, default=8)
     ap.add_argument("--cpu-baseline-worker", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--cpu-iters", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--cpu-cells", type=int, default=0, help=argparse.SUPPRESS)
@@ -335,6 +500,12 @@ def main():
         print("calibration copy: 3 + 3 x %d bytes read and written" % (src_t.numel() * 8), file=sys.stderr)
         del src_t, dst_t
 
+    if args.serving_traces:
+        out = {"serving_fresh": serving_fresh_trace(torch, mg, W, args.trace_requests, 4, args.tol),
+               "serving_resident": serving_resident(torch, mg, W, args.resident_geometries, args.resident_rhs, 4,
+                                                    args.tol, 64 << 30)}
+        print(json.dumps(out))
+        return
     P = W.star_config(0, 4096)
     head, S32, S64, f, g, dt32, it64, (launches, avg_ms) = solve_leg(
         torch, mg, P, args.steps, args.warmup, args.tol, args.timing_solves, "star 4096")
@@ -359,10 +530,13 @@ def main():
     }
     out.update(head)
     out["roofline"] = roofline(S32, avg_ms, launches, load_traffic_for("star4096", "k_smooth_tiles_fp32"))
-    out["fp64_floor"] = fp64_floor(torch, S64, f, g, 60)
-    print("fp64 floor: %s" % out["fp64_floor"], file=sys.stderr, flush=True)
     S32.close()
     S64.close()
+    if not args.no_floor:
+        Sf = mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=mg.FP64, max_iters=60, nu=NU)
+        out["fp64_floor"] = fp64_floor(torch, Sf, f, g)
+        Sf.close()
+        print("fp64 floor: %s" % out["fp64_floor"], file=sys.stderr, flush=True)
     if not args.no_variants and not args.only_headline:
         # the same solve with the FMG cycle, fewer sweeps, and the
         # multicolour smoother

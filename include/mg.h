@@ -12,8 +12,8 @@
  *    top, left), each carrying the boundary condition of that side
  *    (Dirichlet, Neumann or Robin; the Robin ghost cells are the degree-4
  *    reconstruction of Section 4.1 with the Robin condition at the face).
- *    curves[1..] are holes made of line segments
- *    and circular arcs, closed, clockwise (Omega on the left, Section 2),
+ *    curves[1..] are holes made of line segments, circular arcs and cubic
+ *    Bezier pieces, closed, clockwise (Omega on the left, Section 2),
  *    strictly inside the box.
  *  - Cell arrays (f, u, b, r) are row-major with a halo of 2 cells on each
  *    side: cell (i, j), 0 <= i < nx, 0 <= j < ny, lives at index
@@ -62,14 +62,16 @@ typedef enum {
 } mg_status;
 
 typedef enum { MG_BC_DIRICHLET = 0, MG_BC_NEUMANN = 1, MG_BC_ROBIN = 2 } mg_bc;
-typedef enum { MG_SEG_LINE = 0, MG_SEG_ARC = 1 } mg_seg_kind;
+typedef enum { MG_SEG_LINE = 0, MG_SEG_ARC = 1, MG_SEG_CUBIC = 2 } mg_seg_kind;
 
 /* One boundary segment.  LINE: p = {x0, y0, x1, y1}; ARC: p = {cx, cy, r,
- * theta0, theta1} with signed sweep theta1 - theta0.  bc with the Robin
- * coefficients: N u = alpha1 u + alpha2 du/dn (eq. (1.2)). */
+ * theta0, theta1} with signed sweep theta1 - theta0; CUBIC: a cubic Bezier
+ * piece (the spline boundaries of Section 2), p = {x0, y0, x1, y1, x2, y2,
+ * x3, y3} its control points.  bc with the Robin coefficients: N u =
+ * alpha1 u + alpha2 du/dn (eq. (1.2)).  Unused entries of p are ignored. */
 typedef struct {
     int kind;
-    double p[5];
+    double p[8];
     int bc;
     double alpha1, alpha2;
 } mg_segment;
@@ -113,6 +115,12 @@ typedef struct {
      * every level with separators). */
     long long split_cells, small_cells;
     int split_b_sep;
+    /* Partition of the PLG block solve (0 = the library's choice): hole
+     * chains of at most seg_whole PLG cells are solved by one dense inverse
+     * (default 768); longer chains are cut into segments of at most seg_max
+     * cells (32..768, default 256) coupled through separator unknowns.  Any
+     * partition solves A22 exactly; it changes the rounding and the timing. */
+    int seg_max, seg_whole;
 } mg_options;
 
 typedef struct {
@@ -157,7 +165,8 @@ mg_status mg_setup(const mg_grid *grid, int n_curves, const mg_curve *curves,
  * in MG_MIXED precision an FP32 V-cycle on the FP64 residual, added in FP64)
  * until ||b - A u||_inf <= tol ||b||_inf or max_iters.  u_dev is the initial
  * guess on entry and the solution on exit.  *iters and *rel_residual are
- * written on MG_OK and on MG_ERR_NO_CONVERGENCE. */
+ * written on MG_OK, MG_ERR_NO_CONVERGENCE and MG_ERR_DIVERGED (the residual
+ * grew three times in a row or is not finite; u holds the last iterate). */
 mg_status mg_solve(mg_handle h, const double *f_dev, const double *g_dev, double *u_dev,
                    double tol, void *stream, int *iters, double *rel_residual);
 

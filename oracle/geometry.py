@@ -8,8 +8,9 @@ and the connected components of a cut cell.  Section 3.2 (Algorithm 1) merges
 extra components and small cells into neighbours.
 
 The outer boundary must be the grid box itself (grid-aligned, handled by ghost
-cells, Section 4.1); holes are closed curves of line segments and circular
-arcs strictly inside the box, oriented with Omega on their left.
+cells, Section 4.1); holes are closed curves of line segments, circular arcs and
+cubic Bezier pieces (the spline boundaries of Section 2) strictly inside the
+box, oriented with Omega on their left.
 
 Each cut cell is built from its boundary: the pieces of hole curves inside the
 cell ("runs", each entering and leaving through the cell edges) and the pieces
@@ -19,8 +20,10 @@ so runs and perimeter pieces close into loops; each loop bounds one connected
 component.  Areas and monomial moments follow from Green's theorem,
     ∬ X^a Y^b dX dY = ∮ X^(a+1)/(a+1) Y^b dY,
 in the scaled coordinates X = (x - x_c)/h, Y = (y - y_c)/h about the cell
-centre (x_c, y_c).  Line pieces are integrated exactly by Gauss-Legendre, arcs
-by 16-point Gauss-Legendre in the angle.
+centre (x_c, y_c).  Line pieces are integrated exactly by Gauss-Legendre,
+cubic pieces exactly by 16-point Gauss-Legendre (the integrand is a
+polynomial of degree <= 17 in t), arcs by 16-point Gauss-Legendre in the
+angle.
 """
 from __future__ import annotations
 
@@ -44,11 +47,21 @@ class GeometryError(Exception):
 # ----------------------------------------------------------------------------
 # segments
 # ----------------------------------------------------------------------------
+def _bezier(seg):
+    """Control points of a cubic Bezier segment, p = (x0, y0, ..., x3, y3)."""
+    return np.asarray(seg.p[:8], float).reshape(4, 2)
+
+
 def seg_point(seg, t):
     t = np.asarray(t, float)
     if seg.kind == "line":
         x0, y0, x1, y1 = seg.p
         return x0 + t * (x1 - x0), y0 + t * (y1 - y0)
+    if seg.kind == "cubic":
+        P = _bezier(seg)
+        u = 1.0 - t
+        b = [u * u * u, 3 * u * u * t, 3 * u * t * t, t * t * t]
+        return (sum(b[k] * P[k, 0] for k in range(4)), sum(b[k] * P[k, 1] for k in range(4)))
     cx, cy, r, t0, t1 = seg.p
     th = t0 + t * (t1 - t0)
     return cx + r * np.cos(th), cy + r * np.sin(th)
@@ -59,6 +72,12 @@ def seg_deriv(seg, t):
     if seg.kind == "line":
         x0, y0, x1, y1 = seg.p
         return np.full(t.shape, x1 - x0), np.full(t.shape, y1 - y0)
+    if seg.kind == "cubic":
+        P = _bezier(seg)
+        u = 1.0 - t
+        d = [3 * u * u, 6 * u * t, 3 * t * t]
+        return (sum(d[k] * (P[k + 1, 0] - P[k, 0]) for k in range(3)),
+                sum(d[k] * (P[k + 1, 1] - P[k, 1]) for k in range(3)))
     cx, cy, r, t0, t1 = seg.p
     th = t0 + t * (t1 - t0)
     d = t1 - t0
@@ -83,6 +102,36 @@ def _line_params(seg, coord, value):
             return []
         t = (value - a) / (b - a)
         return [t] if -1e-15 < t < 1 + 1e-15 else []
+    if seg.kind == "cubic":
+        # B(t) - value as a polynomial in t (power basis), its real roots,
+        # each polished by Newton steps
+        c = _bezier(seg)[:, coord]
+        poly = np.array([-c[0] + 3 * c[1] - 3 * c[2] + c[3], 3 * c[0] - 6 * c[1] + 3 * c[2],
+                         -3 * c[0] + 3 * c[1], c[0] - value])
+        scale = np.abs(c).max() + abs(value)
+        while len(poly) > 1 and abs(poly[0]) <= 1e-14 * scale:
+            poly = poly[1:]
+        if len(poly) == 1:
+            if abs(poly[0]) <= 1e-14 * scale:
+                raise GeometryError("segment lies on a grid line")
+            return []
+        dpoly = np.polyder(poly)
+        out = []
+        for z in np.roots(poly):
+            if abs(z.imag) > 1e-7:
+                continue
+            t = float(z.real)
+            for _ in range(4):
+                d = float(np.polyval(dpoly, t))
+                if d == 0.0:
+                    break
+                t -= float(np.polyval(poly, t)) / d
+            if -1e-15 < t < 1 + 1e-15:
+                if abs(float(np.polyval(dpoly, t))) < 1e-9 * scale:
+                    raise GeometryError("cubic segment tangent to a grid line")
+                if not any(abs(t - q) < 1e-13 for q in out):
+                    out.append(t)
+        return sorted(out)
     cx, cy, r, t0, t1 = seg.p
     cc = cx if coord == 0 else cy
     q = (value - cc) / r
@@ -256,6 +305,8 @@ class CutGrid:
             ncross = 0
             for si, seg in enumerate(curve):
                 xs, ys = seg_point(seg, np.linspace(0, 1, 65))
+                if seg.kind == "cubic":            # the control polygon bounds the curve
+                    xs, ys = np.append(xs, _bezier(seg)[:, 0]), np.append(ys, _bezier(seg)[:, 1])
                 kx = range(max(0, int(math.floor((xs.min() - g.x0) / h)) - 1),
                            min(nx, int(math.ceil((xs.max() - g.x0) / h)) + 1) + 1)
                 ky = range(max(0, int(math.floor((ys.min() - g.y0) / h)) - 1),

@@ -31,7 +31,7 @@ class MGError(RuntimeError):
 
 
 class mg_segment(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int), ("p", ctypes.c_double * 5), ("bc", ctypes.c_int),
+    _fields_ = [("kind", ctypes.c_int), ("p", ctypes.c_double * 8), ("bc", ctypes.c_int),
                 ("alpha1", ctypes.c_double), ("alpha2", ctypes.c_double)]
 
 
@@ -50,7 +50,7 @@ class mg_options(ctypes.Structure):
                 ("precision", ctypes.c_int), ("max_iters", ctypes.c_int), ("cycle", ctypes.c_int),
                 ("degree", ctypes.c_int), ("w_min", ctypes.c_double), ("colouring", ctypes.c_int),
                 ("split_cells", ctypes.c_longlong), ("small_cells", ctypes.c_longlong),
-                ("split_b_sep", ctypes.c_int)]
+                ("split_b_sep", ctypes.c_int), ("seg_max", ctypes.c_int), ("seg_whole", ctypes.c_int)]
 
 
 class mg_info(ctypes.Structure):
@@ -182,8 +182,8 @@ def _curves(curves):
     for k, curve in enumerate(curves):
         segs = (mg_segment * len(curve))()
         for s, sg in enumerate(curve):
-            segs[s].kind = 0 if sg.kind == "line" else 1
-            for t in range(5):
+            segs[s].kind = {"line": 0, "arc": 1, "cubic": 2}[sg.kind]
+            for t in range(8):
                 segs[s].p[t] = float(sg.p[t]) if t < len(sg.p) else 0.0
             segs[s].bc = BC[sg.bc]
             segs[s].alpha1 = float(sg.alpha1)
@@ -250,7 +250,7 @@ class Solver:
         it = ctypes.c_int()
         rel = ctypes.c_double()
         code = lib().mg_solve(self.h, _ptr(f), _ptr(g), _ptr(u), tol, _stream(), ctypes.byref(it), ctypes.byref(rel))
-        if code not in (MG_OK, -4):
+        if code not in (MG_OK, -4, -5):
             _check(code, "mg_solve")
         return it.value, rel.value, code
 

@@ -334,7 +334,11 @@ void upload_level(mg_handle h, int l, bool last, hipStream_t st) {
     build_plg_plan(L, S, nx, PLG_SLICE, PLG_B_ROWS, PLG_LMAX, PLG_SEP_ROWS, G);
     h->stage[3] += std::chrono::duration<double>(std::chrono::steady_clock::now() - p0).count();
     if (G.hmax > PLG_HMAX || G.lmax > PLG_LMAX || G.kmax > PLG_KMAX || S.nsep > PLG_SMAX)
-        fail(MG_ERR_UNSUPPORTED, "PLG block partition exceeds the LDS staging limits");
+        fail(MG_ERR_UNSUPPORTED, "PLG block partition exceeds the LDS staging limits on level " + std::to_string(l) +
+                                     " (coupled SFV cells " + std::to_string(G.hmax) + "/" + std::to_string(PLG_HMAX) +
+                                     ", group rows " + std::to_string(G.lmax) + "/" + std::to_string(PLG_LMAX) +
+                                     ", separator columns " + std::to_string(G.kmax) + "/" + std::to_string(PLG_KMAX) +
+                                     ", separators " + std::to_string(S.nsep) + "/" + std::to_string(PLG_SMAX) + ")");
     int *grp_start = h->upload(G.grp_start), *hptr = h->upload(G.hptr), *hcell = h->upload(G.hcell);
     int *a21_loc = h->upload(G.a21_loc);
     const PlgBlkA *blk1 = h->upload(G.blk1);
@@ -846,6 +850,8 @@ mg_status mg_default_options(mg_options *opt) {
     opt->split_cells = 0;
     opt->small_cells = 0;
     opt->split_b_sep = 0;
+    opt->seg_max = 0;
+    opt->seg_whole = 0;
     return MG_OK;
 }
 
@@ -864,7 +870,8 @@ mg_status mg_setup(const mg_grid *grid, int n_curves, const mg_curve *curves, do
         (o.precision != MG_FP64 && o.precision != MG_MIXED) || o.n_levels < 0 || o.n_levels > 16 ||
         (o.cycle != MG_CYCLE_V && o.cycle != MG_CYCLE_FMG) || !(o.omega > 0 && o.omega < 2) ||
         !(o.w_min > 0 && o.w_min < 1e6) || (o.colouring != MG_SMOOTH_JACOBI && o.colouring != MG_SMOOTH_MULTICOLOUR) ||
-        o.split_cells < 0 || o.small_cells < -1 || o.split_b_sep < 0)
+        o.split_cells < 0 || o.small_cells < -1 || o.split_b_sep < 0 || o.seg_max < 0 ||
+        (o.seg_max > 0 && (o.seg_max < 32 || o.seg_max > PLG_LMAX)) || o.seg_whole < 0 || o.seg_whole > PLG_LMAX)
         return MG_ERR_INVALID_ARG;
     if (o.degree != 4) {
         g_last_error = "only degree-4 fits (lattices of 15 cells) are built";
@@ -874,9 +881,12 @@ mg_status mg_setup(const mg_grid *grid, int n_curves, const mg_curve *curves, do
         if (curves[k].n_seg < 1 || !curves[k].seg) return MG_ERR_INVALID_ARG;
         for (int s = 0; s < curves[k].n_seg; ++s) {
             const mg_segment &sg = curves[k].seg[s];
-            if ((sg.kind != MG_SEG_LINE && sg.kind != MG_SEG_ARC) || sg.bc < 0 || sg.bc > 2) return MG_ERR_INVALID_ARG;
-            for (double v : sg.p)
-                if (std::isnan(v)) return MG_ERR_INVALID_ARG;
+            if ((sg.kind != MG_SEG_LINE && sg.kind != MG_SEG_ARC && sg.kind != MG_SEG_CUBIC) || sg.bc < 0 ||
+                sg.bc > 2)
+                return MG_ERR_INVALID_ARG;
+            const int np = sg.kind == MG_SEG_LINE ? 4 : sg.kind == MG_SEG_ARC ? 5 : 8;
+            for (int t = 0; t < np; ++t)
+                if (!std::isfinite(sg.p[t])) return MG_ERR_INVALID_ARG;
         }
     }
     auto h = std::make_unique<mg_handle_s>();
@@ -894,7 +904,7 @@ mg_status mg_setup(const mg_grid *grid, int n_curves, const mg_curve *curves, do
                 const mg_segment &sg = curves[k].seg[s];
                 Seg q;
                 q.kind = sg.kind;
-                for (int t = 0; t < 5; ++t) q.p[t] = sg.p[t];
+                for (int t = 0; t < 8; ++t) q.p[t] = sg.kind == MG_SEG_CUBIC || t < 5 ? sg.p[t] : 0.0;
                 q.bc = sg.bc;
                 q.al1 = sg.alpha1;
                 q.al2 = sg.alpha2;
@@ -939,8 +949,9 @@ mg_status mg_setup(const mg_grid *grid, int n_curves, const mg_curve *curves, do
         for (int l = 0; l < nl; ++l) {
             // whole chains as segments when that leaves no separators (one
             // smoother launch per sweep), else short segments
-            build_plg_solver(*h->levels[l], SEG_WHOLE, h->solvers[l]);
-            if (h->solvers[l].nsep > 0) build_plg_solver(*h->levels[l], SEG_MAX, h->solvers[l]);
+            build_plg_solver(*h->levels[l], o.seg_whole > 0 ? o.seg_whole : SEG_WHOLE, h->solvers[l]);
+            if (h->solvers[l].nsep > 0)
+                build_plg_solver(*h->levels[l], o.seg_max > 0 ? o.seg_max : SEG_MAX, h->solvers[l]);
             h->cond_a22[l] = cond1_estimate(*h->levels[l], h->solvers[l]);
         }
         h->stage[3] += std::chrono::duration<double>(std::chrono::steady_clock::now() - s0).count();

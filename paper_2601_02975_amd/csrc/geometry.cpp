@@ -30,6 +30,10 @@ void Seg::point(double t, double &x, double &y) const {
     if (kind == MG_SEG_LINE) {
         x = p[0] + t * (p[2] - p[0]);
         y = p[1] + t * (p[3] - p[1]);
+    } else if (kind == MG_SEG_CUBIC) {
+        const double u = 1.0 - t, b0 = u * u * u, b1 = 3.0 * u * u * t, b2 = 3.0 * u * t * t, b3 = t * t * t;
+        x = b0 * p[0] + b1 * p[2] + b2 * p[4] + b3 * p[6];
+        y = b0 * p[1] + b1 * p[3] + b2 * p[5] + b3 * p[7];
     } else {
         double th = p[3] + t * (p[4] - p[3]);
         x = p[0] + p[2] * std::cos(th);
@@ -41,6 +45,10 @@ void Seg::deriv(double t, double &dx, double &dy) const {
     if (kind == MG_SEG_LINE) {
         dx = p[2] - p[0];
         dy = p[3] - p[1];
+    } else if (kind == MG_SEG_CUBIC) {
+        const double u = 1.0 - t, d0 = 3.0 * u * u, d1 = 6.0 * u * t, d2 = 3.0 * t * t;
+        dx = d0 * (p[2] - p[0]) + d1 * (p[4] - p[2]) + d2 * (p[6] - p[4]);
+        dy = d0 * (p[3] - p[1]) + d1 * (p[5] - p[3]) + d2 * (p[7] - p[5]);
     } else {
         double sw = p[4] - p[3];
         double th = p[3] + t * sw;
@@ -122,8 +130,71 @@ const GL &gl() {
     return g;
 }
 
+// real roots of c3 t^3 + c2 t^2 + c1 t + c0 (leading zeros allowed): the
+// closed forms (trigonometric for three real roots), each polished by
+// Newton steps on the original polynomial
+void real_roots(double c3, double c2, double c1, double c0, double scale, std::vector<double> &r) {
+    r.clear();
+    if (std::fabs(c3) <= 1e-14 * scale) {
+        if (std::fabs(c2) <= 1e-14 * scale) {
+            if (std::fabs(c1) > 1e-14 * scale) r.push_back(-c0 / c1);
+            return;
+        }
+        const double disc = c1 * c1 - 4.0 * c2 * c0;
+        if (disc < 0.0) {
+            if (disc > -1e-24 * scale * scale) r.push_back(-c1 / (2.0 * c2));
+            return;
+        }
+        const double q = -0.5 * (c1 + std::copysign(std::sqrt(disc), c1));
+        r.push_back(q / c2);
+        if (q != 0.0) r.push_back(c0 / q);
+    } else {
+        const double a = c2 / c3, b = c1 / c3, c = c0 / c3;
+        const double Q = (a * a - 3.0 * b) / 9.0, R = (2.0 * a * a * a - 9.0 * a * b + 27.0 * c) / 54.0;
+        if (R * R < Q * Q * Q) {
+            const double th = std::acos(std::max(-1.0, std::min(1.0, R / std::sqrt(Q * Q * Q))));
+            const double m = -2.0 * std::sqrt(Q);
+            for (int k = 0; k < 3; ++k) r.push_back(m * std::cos((th + 2.0 * M_PI * (k - 1)) / 3.0) - a / 3.0);
+        } else {
+            const double A = -std::copysign(std::cbrt(std::fabs(R) + std::sqrt(R * R - Q * Q * Q)), R);
+            const double B = A != 0.0 ? Q / A : 0.0;
+            r.push_back(A + B - a / 3.0);
+        }
+    }
+    for (double &t : r)
+        for (int it = 0; it < 4; ++it) {
+            const double f = ((c3 * t + c2) * t + c1) * t + c0, d = (3.0 * c3 * t + 2.0 * c2) * t + c1;
+            if (d == 0.0) break;
+            t -= f / d;
+        }
+}
+
 // parameters t in (0,1) where coordinate `coord` of seg equals value
 void line_params(const Seg &s, int coord, double value, std::vector<double> &out) {
+    if (s.kind == MG_SEG_CUBIC) {
+        const double q0 = s.p[coord], q1 = s.p[2 + coord], q2 = s.p[4 + coord], q3 = s.p[6 + coord];
+        const double c3 = -q0 + 3.0 * q1 - 3.0 * q2 + q3, c2 = 3.0 * q0 - 6.0 * q1 + 3.0 * q2;
+        const double c1 = -3.0 * q0 + 3.0 * q1, c0 = q0 - value;
+        const double scale = std::max(std::max(std::fabs(q0), std::fabs(q1)), std::max(std::fabs(q2), std::fabs(q3))) +
+                             std::fabs(value);
+        if (std::fabs(c3) <= 1e-14 * scale && std::fabs(c2) <= 1e-14 * scale && std::fabs(c1) <= 1e-14 * scale) {
+            if (std::fabs(c0) <= 1e-14 * scale) fail(MG_ERR_GEOMETRY, "segment lies on a grid line");
+            return;
+        }
+        std::vector<double> r;
+        real_roots(c3, c2, c1, c0, scale, r);
+        std::sort(r.begin(), r.end());
+        size_t first = out.size();
+        for (double t : r) {
+            if (!(t > -1e-15 && t < 1.0 + 1e-15)) continue;
+            const double d = (3.0 * c3 * t + 2.0 * c2) * t + c1;
+            if (std::fabs(d) < 1e-9 * scale) fail(MG_ERR_GEOMETRY, "cubic segment tangent to a grid line");
+            bool dup = false;
+            for (size_t k = first; k < out.size(); ++k) dup = dup || std::fabs(out[k] - t) < 1e-13;
+            if (!dup) out.push_back(t);
+        }
+        return;
+    }
     if (s.kind == MG_SEG_LINE) {
         double a = coord == 0 ? s.p[0] : s.p[1];
         double b = coord == 0 ? s.p[2] : s.p[3];
@@ -262,6 +333,11 @@ void build_cutgrid(const Curves &cv, const mg_grid &g, double eps, CutGrid &cg) 
                 xmin = std::min(xmin, x); xmax = std::max(xmax, x);
                 ymin = std::min(ymin, y); ymax = std::max(ymax, y);
             }
+            if (s.kind == MG_SEG_CUBIC)            // the control polygon bounds the curve
+                for (int k = 0; k < 4; ++k) {
+                    xmin = std::min(xmin, s.p[2 * k]); xmax = std::max(xmax, s.p[2 * k]);
+                    ymin = std::min(ymin, s.p[2 * k + 1]); ymax = std::max(ymax, s.p[2 * k + 1]);
+                }
             int kx0 = std::max(0, (int)std::floor((xmin - g.x0) / h) - 1);
             int kx1 = std::min(nx, (int)std::ceil((xmax - g.x0) / h) + 1);
             int ky0 = std::max(0, (int)std::floor((ymin - g.y0) / h) - 1);

@@ -326,9 +326,21 @@ template <typename T, bool MIXED, int TYv>
 __device__ __forceinline__ void multicolour_tile(const LevelArgs &L, const T *__restrict__ uold,
                                                  const T *__restrict__ b, T *__restrict__ unew,
                                                  const uint8_t *__restrict__ mask, bool uzero, int i0, int j0,
-                                                 T (*s)[HX], double *gws) {
+                                                 T (*s)[HX], T (*bs)[TX], uint8_t (*ms)[TX], double *gws) {
     constexpr int NC = MIXED ? 9 : 3, MULT = MIXED ? 3 : 1;
     constexpr int PER_ROW = (TX + NC - 1) / NC;          // cells of one colour per tile row, at most
+    constexpr int R = TYv / (NT / TX);
+    // b and the class bytes of the tile, row-coalesced, into LDS
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int gi = i0 + tx;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int r = ty * R + k, gj = j0 + r;
+        const bool in = gi < L.nx && gj < L.ny;
+        const size_t id = pidx(L, in ? gi : 0, in ? gj : 0);
+        ms[r][tx] = in ? mask[id] : (uint8_t)0;
+        bs[r][tx] = b[id];
+    }
     auto uat = [&](int a, int c) { return uzero ? (T)0 : uold[pidx(L, a, c)]; };
     load_tile<T, decltype(uat), TYv>(s, gws, uat, L, i0, j0);
     __syncthreads();
@@ -336,20 +348,21 @@ __device__ __forceinline__ void multicolour_tile(const LevelArgs &L, const T *__
     for (int k = 0; k < NC; ++k) {
         for (int q = threadIdx.x; q < TYv * PER_ROW; q += NT) {
             const int r = q / PER_ROW, m = q - r * PER_ROW;
-            const int j = j0 + r;
-            int c0 = (k - i0 - MULT * j) % NC;
+            int c0 = (k - i0 - MULT * (j0 + r)) % NC;
             if (c0 < 0) c0 += NC;
-            const int lx = c0 + NC * m, i = i0 + lx;
-            if (lx >= TX || i >= L.nx || j >= L.ny) continue;
-            const size_t id = pidx(L, i, j);
-            if (mask[id] != 1) continue;
+            const int lx = c0 + NC * m;
+            if (lx >= TX || ms[r][lx] != 1) continue;
             const int ly = r + 2, cx = lx + 2;
             const T au = apply_sfv<T, MIXED>(L, [&](int dx, int dy) { return s[ly + dy][cx + dx]; });
-            const T v = s[ly][cx] + wod * (b[id] - au);
-            s[ly][cx] = v;
-            unew[id] = v;
+            s[ly][cx] += wod * (bs[r][lx] - au);
         }
         __syncthreads();
+    }
+    // the updated SFV cells, row-coalesced
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int r = ty * R + k, gj = j0 + r;
+        if (ms[r][tx] == 1) unew[pidx(L, gi, gj)] = s[r + 2][tx + 2];
     }
 }
 
@@ -524,10 +537,13 @@ __global__ __launch_bounds__(NT) void k_smooth_tiles_mc(LevelArgs L, const T *__
                                                         const T *__restrict__ b, T *__restrict__ unew,
                                                         const uint8_t *__restrict__ mask, int tiles_x, int uzero) {
     __shared__ __align__(16) T smem[(TYv + 4) * HX];
+    __shared__ __align__(16) T bsm[TYv * TX];
+    __shared__ uint8_t msm[TYv * TX];
     __shared__ double gws[32];
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     multicolour_tile<T, MIXED, TYv>(L, uold, b, unew, mask, uzero != 0, (t % tiles_x) * TX, (t / tiles_x) * TYv,
-                                    reinterpret_cast<T(*)[HX]>(smem), gws);
+                                    reinterpret_cast<T(*)[HX]>(smem), reinterpret_cast<T(*)[TX]>(bsm),
+                                    reinterpret_cast<uint8_t(*)[TX]>(msm), gws);
 }
 
 // Launch B: r_S = t_S - A_SB y (every block forms all of it in LDS), then
@@ -656,65 +672,91 @@ __global__ __launch_bounds__(NT) void k_restrict(LevelArgs L, LevelArgs C, int t
         if (uc) uc[ex_target[t]] = 0;
         return;
     }
+    // the tile's fine cells: each thread owns R consecutive rows of one
+    // column and slides a 5 x 5 window down it (as in the smoother); pairs of
+    // rows are summed in registers, pairs of columns across neighbouring
+    // lanes, and the even lanes write the coarse cells
     const int tile = xcd_tile(blockIdx.x, ntile);
-    const int bx = tile % tiles_x, by = tile / tiles_x;
-    const int i0 = bx * TX, j0 = by * TY;
-    constexpr int NC = (TX / 2) * (TY / 2) / NT;      // coarse cells per thread
-    uint8_t ck[NC], fk[NC][4];
-    T fb[NC][4];
+    const int i0 = (tile % tiles_x) * TX, j0 = (tile / tiles_x) * TY;
+    constexpr int R = TY / (NT / TX);
+    static_assert(R % 2 == 0, "rows per thread come in pairs");
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int i = i0 + tx, r0 = ty * R;
+    const bool col_in = i < L.nx;
+    uint8_t mk[R];
+    T bv[R];
 #pragma unroll
-    for (int n = 0; n < NC; ++n) {
-        const int t = threadIdx.x + n * NT;
-        const int ci = bx * (TX / 2) + t % (TX / 2), cj = by * (TY / 2) + t / (TX / 2);
-        const bool cin = ci < C.nx && cj < C.ny;
-        ck[n] = cin ? rmask[pidx(C, ci, cj)] : 0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int fi = 2 * ci + (q & 1), fj = 2 * cj + (q >> 1);
-            const bool fin = cin && fi < L.nx && fj < L.ny;
-            const size_t id = pidx(L, fin ? fi : 0, fin ? fj : 0);
-            fk[n][q] = fin ? mask[id] : 0;
-            fb[n][q] = b[id];
-        }
+    for (int k = 0; k < R; ++k) {
+        const int j = j0 + r0 + k;
+        const bool in = col_in && j < L.ny;
+        const size_t id = pidx(L, in ? i : 0, in ? j : 0);
+        mk[k] = in ? mask[id] : (uint8_t)0;
+        bv[k] = b[id];
     }
+    T res[R];
     if (RESID) {
         load_tile<T>(s, gws, [&](int a, int c) { return u[pidx(L, a, c)]; }, L, i0, j0);
         __syncthreads();
-    }
+        const int lx = tx + 2;
+        T w[5][5];
 #pragma unroll
-    for (int n = 0; n < NC; ++n) {
-        const int t = threadIdx.x + n * NT;
-        const int ci = bx * (TX / 2) + t % (TX / 2), cj = by * (TY / 2) + t / (TX / 2);
-        if (ci >= C.nx || cj >= C.ny || ck[n] == 2) continue;
-        const size_t cid = pidx(C, ci, cj);
-        if (uc) uc[cid] = 0;
-        T sum = 0;
-        if (ck[n]) {
+        for (int a = 1; a < 5; ++a)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int fi = 2 * ci + (q & 1), fj = 2 * cj + (q >> 1);
-                if (!RESID) {
-                    if (fk[n][q]) sum += fb[n][q];
-                } else if (fk[n][q] == 1) {
-                    const int lx = fi - i0 + 2, ly = fj - j0 + 2;
-                    sum += fb[n][q] - apply_sfv<T, MIXED>(L, [&](int dx, int dy) { return s[ly + dy][lx + dx]; });
-                } else if (fk[n][q] == 2 && rplg) {
-                    sum += rplg[plgidx[pidx(L, fi, fj)]];
-                }
-            }
+            for (int c = 0; c < 5; ++c) w[a][c] = s[r0 + a - 1][lx - 2 + c];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 5; ++c) w[a][c] = w[a + 1][c];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) w[4][c] = s[r0 + k + 4][lx - 2 + c];
+            res[k] = (T)0;
+            if (mk[k] == 1)
+                res[k] = bv[k] - apply_sfv<T, MIXED>(L, [&](int dx, int dy) { return w[dy + 2][dx + 2]; });
+            else if (mk[k] == 2 && rplg)
+                res[k] = rplg[plgidx[pidx(L, i, j0 + r0 + k)]];
         }
-        bc[cid] = (T)0.25 * sum;
+    } else {
+#pragma unroll
+        for (int k = 0; k < R; ++k) res[k] = mk[k] ? bv[k] : (T)0;
+    }
+    const int ci = i >> 1;
+#pragma unroll
+    for (int k = 0; k < R; k += 2) {
+        const T pair = res[k] + res[k + 1];
+        const T other = __shfl_xor(pair, 1, 64);
+        const int cj = (j0 + r0 + k) >> 1;
+        if ((tx & 1) || ci >= C.nx || cj >= C.ny) continue;
+        const size_t cid = pidx(C, ci, cj);
+        const uint8_t ck = rmask[cid];
+        if (ck == 2) continue;                      // cells with extra children: the list blocks
+        if (uc) uc[cid] = 0;
+        bc[cid] = ck ? (T)0.25 * (pair + other) : (T)0;
     }
 }
 
 // Piecewise-constant interpolation and correction, eq. (5.9) (SET: the
-// interpolant itself, as FMG starts a V-cycle from it): blocks
-// [0, nmain) cover the fine rows; the rest handle the fine cells whose coarse
-// parent was merged away (they take the value of the absorbing cell).
+// interpolant itself, as FMG starts a V-cycle from it).  Blocks [0, nmain)
+// take one coarse cell per thread and its 2 x 2 fine children with one
+// 2-element vector access per fine row (the children of a coarse cell start
+// at an even padded index); the rest handle the fine cells whose coarse
+// parent was merged away (they take the value of the absorbing cell).  A
+// coarse cell that is not active leaves its children to those blocks, so
+// its thread touches only the inactive children (SET) or nothing.
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<float> { using V = float2; };
+template <>
+struct Vec2<double> { using V = double2; };
+
 template <typename T, bool SET>
-__global__ void k_prolong(LevelArgs L, LevelArgs C, int bx_per_row, int nmain, const uint8_t *__restrict__ mask,
-                          const uint8_t *__restrict__ cmask, const T *__restrict__ ec, T *__restrict__ u, int nex,
-                          const int *__restrict__ ex_fine, const int *__restrict__ ex_coarse) {
+__global__ __launch_bounds__(256) void k_prolong(LevelArgs L, LevelArgs C, int nmain,
+                                                 const uint8_t *__restrict__ mask, const uint8_t *__restrict__ cmask,
+                                                 const T *__restrict__ ec, T *__restrict__ u, int nex,
+                                                 const int *__restrict__ ex_fine, const int *__restrict__ ex_coarse) {
+    using V = typename Vec2<T>::V;
     if ((int)blockIdx.x >= nmain) {
         const int k = (blockIdx.x - nmain) * blockDim.x + threadIdx.x;
         if (k < nex) {
@@ -723,16 +765,31 @@ __global__ void k_prolong(LevelArgs L, LevelArgs C, int bx_per_row, int nmain, c
         }
         return;
     }
-    const int j = blockIdx.x / bx_per_row;
-    const int i = (blockIdx.x - j * bx_per_row) * blockDim.x + threadIdx.x;
-    if (i >= L.nx) return;
-    const size_t id = pidx(L, i, j);
-    const size_t cid = pidx(C, i >> 1, j >> 1);
-    if (SET) {
-        if (mask[id] && cmask[cid]) u[id] = ec[cid];
-        else if (!mask[id]) u[id] = 0;
-    } else if (mask[id] && cmask[cid]) {
-        u[id] += ec[cid];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= C.nx * C.ny) return;
+    const int cj = t / C.nx, ci = t - cj * C.nx;
+    const size_t cid = pidx(C, ci, cj);
+    const uint8_t cm = cmask[cid];
+    if (!SET && !cm) return;
+    const T e = cm ? ec[cid] : (T)0;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const size_t id = pidx(L, 2 * ci, 2 * cj + r);
+        const uchar2 m = *reinterpret_cast<const uchar2 *>(mask + id);
+        if (!cm) {                                  // SET only: zero the inactive children
+            if (!m.x) u[id] = (T)0;
+            if (!m.y) u[id + 1] = (T)0;
+            continue;
+        }
+        V v = *reinterpret_cast<const V *>(u + id);
+        if (SET) {
+            v.x = m.x ? e : (T)0;
+            v.y = m.y ? e : (T)0;
+        } else {
+            if (m.x) v.x += e;
+            if (m.y) v.y += e;
+        }
+        *reinterpret_cast<V *>(u + id) = v;
     }
 }
 
@@ -1126,13 +1183,13 @@ void launch_restrict(const LevelArgs &L, const LevelArgs &C, const T *u, const T
 template <typename T>
 void launch_prolong(const LevelArgs &L, const LevelArgs &C, const uint8_t *mask, const uint8_t *cmask, const T *ec,
                     T *u, int nex, const int *ex_fine, const int *ex_coarse, bool set, hipStream_t st) {
-    const int bxr = (L.nx + 255) / 256, nmain = bxr * L.ny;
+    const int nmain = (C.nx * C.ny + 255) / 256;
     const dim3 grid(nmain + (nex + 255) / 256);
     if (set)
-        hipLaunchKernelGGL((k_prolong<T, true>), grid, dim3(256), 0, st, L, C, bxr, nmain, mask, cmask, ec, u, nex,
+        hipLaunchKernelGGL((k_prolong<T, true>), grid, dim3(256), 0, st, L, C, nmain, mask, cmask, ec, u, nex,
                            ex_fine, ex_coarse);
     else
-        hipLaunchKernelGGL((k_prolong<T, false>), grid, dim3(256), 0, st, L, C, bxr, nmain, mask, cmask, ec, u, nex,
+        hipLaunchKernelGGL((k_prolong<T, false>), grid, dim3(256), 0, st, L, C, nmain, mask, cmask, ec, u, nex,
                            ex_fine, ex_coarse);
 }
 

@@ -23,8 +23,8 @@ extern const int MONO_Q[NB];           // exponents of y
 int mono_index(int p, int q);
 
 struct Seg {
-    int kind;        // MG_SEG_LINE / MG_SEG_ARC
-    double p[5];
+    int kind;        // MG_SEG_LINE / MG_SEG_ARC / MG_SEG_CUBIC
+    double p[8];
     int bc;
     double al1, al2;
     void point(double t, double &x, double &y) const;

@@ -25,6 +25,32 @@ namespace {
 
 // closest point of a segment to (px, py): returns squared distance and t
 void closest_on_seg(const Seg &s, double px, double py, double &d2, double &t) {
+    if (s.kind == MG_SEG_CUBIC) {
+        // the nearest of 33 samples, refined by Newton steps on
+        // (B(t) - p) . B'(t) = 0 within [0, 1]
+        double best = 1e300;
+        for (int k = 0; k <= 32; ++k) {
+            double x, y;
+            s.point(k / 32.0, x, y);
+            const double d = (x - px) * (x - px) + (y - py) * (y - py);
+            if (d < best) { best = d; t = k / 32.0; }
+        }
+        for (int it = 0; it < 8; ++it) {
+            double x, y, dx, dy, x2, y2;
+            s.point(t, x, y);
+            s.deriv(t, dx, dy);
+            const double e = 1e-6;
+            s.deriv(std::min(1.0, t + e), x2, y2);
+            const double g = (x - px) * dx + (y - py) * dy;
+            const double gp = dx * dx + dy * dy + (x - px) * (x2 - dx) / e + (y - py) * (y2 - dy) / e;
+            if (gp <= 0.0) break;
+            t = std::min(1.0, std::max(0.0, t - g / gp));
+        }
+        double x, y;
+        s.point(t, x, y);
+        d2 = (x - px) * (x - px) + (y - py) * (y - py);
+        return;
+    }
     if (s.kind == MG_SEG_LINE) {
         double dx = s.p[2] - s.p[0], dy = s.p[3] - s.p[1];
         double L2 = dx * dx + dy * dy;
@@ -97,14 +123,19 @@ void build_plg_solver(const Level &L, int seg_max, PlgSolver &S) {
     S.m = m;
     if (m == 0) return;
     const auto &curves = L.curves->c;
-    // Definition 5.1 ordering
-    struct Key { int curve; double s; int cell; };
+    // Definition 5.1 ordering.  Cells whose closest point is a corner of
+    // the curve (a segment end, as at the sharp tips of a star) share one
+    // curve parameter; they are ordered by the angle of the cell centre
+    // around the corner, swept from the incoming segment's side of Omega to
+    // the outgoing one's, so that the chain stays banded around the corner.
+    struct Key { int curve; double s, s2; int cell; };
     std::vector<Key> keys(m);
     for (int r = 0; r < m; ++r) {
         int cell = L.plg_cells[r];
         double px = L.g.x0 + (cell % nx + 0.5) * L.g.h, py = L.g.y0 + (cell / nx + 0.5) * L.g.h;
-        double best = 1e300;
-        Key k{0, 0.0, cell};
+        double best = 1e300, best_t = 0.0;
+        int best_seg = 0;
+        Key k{0, 0.0, 0.0, cell};
         // PLG cells arise near the holes; the box is grid-aligned (ghost cells)
         for (size_t ci = curves.size() > 1 ? 1 : 0; ci < curves.size(); ++ci)
             for (size_t si = 0; si < curves[ci].size(); ++si) {
@@ -112,10 +143,26 @@ void build_plg_solver(const Level &L, int seg_max, PlgSolver &S) {
                 closest_on_seg(curves[ci][si], px, py, d2, t);
                 if (d2 < best) {
                     best = d2;
+                    best_t = t;
+                    best_seg = (int)si;
                     k.curve = (int)ci;
                     k.s = (si + t) / curves[ci].size();
                 }
             }
+        if (best_t <= 0.0 || best_t >= 1.0) {
+            const auto &cv = curves[k.curve];
+            const int nseg = (int)cv.size();
+            const int sin_ = best_t >= 1.0 ? best_seg : (best_seg + nseg - 1) % nseg;   // incoming segment
+            double ax, ay, dx, dy;
+            cv[sin_].point(1.0, ax, ay);
+            cv[sin_].deriv(1.0, dx, dy);
+            const double nlx = -dy, nly = dx;                       // Omega's side of the incoming segment
+            const double vx = px - ax, vy = py - ay;
+            double cw = -std::atan2(nlx * vy - nly * vx, nlx * vx + nly * vy);
+            if (cw < 0.0) cw += 2.0 * M_PI;
+            k.s = (double)((best_t >= 1.0 ? best_seg + 1 : best_seg) % nseg) / nseg;
+            k.s2 = cw;
+        }
         keys[r] = k;
     }
     std::vector<int> order(m);
@@ -123,6 +170,7 @@ void build_plg_solver(const Level &L, int seg_max, PlgSolver &S) {
     std::sort(order.begin(), order.end(), [&](int a, int b) {
         if (keys[a].curve != keys[b].curve) return keys[a].curve < keys[b].curve;
         if (keys[a].s != keys[b].s) return keys[a].s < keys[b].s;
+        if (keys[a].s2 != keys[b].s2) return keys[a].s2 < keys[b].s2;
         return keys[a].cell < keys[b].cell;
     });
     std::vector<int> pos(m);
@@ -154,21 +202,38 @@ void build_plg_solver(const Level &L, int seg_max, PlgSolver &S) {
             ++nseg;
             continue;
         }
+        // reach[q]: the farthest in-chain coupling of position q (either
+        // direction, wrap-around couplings excluded); a separator run at a
+        // cut only needs to cover the couplings near that cut, so its length
+        // is the largest reach within the global bandwidth w of the cut (a
+        // few corner cells with long couplings, as at the tips of a star,
+        // then lengthen only the runs next to them)
+        std::vector<int> reach(len, 0);
         int w = 1;
         for (int q = ch.first; q < ch.second; ++q)
             for (auto &e : a22[q])
                 if (chain_of[e.first] == chain_of[q]) {
                     int d = std::abs(e.first - q);
-                    if (d < len / 2) w = std::max(w, d);
+                    if (d < len / 2) {
+                        w = std::max(w, d);
+                        reach[q - ch.first] = std::max(reach[q - ch.first], d);
+                        reach[e.first - ch.first] = std::max(reach[e.first - ch.first], d);
+                    }
                 }
-        int seglen = std::max(seg_max - w, 2 * w);
-        int q = ch.first + w;                       // separator at the chain start
+        auto run_at = [&](int e) {                  // separator run length at position e
+            int r = 1;
+            for (int k = std::max(ch.first, e - w); k < std::min(ch.second, e + w); ++k)
+                r = std::max(r, reach[k - ch.first]);
+            return r;
+        };
+        int q = ch.first + run_at(ch.first);        // separator at the chain start
         while (q < ch.second) {
-            int e = std::min(ch.second, q + seglen);
-            if (ch.second - e < seglen / 4) e = ch.second;   // no tiny tail segment
+            int e = std::min(ch.second, q + seg_max - run_at(q + seg_max));
+            e = std::max(e, std::min(ch.second, q + 1));
+            if (ch.second - e < seg_max / 4) e = ch.second;   // no tiny tail segment
             for (int k = q; k < e; ++k) seg_of[k] = nseg;
             ++nseg;
-            q = e + w;                              // next separator run
+            q = e + run_at(e);                      // next separator run
         }
     }
     // any coupling between different segments moves its column to S

@@ -26,10 +26,9 @@ def test_omega_four_fifths_diverges():
     S = mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, omega=0.8)
     f, g = S.project(P.solution)
     u = torch.zeros_like(f)
-    with pytest.raises(mg.MGError) as e:
-        S.solve(f, g, u, 1e-10)
-    print("omega 0.8:", e.value)
-    assert e.value.code == -5
+    it, rel, code = S.solve(f, g, u, 1e-10)
+    print("omega 0.8: code %d after %d iterations, rel %.2e" % (code, it, rel))
+    assert code == -5 and it <= 6 and rel > 1.0
 
 
 @pytest.mark.parametrize("precision", [0, 1])

@@ -33,6 +33,8 @@ CASES = {
     # Robin box sides (face and, with the cross term, corner ghosts)
     "disk_robin_box64": lambda: _robin_box(W.unit_disk_config(0, 64), 1.0, 0.5),
     "square_cross_robin_box32": lambda: _robin_box(W.unit_square_config(32, 1.0, 0.5, 2.0), 2.0, 0.25),
+    # a hole of cubic Bezier pieces (Neumann), with the cross term
+    "bezier96": lambda: W.bezier_config(0, 96),
 }
 
 

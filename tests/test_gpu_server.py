@@ -65,3 +65,32 @@ def test_server_results_equal_alone(budget, precision):
     if budget == 1:
         assert st["evictions"] > 0 and st["resident_problems"] <= 1
     print(st)
+
+
+def test_small_request_overtakes_a_large_setup():
+    """A slot setting up a large new geometry does not hold the other slots:
+    a small request submitted just after it (a new geometry too, so it also
+    sets up and captures its graphs) completes first."""
+    torch = _torch()
+    import paper_2601_02975_amd as mg
+    big = W.three_disks_config(3, 1024)
+    small = W.unit_disk_config(0, 64)
+    Sb = mg.Solver(big.grid, big.curves, big.a, big.b, big.c, eps=big.eps)
+    Ss = mg.Solver(small.grid, small.curves, small.a, small.b, small.c, eps=small.eps)
+    fb, gb = Sb.project(big.solution)
+    fs, gs = Ss.project(small.solution)
+    Sb.close()
+    Ss.close()
+    srv = mg.Server(max_active=2, hbm_budget=64 << 30)
+    pb = srv.add_problem(big.grid, big.curves, big.a, big.b, big.c, eps=big.eps, nu=(6, 6), max_iters=1000)
+    ps = srv.add_problem(small.grid, small.curves, small.a, small.b, small.c, eps=small.eps)
+    tb = srv.submit(pb, fb, gb, torch.zeros_like(fb), 1e-10)
+    ts = srv.submit(ps, fs, gs, torch.zeros_like(fs), 1e-10)
+    rs = srv.wait(ts)
+    done_b = srv.poll(tb)
+    rb = srv.wait(tb)
+    srv.close()
+    print("small request %.3f s, large request (with setup) %.3f s" % (rs["latency_s"], rb["latency_s"]))
+    assert rs["status"] == 0 and rb["status"] == 0
+    assert done_b is None, "the small request waited for the large setup"
+    assert rs["latency_s"] < 0.5 * rb["latency_s"]

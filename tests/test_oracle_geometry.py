@@ -134,3 +134,66 @@ def test_hole_inside_one_cell_is_rejected():
     curves = [W.box_curve(0, 0, 1, 1), W.disk_hole(0.5 + 1 / 16, 0.5 + 1 / 16, 0.02)]
     with pytest.raises(GeometryError):
         CutGrid(grid, curves, 0.08)
+
+
+def _bezier_area_and_moment(curve):
+    """Signed area and first x-moment enclosed by a closed curve of cubic
+    Bezier pieces, by exact polynomial integration of Green's theorem
+    (x dy and x^2/2 dy) in the power basis of each piece's control points."""
+    from numpy.polynomial import polynomial as Pn
+    to_power = np.array([[1, 0, 0, 0], [-3, 3, 0, 0], [3, -6, 3, 0], [-1, 3, -3, 1]], float)
+    area = mom = 0.0
+    for sg in curve:
+        c = np.array(sg.p, float).reshape(4, 2)
+        x, y = to_power @ c[:, 0], to_power @ c[:, 1]
+        dy = Pn.polyder(y)
+        for integrand, acc in ((Pn.polymul(x, dy), "a"), (0.5 * Pn.polymul(Pn.polymul(x, x), dy), "m")):
+            F = Pn.polyint(integrand)
+            v = Pn.polyval(1.0, F) - Pn.polyval(0.0, F)
+            if acc == "a":
+                area += v
+            else:
+                mom += v
+    return area, mom
+
+
+@pytest.mark.parametrize("seed,n", [(0, 64), (1, 128), (2, 96)])
+def test_bezier_hole_volumes_and_first_moment(seed, n):
+    """Cubic Bezier boundary pieces (Section 2's splines): the cut cells
+    partition the unit square minus the hole, whose area and first moment
+    follow exactly from its control points."""
+    P = W.bezier_config(seed, n)
+    cg = CutGrid(P.grid, P.curves, P.eps)
+    h = P.grid.h
+    a_hole, m_hole = _bezier_area_and_moment(P.curves[1])     # clockwise: negative
+    assert cg.volfrac.sum() * h * h == pytest.approx(1.0 + a_hole, abs=1e-13)
+    tot = 0.0
+    jj, ii = np.nonzero(cg.regular)
+    tot += np.sum((ii + 0.5) * h) * h * h
+    kx = MONOS.index((1, 0))
+    for (i, j), d in cg.cells.items():
+        tot += ((i + 0.5) * h * d["mom"][0] + h * d["mom"][kx]) * h * h
+    assert tot == pytest.approx(0.5 + m_hole, abs=1e-13)
+    act = cg.active
+    assert np.all(cg.volfrac[act] >= P.eps - 1e-15)
+
+
+def test_bezier_crossings_are_roots():
+    """Every grid-line crossing of a cubic piece is a root of its coordinate
+    polynomial to rounding, and no crossing is missed (sign changes of the
+    coordinate minus the grid value on a fine sampling)."""
+    from oracle.geometry import _line_params, seg_point
+    P = W.bezier_config(3, 64)
+    h = P.grid.h
+    for sg in P.curves[1]:
+        t = np.linspace(0.0, 1.0, 4001)
+        x, y = seg_point(sg, t)
+        for coord, vals in ((0, x), (1, y)):
+            for k in range(65):
+                v = k * h
+                got = _line_params(sg, coord, v)
+                for tt in got:
+                    xv, yv = seg_point(sg, tt)
+                    assert abs((xv if coord == 0 else yv) - v) <= 1e-14
+                changes = int(np.sum(np.sign(vals[1:] - v) != np.sign(vals[:-1] - v)))
+                assert len(got) == changes

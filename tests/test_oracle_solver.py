@@ -70,6 +70,7 @@ def _robin_box(base, alpha1=1.0, alpha2=0.5):
     (lambda s, n: W.unit_square_config(n, 1.0, 0.5, 2.0), 32, POLY3),
     (lambda s, n: _robin_box(W.unit_disk_config(s, n)), 64, POLY4),
     (lambda s, n: _robin_box(W.unit_square_config(n, 1.0, 0.5, 2.0), 2.0, 0.25), 32, POLY3),
+    (W.bezier_config, 96, POLY3),
 ])
 def test_polynomial_solution_is_exact(maker, n, coeffs):
     """Every row is exact on the polynomials it must reproduce (degree 4 for

@@ -13,8 +13,9 @@ boundary curve is closed and oriented with Omega on its left (Section 2),
 so the box is traversed counter-clockwise and each hole clockwise.
 
 Segment kinds
-  ('line', (x0, y0, x1, y1))
-  ('arc',  (cx, cy, r, theta0, theta1))   signed sweep theta1 - theta0
+  ('line',  (x0, y0, x1, y1))
+  ('arc',   (cx, cy, r, theta0, theta1))   signed sweep theta1 - theta0
+  ('cubic', (x0, y0, x1, y1, x2, y2, x3, y3))   Bezier control points
 Each segment carries its boundary condition: bc in {'D', 'N', 'R'} and the
 Robin coefficients (alpha1, alpha2).  The outward normal of Omega at a point
 with tangent (x', y') is (y', -x') / |(x', y')|.
@@ -224,6 +225,43 @@ def star_hole(cx, cy, R, r_in, phi, npts=8, bc=BC_ROBIN, alpha1=1.0, alpha2=0.5,
     return cw
 
 
+def bezier_hole(cx, cy, rx, ry, phi=0.0, wobble=(0.0, 0.0, 0.0, 0.0), bc=BC_DIRICHLET, alpha1=1.0, alpha2=0.0):
+    """A smooth closed hole made of four cubic Bezier pieces, traversed
+    clockwise: an ellipse-like curve with semi-axes (rx, ry) rotated by phi,
+    whose four on-curve points move radially by the factors (1 + wobble[k])
+    (the tangent handles follow, so the curve stays C1)."""
+    kappa = 0.5522847498307936            # handle length of the usual quarter-circle Bezier
+    pts = []
+    for k in range(4):                     # on-curve points at angles 0, -90, -180, -270 (clockwise)
+        th = -0.5 * math.pi * k
+        f = 1.0 + wobble[k]
+        ex, ey = rx * f * math.cos(th), ry * f * math.sin(th)
+        tx, ty = rx * f * math.sin(th), -ry * f * math.cos(th)      # clockwise tangent
+        rot = lambda x, y: (cx + x * math.cos(phi) - y * math.sin(phi), cy + x * math.sin(phi) + y * math.cos(phi))
+        pts.append((rot(ex, ey), rot(ex + kappa * tx, ey + kappa * ty), rot(ex - kappa * tx, ey - kappa * ty)))
+    segs = []
+    for k in range(4):
+        P0, H0, _ = pts[k]
+        P3, _, H3 = pts[(k + 1) % 4]
+        segs.append(Segment("cubic", (P0[0], P0[1], H0[0], H0[1], H3[0], H3[1], P3[0], P3[1]), bc, alpha1, alpha2))
+    return segs
+
+
+def bezier_config(seed=0, n=128):
+    """[0,1]^2 minus a seeded smooth hole of four cubic Bezier pieces (the
+    spline boundaries of Section 2), Neumann on the hole, Dirichlet box;
+    (a, b, c) = (1, 0.5, 2); 6 sine modes."""
+    rng = np.random.default_rng(seed)
+    rx, ry = (float(v) for v in rng.uniform(0.15, 0.25, size=2))
+    phi = float(rng.uniform(0.0, math.pi))
+    wob = tuple(float(v) for v in rng.uniform(-0.15, 0.15, size=4))
+    cx, cy = (float(v) for v in 0.5 + rng.uniform(-0.05, 0.05, size=2))
+    modes = _modes(rng, 6)
+    curves = [box_curve(0.0, 0.0, 1.0, 1.0), bezier_hole(cx, cy, rx, ry, phi, wob, BC_NEUMANN)]
+    return Problem("bezier%d_seed%d" % (n, seed), Grid(0.0, 0.0, 1.0 / n, n, n), curves, 1.0, 0.5, 2.0,
+                   SineModes(modes, 1.0, 0.5, 2.0), eps=0.08)
+
+
 def _modes(rng, count):
     ks = rng.integers(1, 5, size=(count, 2))
     amps = rng.uniform(-1.0, 1.0, size=count)
@@ -268,8 +306,9 @@ def three_disks_config(seed=0, n=1024):
 
 
 def star_config(seed=0, n=4096):
-    """[0,1]^2 minus a seeded 8-point star joined to circular arcs; a=2, b=-1,
-    c=1; Robin (1, 0.5) on the star, Dirichlet outside; 8 seeded sine modes."""
+    """[0,1]^2 minus a seeded 8-point star whose valleys are circular arcs and
+    whose 8 tips stay sharp corners; a=2, b=-1, c=1; Robin (1, 0.5) on the
+    star, Dirichlet outside; 8 seeded sine modes."""
     rng = np.random.default_rng(seed)
     cx, cy = (0.5 + float(v) for v in rng.uniform(-0.03, 0.03, size=2))
     phi = float(rng.uniform(0.0, math.pi / 4))
@@ -277,7 +316,7 @@ def star_config(seed=0, n=4096):
     r_in = float(rng.uniform(0.14, 0.18))
     modes = _modes(rng, 8)
     a, b, c = 2.0, -1.0, 1.0
-    curves = [box_curve(0.0, 0.0, 1.0, 1.0), star_hole(cx, cy, R, r_in, phi)]
+    curves = [box_curve(0.0, 0.0, 1.0, 1.0), star_hole(cx, cy, R, r_in, phi, round_tips=False)]
     return Problem("star%d" % n, Grid(0.0, 0.0, 1.0 / n, n, n), curves, a, b, c,
                    SineModes(modes, a, b, c), eps=0.08,
                    meta={"seed": seed, "modes": modes, "star": (cx, cy, R, r_in, phi)})
@@ -316,6 +355,30 @@ def with_grid(problem, n):
     L = g.h * g.nx
     return Problem(problem.name, Grid(g.x0, g.y0, L / n, n, n), problem.curves, problem.a,
                    problem.b, problem.c, problem.solution, problem.eps, dict(problem.meta))
+
+
+def serving_geometry(seed, n=2048):
+    """One geometry of the resident-serving workload: a seeded star (its
+    boundary condition uniform over D, N, R) on even seeds, 1-5 seeded disks
+    with mixed boundary conditions on odd seeds; a, c ~ U[0.5, 2],
+    |b| < sqrt(ac); n x n cells."""
+    rng = np.random.default_rng([int(seed), 4099])
+    a = float(rng.uniform(0.5, 2.0)); c = float(rng.uniform(0.5, 2.0))
+    b = float(rng.uniform(-1.0, 1.0)) * math.sqrt(a * c) * 0.95
+    curves = [box_curve(0.0, 0.0, 1.0, 1.0)]
+    if seed % 2 == 0:
+        cx, cy = (0.5 + float(v) for v in rng.uniform(-0.03, 0.03, size=2))
+        phi = float(rng.uniform(0.0, math.pi / 4))
+        R = float(rng.uniform(0.28, 0.32)); r_in = float(rng.uniform(0.14, 0.18))
+        bc = str(rng.choice([BC_DIRICHLET, BC_NEUMANN, BC_ROBIN]))
+        curves.append(star_hole(cx, cy, R, r_in, phi, bc=bc, alpha1=1.0, alpha2=0.5, round_tips=False))
+    else:
+        for (x, y, r) in _disks(rng, int(rng.integers(1, 6))):
+            bc = str(rng.choice([BC_DIRICHLET, BC_NEUMANN, BC_ROBIN]))
+            curves.append(disk_hole(x, y, r, bc, 1.0, 0.5))
+    modes = _modes(rng, 6)
+    return Problem("geom%d_%d" % (seed, n), Grid(0.0, 0.0, 1.0 / n, n, n), curves, a, b, c,
+                   SineModes(modes, a, b, c), eps=0.08)
 
 
 def with_solution(problem, seed, count=6):
