@@ -199,6 +199,19 @@ mg_status mg_prolong(mg_handle h, int level, int precision, const void *ec_dev, 
 mg_status mg_residual(mg_handle h, int level, const double *b_dev, const double *u_dev,
                       double *r_dev, double *rnorm, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops): the residual and its norm of mg_residual,
+ * with the norm written to the device scalar *rnorm_dev instead of the host,
+ * no synchronisation and no allocation of any kind.  The per-block partial
+ * maxima go to a fixed array of 32768 doubles (256 KiB) in device memory that
+ * the library holds on each device for the life of the process (enough for
+ * grids of about 4 x 4096^2 cells); a level that needs more returns
+ * MG_ERR_UNSUPPORTED.  Every call on one device shares that array: calls that
+ * overlap on one device (other streams or threads) race and must be ordered
+ * by the caller.  r_dev may be NULL. */
+mg_status mg_residual_norm_noalloc(mg_handle h, int level, const double *b_dev, const double *u_dev, double *r_dev,
+                                   double *rnorm_dev, void *stream);
+
 mg_status mg_query(mg_handle h, mg_info *info);
 
 /* Host copies of one level's structure: kind[ny*nx] (0 inactive, 1 SFV,

@@ -104,6 +104,7 @@ struct mg_handle_s {
     double tim_total_ms = 0.0;
     std::vector<double> cond_a22;
     double stage[6] = {0, 0, 0, 0, 0, 0};
+    double *scratch = nullptr;           // the device's fixed scratch (mg_residual_norm_noalloc)
 
     template <typename T>
     T *alloc(size_t n) {
@@ -896,6 +897,8 @@ mg_status mg_setup(const mg_grid *grid, int n_curves, const mg_curve *curves, do
         // capture lock; device allocations, copies and the fits take it
         auto t0 = std::chrono::steady_clock::now();
         HIPCHECK(hipGetDevice(&h->device));
+        h->scratch = noalloc_scratch();
+        if (!h->scratch) fail(MG_ERR_HIP, "hipGetSymbolAddress of the fixed scratch failed");
         h->opt = o;
         h->a = a; h->b = b; h->c = c;
         for (int k = 0; k < n_curves; ++k) {
@@ -1076,6 +1079,27 @@ mg_status mg_residual(mg_handle h, int level, const double *b_dev, const double 
     return guard(h, [&]() {
         double v = residual_norm(h, level, u_dev, b_dev, r_dev, (hipStream_t)stream);
         if (rnorm) *rnorm = v;
+    });
+}
+
+mg_status mg_residual_norm_noalloc(mg_handle h, int level, const double *b_dev, const double *u_dev, double *r_dev,
+                                   double *rnorm_dev, void *stream) {
+    if (!h || !b_dev || !u_dev || !rnorm_dev || level < 0 || level >= (int)h->dev.size()) return MG_ERR_INVALID_ARG;
+    DevLevel &D = h->dev[level];
+    const int nb = residual_norm_blocks(D.args, D.m);
+    if (nb > NOALLOC_SCRATCH_DOUBLES) {
+        g_last_error = "mg_residual_norm_noalloc: the level needs " + std::to_string(nb) +
+                       " partial maxima, more than the fixed scratch holds (" +
+                       std::to_string(NOALLOC_SCRATCH_DOUBLES) + ")";
+        return MG_ERR_UNSUPPORTED;
+    }
+    if (!h->scratch) return MG_ERR_HIP;
+    return guard(h, [&]() {
+        hipStream_t st = (hipStream_t)stream;
+        const int n = launch_residual_norm(D.args, u_dev, nullptr, false, nullptr, b_dev, D.mask, D.m, D.plg_cell,
+                                           D.fe_col, D.fe_val, nullptr, r_dev, h->scratch, st);
+        launch_absmax(n, h->scratch, nullptr, rnorm_dev, 1, st);
+        HIPCHECK(hipGetLastError());
     });
 }
 

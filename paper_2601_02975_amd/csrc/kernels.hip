@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
+#include <mutex>
 
 #include "kernels.hpp"
 #include "kernels_launch.hpp"
@@ -1217,6 +1219,31 @@ int launch_residual_norm(const LevelArgs &L, const double *u, const void *e, boo
 #undef MG_RES2
 #undef MG_RES
     return nblk;
+}
+
+int residual_norm_blocks(const LevelArgs &L, int m) {
+    const dim3 tg = tile_grid(L);
+    return (int)(tg.x * tg.y) + (m + NT - 1) / NT;
+}
+
+// Fixed device memory for the entry point that allocates nothing
+// (mg_residual_norm_noalloc): the per-block partial maxima of the residual
+// norm.  Each device holds its own copy for the life of the process; host
+// code must use the address from noalloc_scratch(), never the symbol.
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+
+double *noalloc_scratch() {
+    static std::mutex mu;
+    static std::map<int, double *> addr;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(dev);
+    if (it != addr.end()) return it->second;
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    addr[dev] = (double *)p;
+    return (double *)p;
 }
 
 void launch_absmax(int n, const double *v, const uint8_t *mask, double *partial, int nblocks, hipStream_t st) {

@@ -39,6 +39,13 @@ void launch_bottom(int n, const int *cells, const double *ainv, const TI *b, TO 
 int launch_residual_norm(const LevelArgs &L, const double *u, const void *e, bool e64, double *uout, const double *b,
                          const uint8_t *mask, int m, const int *pcell, const int *fe_col, const double *fe_val,
                          float *r32, double *r64, double *partial, hipStream_t st);
+// number of partial maxima launch_residual_norm writes on a level with m PLG rows
+int residual_norm_blocks(const LevelArgs &L, int m);
+// capacity, in doubles, of the fixed device scratch of the no-allocation
+// entry point; noalloc_scratch() returns its address on the current device
+// (resolved once per device with hipGetSymbolAddress), or null on failure
+constexpr int NOALLOC_SCRATCH_DOUBLES = 32768;
+double *noalloc_scratch();
 void launch_absmax(int n, const double *v, const uint8_t *mask, double *partial, int nblocks, hipStream_t st);
 void launch_rhs(size_t n, const uint8_t *mask, const double *f, double *b, int nrows, const int *ptr, const int *cell,
                 const int *gidx, const double *coef, const double *g, hipStream_t st);
