@@ -232,7 +232,8 @@ def serving_leg(torch, mg, W, geoms, n_rhs, qps, slots, tol, label):
     inputs = []
     for k, P in reqs:
         inputs.append(seq[mg.FP64][k].project(P.solution, gauss_points(P.grid.nx)))
-    print("%s: %d inputs projected" % (label[:24], len(inputs)), file=sys.stderr, flush=True)
+        print("%s: input %d/%d projected (%d^2)" % (label[:24], len(inputs), len(reqs), P.grid.nx),
+              file=sys.stderr, flush=True)
     seq_rate = {}
     for p, name in ((mg.FP64, "fp64"), (mg.MIXED, "mixed")):
         torch.cuda.synchronize()
@@ -293,8 +294,7 @@ def _project_all(torch, mg, probs, threads=4):
     with ThreadPoolExecutor(threads) as pool:
         for k, fg in enumerate(pool.map(one, probs)):
             out.append(fg)
-            if (k + 1) % 8 == 0:
-                print("projected %d/%d" % (k + 1, len(probs)), file=sys.stderr, flush=True)
+            print("projected %d/%d" % (k + 1, len(probs)), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     return out
 
@@ -590,9 +590,9 @@ def main():
             print("serving: p50 %.3f s, p99 %.3f s, %.1f solves/s" % (
                 out["serving"]["p50_latency_s"], out["serving"]["p99_latency_s"], out["serving"]["solves_per_s"]),
                 file=sys.stderr, flush=True)
-            mix = [W.serving_request(0, k) for k in range(8)]
+            mix = [W.serving_request(0, k) for k in range(6)]
             out["serving_mix"] = serving_leg(torch, mg, W, mix, 4, 200.0, 4, args.tol,
-                                             "the first 8 requests of serving trace 0 as geometries (grids %s; "
+                                             "the first 6 requests of serving trace 0 as geometries (grids %s; "
                                              "1-5 holes, mixed boundary conditions, seeded a, b, c)"
                                              % "/".join(str(Q.grid.nx) for Q in mix))
             print("serving mix: p50 %.3f s, p99 %.3f s, %.1f solves/s" % (

@@ -61,7 +61,11 @@ typedef enum {
                                   level too large for the dense bottom solve */
 } mg_status;
 
-typedef enum { MG_BC_DIRICHLET = 0, MG_BC_NEUMANN = 1, MG_BC_ROBIN = 2 } mg_bc;
+/* MG_BC_PERIODIC: box sides only, in opposite pairs (left and right, or
+ * bottom and top; Sec. 4.1): a ghost position beyond such a side is the cell
+ * one period away, and the side carries no data (its entries of g are
+ * ignored). */
+typedef enum { MG_BC_DIRICHLET = 0, MG_BC_NEUMANN = 1, MG_BC_ROBIN = 2, MG_BC_PERIODIC = 3 } mg_bc;
 typedef enum { MG_SEG_LINE = 0, MG_SEG_ARC = 1, MG_SEG_CUBIC = 2 } mg_seg_kind;
 
 /* One boundary segment.  LINE: p = {x0, y0, x1, y1}; ARC: p = {cx, cy, r,

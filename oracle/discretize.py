@@ -237,8 +237,16 @@ class Level:
         sj, si = np.nonzero(self.kind == SFV)
         srow = self.idx[sj, si]
         box_bc = self.cg.box_bc
+        # periodic box sides (Sec. 4.1): a position beyond the box in a
+        # periodic direction is the cell one period away; what is still
+        # outside afterwards takes the ghost formulas of the other sides
+        per_x, per_y = box_bc[1][0] == "P", box_bc[0][0] == "P"
         for (m1, m2), w in terms:
             qi, qj = si + m1, sj + m2
+            if per_x:
+                qi = qi % nx
+            if per_y:
+                qj = qj % ny
             inside = (qi >= 0) & (qi < nx) & (qj >= 0) & (qj < ny)
             rows.append(srow[inside]); cols.append(self.idx[qj[inside], qi[inside]])
             vals.append(np.full(inside.sum(), w))

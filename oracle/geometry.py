@@ -293,6 +293,12 @@ class CutGrid:
                 raise GeometryError("the outer curve must be the counter-clockwise grid box")
         # side order bottom, right, top, left
         self.box_bc = [(s.bc, s.alpha1, s.alpha2) for s in box]
+        # periodic sides come in opposite pairs (Sec. 4.1), and only on the box
+        for a, b in ((0, 2), (1, 3)):
+            if (box[a].bc == "P") != (box[b].bc == "P"):
+                raise GeometryError("periodic box sides must come in opposite pairs")
+        if any(s.bc == "P" for c in self.curves[1:] for s in c):
+            raise GeometryError("periodic conditions apply to box sides only")
 
     # -- crossings, runs, loops -------------------------------------------------
     def _cut(self):

@@ -88,6 +88,8 @@ def cell_averages(level, func):
 
 def _bc_value(seg, sol, x, y, nx, ny):
     u = sol.u(x, y)
+    if seg.bc == "P":                  # periodic box sides carry no data
+        return np.zeros_like(u)
     dn = sol.ux(x, y) * nx + sol.uy(x, y) * ny
     if seg.bc == "D":
         return u

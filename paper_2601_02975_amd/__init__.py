@@ -19,7 +19,7 @@ MG_OK = 0
 STATUS = {0: "MG_OK", -1: "MG_ERR_INVALID_ARG", -2: "MG_ERR_GEOMETRY", -3: "MG_ERR_SINGULAR",
           -4: "MG_ERR_NO_CONVERGENCE", -5: "MG_ERR_DIVERGED", -6: "MG_ERR_OOM", -7: "MG_ERR_HIP",
           -8: "MG_ERR_UNSUPPORTED"}
-BC = {"D": 0, "N": 1, "R": 2}
+BC = {"D": 0, "N": 1, "R": 2, "P": 3}
 FP64, MIXED = 0, 1
 CYCLE_V, CYCLE_FMG = 0, 1
 
@@ -391,7 +391,7 @@ class Solver:
                 bc[sel], a1[sel], a2[sel] = b0, b1, b2
             u = sol.u(x, y)
             dn = sol.ux(x, y) * nx + sol.uy(x, y) * ny
-            return np.where(bc == 0, u, np.where(bc == 1, dn, a1 * u + a2 * dn))
+            return np.where(bc == 0, u, np.where(bc == 1, dn, np.where(bc == 3, 0.0, a1 * u + a2 * dn)))
 
         return self.project_rhs(sol.f, g, gauss_points)
 

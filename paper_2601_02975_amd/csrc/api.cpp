@@ -151,6 +151,7 @@ LevelArgs make_args(const Level &L, const mg_options &o) {
     a.small32 = o.small_cells < 0 ? 0 : cells <= (o.small_cells > 0 ? o.small_cells : 512LL * 512) ? 1 : 0;
     a.small64 = o.small_cells < 0 ? 0 : cells <= (o.small_cells > 0 ? o.small_cells : 256LL * 256) ? 1 : 0;
     a.colouring = o.colouring == MG_SMOOTH_MULTICOLOUR ? 1 : 0;
+    a.periodic = (L.cg.box_bc[1] == MG_BC_PERIODIC ? 1 : 0) | (L.cg.box_bc[0] == MG_BC_PERIODIC ? 2 : 0);
     return a;
 }
 
@@ -883,7 +884,7 @@ mg_status mg_setup(const mg_grid *grid, int n_curves, const mg_curve *curves, do
         for (int s = 0; s < curves[k].n_seg; ++s) {
             const mg_segment &sg = curves[k].seg[s];
             if ((sg.kind != MG_SEG_LINE && sg.kind != MG_SEG_ARC && sg.kind != MG_SEG_CUBIC) || sg.bc < 0 ||
-                sg.bc > 2)
+                sg.bc > 3)
                 return MG_ERR_INVALID_ARG;
             const int np = sg.kind == MG_SEG_LINE ? 4 : sg.kind == MG_SEG_ARC ? 5 : 8;
             for (int t = 0; t < np; ++t)

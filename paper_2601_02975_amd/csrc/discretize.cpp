@@ -37,6 +37,10 @@ void ghost_weights(int bc, int which, double w[5]) {
 // alpha1 p(0) + alpha2 p'(0) / h = g, averaged over the ghost cell
 // [which - 1, which].
 void face_ghost(int bc, double al1, double al2, double h, int which, double w[5]) {
+    if (bc == MG_BC_PERIODIC) {            // no ghost formula: the kernels wrap instead
+        for (int k = 0; k < 5; ++k) w[k] = 0.0;
+        return;
+    }
     if (bc != MG_BC_ROBIN) {
         ghost_weights(bc, which, w);
         if (bc == MG_BC_NEUMANN) w[4] *= h;
@@ -117,8 +121,13 @@ void Level::sfv_row(int i, int j, std::vector<std::pair<int, double>> &cells,
     sfv_terms(a, b, c, h, terms);
     cells.clear();
     gdat.clear();
+    // periodic box sides: positions beyond them are the cells one period
+    // away; what is still outside takes the other sides' ghost formulas
+    const bool per_x = cg.box_bc[1] == MG_BC_PERIODIC, per_y = cg.box_bc[0] == MG_BC_PERIODIC;
     for (auto &t : terms) {
         int qi = i + (int)t[0], qj = j + (int)t[1];
+        if (per_x) qi = (qi % nx + nx) % nx;
+        if (per_y) qj = (qj % ny + ny) % ny;
         double w = t[2];
         bool outx = qi < 0 || qi >= nx, outy = qj < 0 || qj >= ny;
         if (!outx && !outy) {

@@ -317,6 +317,12 @@ void build_cutgrid(const Curves &cv, const mg_grid &g, double eps, CutGrid &cg) 
             cg.box_al[s][0] = box[s].al1;
             cg.box_al[s][1] = box[s].al2;
         }
+        for (int s = 0; s < 2; ++s)
+            if ((box[s].bc == MG_BC_PERIODIC) != (box[s + 2].bc == MG_BC_PERIODIC))
+                fail(MG_ERR_GEOMETRY, "periodic box sides must come in opposite pairs");
+        for (size_t k = 1; k < cv.c.size(); ++k)
+            for (const Seg &sg : cv.c[k])
+                if (sg.bc == MG_BC_PERIODIC) fail(MG_ERR_GEOMETRY, "periodic conditions apply to box sides only");
     }
     // runs per cell
     std::map<int, std::vector<Run>> runs;

@@ -47,10 +47,13 @@ struct GhostWLds {
 // Ghost value at (qi, qj) outside the box (homogeneous part; face data live
 // in the right-hand side), from in-box values at(i, j) and ghost weights
 // W(side, depth, k).  Corner positions apply the x and y face formulas in
-// turn.
+// turn.  Across a periodic side the position is first moved by one period.
 template <typename T, typename At, typename Wt>
 __device__ T ghost_at(const At &at, const Wt &W, const LevelArgs &L, int qi, int qj) {
+    if (L.periodic & 1) qi = qi < 0 ? qi + L.nx : qi >= L.nx ? qi - L.nx : qi;
+    if (L.periodic & 2) qj = qj < 0 ? qj + L.ny : qj >= L.ny ? qj - L.ny : qj;
     const bool ox = qi < 0 || qi >= L.nx, oy = qj < 0 || qj >= L.ny;
+    if (!ox && !oy) return at(qi, qj);
     if (ox && oy) {
         const int xside = qi < 0 ? 3 : 1, yside = qj < 0 ? 0 : 2;
         const int m = qi < 0 ? -qi : qi - L.nx + 1, k = qj < 0 ? -qj : qj - L.ny + 1;
@@ -152,7 +155,9 @@ __device__ __forceinline__ void load_tile(T (*s)[HX], double *gws, const At &at,
     }
     if (!edge) return;
     // the tile holds cells [i0 - 2, i0 + TX + 2) x [j0 - 2, j0 + TY + 2)
-    const bool lds_ok = (i0 + TX + 2 <= L.nx || L.nx - 4 >= i0 - 2) && (j0 + TYv + 2 <= L.ny || L.ny - 4 >= j0 - 2);
+    // (periodic sides wrap to cells that may lie outside the tile)
+    const bool lds_ok = !L.periodic && (i0 + TX + 2 <= L.nx || L.nx - 4 >= i0 - 2) &&
+                        (j0 + TYv + 2 <= L.ny || L.ny - 4 >= j0 - 2);
     auto lat = [&](int i, int j) { return s[j - j0 + 2][i - i0 + 2]; };
     const GhostWLds W{gws};
     __syncthreads();
@@ -675,9 +680,9 @@ __global__ __launch_bounds__(NT) void k_restrict(LevelArgs L, LevelArgs C, int t
         return;
     }
     // the tile's fine cells: each thread owns R consecutive rows of one
-    // column and slides a 5 x 5 window down it (as in the smoother); pairs of
-    // rows are summed in registers, pairs of columns across neighbouring
-    // lanes, and the even lanes write the coarse cells
+    // column and slides a 5 x 5 window down it (as in the smoother); each
+    // pair of rows is summed as it completes, then across the neighbouring
+    // lane, and the even lanes write the coarse cells
     const int tile = xcd_tile(blockIdx.x, ntile);
     const int i0 = (tile % tiles_x) * TX, j0 = (tile / tiles_x) * TY;
     constexpr int R = TY / (NT / TX);
@@ -695,7 +700,18 @@ __global__ __launch_bounds__(NT) void k_restrict(LevelArgs L, LevelArgs C, int t
         mk[k] = in ? mask[id] : (uint8_t)0;
         bv[k] = b[id];
     }
-    T res[R];
+    const int ci = i >> 1;
+    // row pair (k - 1, k) complete: sum across the lane pair, even lanes write
+    auto emit = [&](int k, T pair) {
+        const T other = __shfl_xor(pair, 1, 64);
+        const int cj = (j0 + r0 + k) >> 1;
+        if ((tx & 1) || ci >= C.nx || cj >= C.ny) return;
+        const size_t cid = pidx(C, ci, cj);
+        const uint8_t ck = rmask[cid];
+        if (ck == 2) return;                        // cells with extra children: the list blocks
+        if (uc) uc[cid] = 0;
+        bc[cid] = ck ? (T)0.25 * (pair + other) : (T)0;
+    };
     if (RESID) {
         load_tile<T>(s, gws, [&](int a, int c) { return u[pidx(L, a, c)]; }, L, i0, j0);
         __syncthreads();
@@ -705,6 +721,7 @@ __global__ __launch_bounds__(NT) void k_restrict(LevelArgs L, LevelArgs C, int t
         for (int a = 1; a < 5; ++a)
 #pragma unroll
             for (int c = 0; c < 5; ++c) w[a][c] = s[r0 + a - 1][lx - 2 + c];
+        T pair = 0;
 #pragma unroll
         for (int k = 0; k < R; ++k) {
 #pragma unroll
@@ -713,28 +730,18 @@ __global__ __launch_bounds__(NT) void k_restrict(LevelArgs L, LevelArgs C, int t
                 for (int c = 0; c < 5; ++c) w[a][c] = w[a + 1][c];
 #pragma unroll
             for (int c = 0; c < 5; ++c) w[4][c] = s[r0 + k + 4][lx - 2 + c];
-            res[k] = (T)0;
+            T r = (T)0;
             if (mk[k] == 1)
-                res[k] = bv[k] - apply_sfv<T, MIXED>(L, [&](int dx, int dy) { return w[dy + 2][dx + 2]; });
+                r = bv[k] - apply_sfv<T, MIXED>(L, [&](int dx, int dy) { return w[dy + 2][dx + 2]; });
             else if (mk[k] == 2 && rplg)
-                res[k] = rplg[plgidx[pidx(L, i, j0 + r0 + k)]];
+                r = rplg[plgidx[pidx(L, i, j0 + r0 + k)]];
+            if (k & 1) emit(k - 1, pair + r);
+            else pair = r;
         }
     } else {
 #pragma unroll
-        for (int k = 0; k < R; ++k) res[k] = mk[k] ? bv[k] : (T)0;
-    }
-    const int ci = i >> 1;
-#pragma unroll
-    for (int k = 0; k < R; k += 2) {
-        const T pair = res[k] + res[k + 1];
-        const T other = __shfl_xor(pair, 1, 64);
-        const int cj = (j0 + r0 + k) >> 1;
-        if ((tx & 1) || ci >= C.nx || cj >= C.ny) continue;
-        const size_t cid = pidx(C, ci, cj);
-        const uint8_t ck = rmask[cid];
-        if (ck == 2) continue;                      // cells with extra children: the list blocks
-        if (uc) uc[cid] = 0;
-        bc[cid] = ck ? (T)0.25 * (pair + other) : (T)0;
+        for (int k = 0; k < R; k += 2)
+            emit(k, (mk[k] ? bv[k] : (T)0) + (mk[k + 1] ? bv[k + 1] : (T)0));
     }
 }
 

@@ -29,6 +29,7 @@ struct LevelArgs {
     // selects 8-row tiles for the fused kernel in FP32 / FP64
     int split_a, small32, small64;
     int colouring;              // 1: the multicolour variant of the SFV half of the smoother
+    int periodic;               // bit 0: left/right sides periodic, bit 1: bottom/top sides periodic
 };
 
 // Launch A PLG block: rows [r0, r1) of group g (rows [gs, gs + n) in solve

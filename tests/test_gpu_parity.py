@@ -35,6 +35,8 @@ CASES = {
     "square_cross_robin_box32": lambda: _robin_box(W.unit_square_config(32, 1.0, 0.5, 2.0), 2.0, 0.25),
     # a hole of cubic Bezier pieces (Neumann), with the cross term
     "bezier96": lambda: W.bezier_config(0, 96),
+    # box periodic in x (Sec. 4.1), Dirichlet in y, cross term
+    "periodic64": lambda: W.periodic_config(0, 64),
 }
 
 

@@ -17,7 +17,8 @@ Segment kinds
   ('arc',   (cx, cy, r, theta0, theta1))   signed sweep theta1 - theta0
   ('cubic', (x0, y0, x1, y1, x2, y2, x3, y3))   Bezier control points
 Each segment carries its boundary condition: bc in {'D', 'N', 'R'} and the
-Robin coefficients (alpha1, alpha2).  The outward normal of Omega at a point
+Robin coefficients (alpha1, alpha2); box sides may also be periodic ('P', in
+opposite pairs).  The outward normal of Omega at a point
 with tangent (x', y') is (y', -x') / |(x', y')|.
 
 Random draws use numpy.random.default_rng(seed) (PCG64); the draw order is the
@@ -31,7 +32,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-BC_DIRICHLET, BC_NEUMANN, BC_ROBIN = "D", "N", "R"
+BC_DIRICHLET, BC_NEUMANN, BC_ROBIN, BC_PERIODIC = "D", "N", "R", "P"
 
 
 @dataclass(frozen=True)
@@ -223,6 +224,25 @@ def star_hole(cx, cy, R, r_in, phi, npts=8, bc=BC_ROBIN, alpha1=1.0, alpha2=0.5,
         else:
             cw.append(Segment("arc", (p[0], p[1], p[2], p[4], p[3]), bc, alpha1, alpha2))
     return cw
+
+
+def periodic_config(seed=0, n=64):
+    """[0,1]^2 minus a seeded disk, periodic in x (left and right sides),
+    Dirichlet at the bottom and the top, Dirichlet on the disk; (a, b, c) =
+    (1, 0.5, 2); 4 sine modes sin(k1 pi x) sin(k2 pi y) with even k1, so
+    that u is 1-periodic in x."""
+    rng = np.random.default_rng([int(seed), 31])
+    r = float(rng.uniform(0.1, 0.2))
+    cx, cy = (float(v) for v in rng.uniform(0.3, 0.7, size=2))
+    ks = rng.integers(1, 5, size=(4, 2))
+    amps = rng.uniform(-1.0, 1.0, size=4)
+    modes = [(2 * int(1 + ks[m, 0] % 2), int(ks[m, 1]), float(amps[m])) for m in range(4)]
+    box = box_curve(0.0, 0.0, 1.0, 1.0)
+    box = [Segment(sg.kind, sg.p, BC_PERIODIC if k in (1, 3) else BC_DIRICHLET, 1.0, 0.0)
+           for k, sg in enumerate(box)]
+    curves = [box, disk_hole(cx, cy, r)]
+    return Problem("periodic%d_seed%d" % (n, seed), Grid(0.0, 0.0, 1.0 / n, n, n), curves, 1.0, 0.5, 2.0,
+                   SineModes(modes, 1.0, 0.5, 2.0), eps=0.08, meta={"modes": modes})
 
 
 def bezier_hole(cx, cy, rx, ry, phi=0.0, wobble=(0.0, 0.0, 0.0, 0.0), bc=BC_DIRICHLET, alpha1=1.0, alpha2=0.0):
