@@ -40,6 +40,12 @@ def gauss_points(n):
     return 8 if n <= 1024 else 4
 
 
+# Gauss points per direction for the serving requests' inputs: the serving
+# figures measure the solver, and a 2 x 2 rule (exact to degree 3) keeps the
+# host-side projection of many 2048^2 inputs short
+SERVING_GAUSS = 2
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     with open(os.path.join(ROOT, "paper_2601_02975_amd", "csrc", "kernels.hip"), "rb") as fh:
@@ -85,8 +91,9 @@ def timed_solves(torch, S, f, g, steps, warmup, tol):
 
 def kernel_time(torch, S, f, g, solves, tol):
     """Average duration of the finest level's SFV tile kernel over `solves`
-    solves that replay graphs with HIP events recorded around that kernel
-    (on the stream it runs on), and the time per solve in that mode."""
+    solves launched eagerly (no graph replay) with HIP events recorded
+    around each of its launches on the stream it runs on, and the time per
+    solve in that mode."""
     u = torch.zeros_like(f)
     S.kernel_timing(True)
     torch.cuda.synchronize()
@@ -101,16 +108,23 @@ def kernel_time(torch, S, f, g, solves, tol):
 
 
 def roofline(S, avg_ms, launches, traffic):
-    """k_smooth_tiles<float> on the finest level (the dominant kernel of the
-    mixed solve): algorithmic bytes 3 w per SFV cell (u and b read, u
-    written; w = 4 bytes) over its average duration."""
-    alg_bytes = 12 * S.info["n_sfv"][0]
+    """The dominant kernel of the mixed solve on the finest level, over its
+    average duration: with two-sweep tiles k_smooth_pair<float> (the first
+    sweep of a pair on every SFV cell, u and b read and u written, 3 w per
+    cell, w = 4 bytes, plus the second sweep's u written on the cells of the
+    two-sweep tiles, w per cell), else k_smooth_tiles<float> (3 w per SFV
+    cell)."""
+    n_sfv, n_pair = S.info["n_sfv"][0], S.info["n_pair_sfv"][0]
+    alg_bytes = 12 * n_sfv + 4 * n_pair
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None
-    return {"bound": "hbm", "kernel": "k_smooth_tiles<float> (finest level: omega-Jacobi on the SFV cells)",
+    kernel = ("k_smooth_pair<float> (finest level: two omega-Jacobi sweeps on the SFV cells of the two-sweep "
+              "tiles, the first sweep on the other SFV cells)" if n_pair else
+              "k_smooth_tiles<float> (finest level: omega-Jacobi on the SFV cells)")
+    return {"bound": "hbm", "kernel": kernel,
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
             "launches_timed": launches, "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": alg_bytes,
-            "sfv_cells": S.info["n_sfv"][0]}
+            "sfv_cells": n_sfv, "two_sweep_sfv_cells": n_pair}
 
 
 def fp64_floor(torch, S, f, g, tols=(1e-11, 1e-12, 1e-13, 1e-14)):
@@ -231,7 +245,7 @@ def serving_leg(torch, mg, W, geoms, n_rhs, qps, slots, tol, label):
                   file=sys.stderr, flush=True)
     inputs = []
     for k, P in reqs:
-        inputs.append(seq[mg.FP64][k].project(P.solution, gauss_points(P.grid.nx)))
+        inputs.append(seq[mg.FP64][k].project(P.solution, SERVING_GAUSS))
         print("%s: input %d/%d projected (%d^2)" % (label[:24], len(inputs), len(reqs), P.grid.nx),
               file=sys.stderr, flush=True)
     seq_rate = {}
@@ -287,7 +301,7 @@ def _project_all(torch, mg, probs, threads=4):
 
     def one(P):
         S = mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, max_iters=1000, nu=NU)
-        fg = S.project(P.solution, gauss_points(P.grid.nx))
+        fg = S.project(P.solution, SERVING_GAUSS)
         S.close()
         return fg
     out = []
@@ -418,7 +432,7 @@ def serving_resident(torch, mg, W, n_geom, n_rhs, slots, tol, budget):
 
 def solve_leg(torch, mg, P, steps, warmup, tol, timing_solves, label):
     """Mixed and FP64 solves of one workload, both replaying graphs; the
-    tile kernel's duration from a separate pass with in-graph events."""
+    tile kernel's duration from a separate eager pass with HIP events."""
     n = P.grid.nx
     t0 = time.perf_counter()
     S32 = mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=mg.MIXED, max_iters=1000, nu=NU)
@@ -463,6 +477,8 @@ def main():
     ap.add_argument("--no-secondary", action="store_true", help="skip the 1024^2 three-disk line")
     ap.add_argument("--no-floor", action="store_true", help="skip the FP64 floor measurement")
     ap.add_argument("--only-headline", action="store_true", help="the 4096^2 star line only")
+    ap.add_argument("--only-secondary", action="store_true",
+                    help="the 1024^2 three-disk line only (for profiling its kernels)")
     ap.add_argument("--serving-traces", action="store_true",
                     help="run only the serving traces with fresh geometries and with resident 2048^2 geometries")
     ap.add_argument("--trace-requests", type=int, default=64)
@@ -506,6 +522,16 @@ def main():
                                                     args.tol, 64 << 30)}
         print(json.dumps(out))
         return
+    if args.only_secondary:
+        P2 = W.three_disks_config(0, 1024)
+        sec, S32b, S64b, f2, g2, _, _, (nl2, ms2) = solve_leg(
+            torch, mg, P2, args.steps, args.warmup, args.tol, args.timing_solves, "three disks 1024")
+        sec["roofline"] = roofline(S32b, ms2, nl2, load_traffic_for("three_disks1024", "k_smooth_a_fp32"))
+        sec["roofline"]["kernel"] = "k_smooth_a<float> (finest level: SFV tiles and PLG groups, one kernel)"
+        S32b.close()
+        S64b.close()
+        print(json.dumps({"three_disks1024": sec}))
+        return
     P = W.star_config(0, 4096)
     head, S32, S64, f, g, dt32, it64, (launches, avg_ms) = solve_leg(
         torch, mg, P, args.steps, args.warmup, args.tol, args.timing_solves, "star 4096")
@@ -529,7 +555,8 @@ def main():
                    "solver": "V-cycles (Algorithm 3), nu = %s, omega = 1/2; graph replay" % (NU,)},
     }
     out.update(head)
-    out["roofline"] = roofline(S32, avg_ms, launches, load_traffic_for("star4096", "k_smooth_tiles_fp32"))
+    out["roofline"] = roofline(S32, avg_ms, launches, load_traffic_for(
+        "star4096", "k_smooth_pair_fp32" if S32.info["n_pair_sfv"][0] else "k_smooth_tiles_fp32"))
     S32.close()
     S64.close()
     if not args.no_floor:
@@ -541,7 +568,8 @@ def main():
         # the same solve with the FMG cycle, fewer sweeps, and the
         # multicolour smoother
         var = {}
-        for kw, name in ((dict(cycle=mg.CYCLE_FMG), "fmg_nu66"), (dict(nu=(4, 4)), "v_nu44"),
+        for kw, name in ((dict(pair_sweeps=-1), "v_nu66_single_sweep_tiles"),
+                         (dict(cycle=mg.CYCLE_FMG), "fmg_nu66"), (dict(nu=(4, 4)), "v_nu44"),
                          (dict(colouring=mg.SMOOTH_MULTICOLOUR), "v_nu66_multicolour"),
                          (dict(colouring=mg.SMOOTH_MULTICOLOUR, nu=(4, 4)), "v_nu44_multicolour")):
             opts = dict(eps=P.eps, precision=mg.MIXED, max_iters=1000, nu=NU)

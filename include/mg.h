@@ -125,6 +125,13 @@ typedef struct {
      * cells (32..768, default 256) coupled through separator unknowns.  Any
      * partition solves A22 exactly; it changes the rounding and the timing. */
     int seg_max, seg_whole;
+    /* Two-sweep tiles (0 = on, -1 = off; timing, and rounding only): on
+     * levels whose launch A is split, with the Jacobi smoother, consecutive
+     * sweeps are run in pairs, and the tiles whose cells and 2-cell halo are
+     * SFV cells and whose 4-cell halo lies inside the box do both sweeps'
+     * SFV updates in one pass (eq. (5.5) twice: the PLG block solve between
+     * the sweeps does not reach them). */
+    int pair_sweeps;
 } mg_options;
 
 typedef struct {
@@ -151,6 +158,7 @@ typedef struct {
      * block solver (ordering, factors) and its device layout, [4] the bottom
      * inverse, [5] everything else (uploads, right-hand-side tables) */
     double setup_stage_seconds[6];
+    long long n_pair_sfv[16];  /* SFV cells in two-sweep tiles per level (see pair_sweeps) */
 } mg_info;
 
 /* Defaults listed in mg_options. */
@@ -270,7 +278,9 @@ const char *mg_error_string(mg_status s);
  * captured graphs) with a pair of HIP events recorded on the launch stream
  * around every finest-level launch of the smoother's SFV tile kernel (the
  * dominant kernel: the omega-Jacobi sweep of eq. (5.5); on levels where
- * launch A is one kernel, that whole kernel).  enable = 0 stops recording
+ * launch A is one kernel, that whole kernel; where sweeps run in pairs
+ * (pair_sweeps), only the kernel of the two-sweep tiles, and sweeps left
+ * over from the pairs are not recorded).  enable = 0 stops recording
  * and returns the number of recorded launches and their average duration in
  * milliseconds. */
 mg_status mg_kernel_timing(mg_handle h, int enable, int *launches, double *avg_ms);

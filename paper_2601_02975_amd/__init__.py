@@ -50,7 +50,8 @@ class mg_options(ctypes.Structure):
                 ("precision", ctypes.c_int), ("max_iters", ctypes.c_int), ("cycle", ctypes.c_int),
                 ("degree", ctypes.c_int), ("w_min", ctypes.c_double), ("colouring", ctypes.c_int),
                 ("split_cells", ctypes.c_longlong), ("small_cells", ctypes.c_longlong),
-                ("split_b_sep", ctypes.c_int), ("seg_max", ctypes.c_int), ("seg_whole", ctypes.c_int)]
+                ("split_b_sep", ctypes.c_int), ("seg_max", ctypes.c_int), ("seg_whole", ctypes.c_int),
+                ("pair_sweeps", ctypes.c_int)]
 
 
 class mg_info(ctypes.Structure):
@@ -59,7 +60,8 @@ class mg_info(ctypes.Structure):
                 ("sweep_words", ctypes.c_longlong * 16), ("n_sfv", ctypes.c_longlong * 16),
                 ("n_face", ctypes.c_int), ("n_irr", ctypes.c_int), ("nnz_plg", ctypes.c_longlong),
                 ("device_bytes", ctypes.c_longlong), ("setup_seconds", ctypes.c_double),
-                ("cond_A22", ctypes.c_double * 16), ("setup_stage_seconds", ctypes.c_double * 6)]
+                ("cond_A22", ctypes.c_double * 16), ("setup_stage_seconds", ctypes.c_double * 6),
+                ("n_pair_sfv", ctypes.c_longlong * 16)]
 
 
 F_BATCH = ctypes.CFUNCTYPE(None, ctypes.c_longlong, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
@@ -293,7 +295,8 @@ class Solver:
                 "sweep_words": list(inf.sweep_words[:n]), "n_face": inf.n_face,
                 "n_irr": inf.n_irr, "nnz_plg": inf.nnz_plg, "device_bytes": inf.device_bytes,
                 "setup_seconds": inf.setup_seconds, "n_sfv": list(inf.n_sfv[:n]),
-                "cond_A22": list(inf.cond_A22[:n]), "setup_stage_seconds": list(inf.setup_stage_seconds)}
+                "cond_A22": list(inf.cond_A22[:n]), "setup_stage_seconds": list(inf.setup_stage_seconds),
+                "n_pair_sfv": list(inf.n_pair_sfv[:n])}
 
     def export_level(self, level):
         nx, ny = self.info["nx"][level], self.info["ny"][level]

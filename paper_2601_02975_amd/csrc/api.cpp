@@ -41,8 +41,15 @@ struct DevLevel {
     size_t ncells = 0;
     uint8_t *mask = nullptr;
     int *plgidx = nullptr;
-    double *u64[2] = {nullptr, nullptr}, *b64 = nullptr, *rplg64 = nullptr;
-    float *u32[2] = {nullptr, nullptr}, *b32 = nullptr, *rplg32 = nullptr;
+    // iterates: two buffers, three on levels with two-sweep tiles
+    double *u64[3] = {nullptr, nullptr, nullptr}, *b64 = nullptr, *rplg64 = nullptr;
+    float *u32[3] = {nullptr, nullptr, nullptr}, *b32 = nullptr, *rplg32 = nullptr;
+    int nbuf = 2;
+    // two-sweep tiles and the other tiles with SFV cells (row-major tile
+    // numbers of the split launch's tiles in the handle's cycle precision)
+    int *pair_tiles = nullptr, *single_tiles = nullptr;
+    int npair = 0, nsingle = 0, pair_word = 0;     // pair_word: the word size the lists are for
+    long long n_pair_sfv = 0;
     int m = 0;
     int *plg_cell = nullptr, *full_ptr = nullptr, *full_col = nullptr;
     int *fe_col = nullptr;                  // PLG rows, fixed width (ELL_W), padded cell index
@@ -63,7 +70,7 @@ struct DevLevel {
     long long sweep_words = 0;    // words moved by one smoother launch A (algorithmic)
     long long nsfv = 0;
     // finest level, FP64 FMG: residual equation right-hand side and its iterate
-    double *r64 = nullptr, *e64[2] = {nullptr, nullptr};
+    double *r64 = nullptr, *e64[3] = {nullptr, nullptr, nullptr};
 };
 
 }  // namespace
@@ -274,16 +281,29 @@ void upload_level(mg_handle h, int l, bool last, hipStream_t st) {
             for (int k = 0; k < 4; ++k) gw[(side * 2 + d - 1) * 4 + k] = w[k];
         }
     D.args.gw = h->upload(gw);
-    // blocks of 64 x 8 cells made only of SFV cells
+    // class flags of the blocks of 64 x 8 cells: every cell SFV; no SFV
+    // cell; no active cell here nor among the 32 x 4 cells of the next level
+    // under the block
     D.args.full_bx = (nx + 63) / 64;
     D.args.full_by = (ny + 7) / 8;
     std::vector<uint8_t> full((size_t)D.args.full_bx * D.args.full_by, 0);
+    const Level *Cn = last ? nullptr : h->levels[l + 1].get();
     for (int by = 0; by < D.args.full_by; ++by)
         for (int bx = 0; bx < D.args.full_bx; ++bx) {
-            bool all = bx * 64 + 64 <= nx && by * 8 + 8 <= ny;
-            for (int j = by * 8; all && j < by * 8 + 8; ++j)
-                for (int i = bx * 64; all && i < bx * 64 + 64; ++i) all = L.kind[(size_t)j * nx + i] == 1;
-            full[(size_t)by * D.args.full_bx + bx] = all ? 1 : 0;
+            bool all = bx * 64 + 64 <= nx && by * 8 + 8 <= ny, none = true, dead = true;
+            for (int j = by * 8; j < std::min(by * 8 + 8, ny); ++j)
+                for (int i = bx * 64; i < std::min(bx * 64 + 64, nx); ++i) {
+                    const uint8_t k = L.kind[(size_t)j * nx + i];
+                    all = all && k == 1;
+                    none = none && k != 1;
+                    dead = dead && k == 0;
+                }
+            if (dead && Cn)
+                for (int j = by * 4; j < std::min(by * 4 + 4, Cn->g.ny); ++j)
+                    for (int i = bx * 32; i < std::min(bx * 32 + 32, Cn->g.nx); ++i)
+                        dead = dead && !Cn->cg.active[(size_t)j * Cn->g.nx + i];
+            full[(size_t)by * D.args.full_bx + bx] =
+                (uint8_t)((all ? FULL_ALL_SFV : 0) | (none ? FULL_NO_SFV : 0) | (dead ? FULL_DEAD : 0));
         }
     D.args.full = h->upload(full);
     D.ncells = (size_t)(nx + 4) * (ny + 4);
@@ -293,7 +313,34 @@ void upload_level(mg_handle h, int l, bool last, hipStream_t st) {
     for (int q = 0; q < S.m; ++q) plgidx[padded_index(nx, L.plg_cells[S.order[q]])] = q;
     D.mask = h->upload(mask);
     D.plgidx = h->upload(plgidx);
-    for (int k = 0; k < 2; ++k) {
+    // two-sweep tiles (split launch A, Jacobi): all cells of the tile and
+    // its 2-cell halo are SFV cells, and its 4-cell halo lies in the box
+    if (D.args.split_a && !D.args.colouring && h->opt.pair_sweeps == 0) {
+        const int word = h->opt.precision == MG_MIXED ? 4 : 8, tys = split_tile_rows(word);
+        const int tiles_x = (nx + 63) / 64, tiles_y = (ny + tys - 1) / tys;
+        std::vector<int> pairs, singles;
+        for (int t = 0; t < tiles_x * tiles_y; ++t) {
+            const int i0 = (t % tiles_x) * 64, j0 = (t / tiles_x) * tys;
+            bool any = false;
+            for (int j = j0; j < std::min(j0 + tys, ny); ++j)
+                for (int i = i0; i < std::min(i0 + 64, nx); ++i) any = any || L.kind[(size_t)j * nx + i] == 1;
+            if (!any) continue;
+            bool pair = i0 >= 4 && i0 + 68 <= nx && j0 >= 4 && j0 + tys + 4 <= ny;
+            for (int j = j0 - 2; pair && j < j0 + tys + 2; ++j)
+                for (int i = i0 - 2; pair && i < i0 + 66; ++i) pair = L.kind[(size_t)j * nx + i] == 1;
+            (pair ? pairs : singles).push_back(t);
+        }
+        if (!pairs.empty()) {
+            D.npair = (int)pairs.size();
+            D.nsingle = (int)singles.size();
+            D.n_pair_sfv = (long long)D.npair * 64 * tys;
+            D.pair_tiles = h->upload(pairs);
+            D.single_tiles = h->upload(singles);
+            D.nbuf = 3;
+            D.pair_word = word;
+        }
+    }
+    for (int k = 0; k < D.nbuf; ++k) {
         D.u64[k] = h->alloc<double>(D.ncells);
         D.u32[k] = h->alloc<float>(D.ncells);
     }
@@ -513,19 +560,47 @@ struct Prec<float> {
     static PlgDev<float> &P(DevLevel &D) { return D.P32; }
 };
 
-// one block-smoother sweep on level l (the iterate ping-pongs between the
-// level's two buffers); uzero: the current iterate is known to be zero
+// sweeps in pairs on this level in precision T (the tile lists are built
+// for the tile height of the handle's cycle precision)
+template <typename T>
+bool use_pairs(const DevLevel &D) {
+    return D.npair > 0 && (int)sizeof(T) == D.pair_word;
+}
+
+// one block-smoother sweep on level l (the iterate rotates through the
+// level's buffers); uzero: the current iterate is known to be zero
 template <typename T>
 void smooth(mg_handle h, int l, bool uzero, hipStream_t st) {
     DevLevel &D = h->dev[l];
-    T *uo = Prec<T>::u(D, D.cur), *un = Prec<T>::u(D, 1 - D.cur);
-    // in timing mode: events around the finest level's tile kernel
-    const bool rec = h->tim_capture && l == 0 && 2 * h->ev_next + 1 < (int)h->ev.size();
+    const int nx = (D.cur + 1) % D.nbuf;
+    T *uo = Prec<T>::u(D, D.cur), *un = Prec<T>::u(D, nx);
+    // in timing mode: events around the finest level's tile kernel (levels
+    // with two-sweep tiles time those instead)
+    const bool rec = h->tim_capture && l == 0 && !use_pairs<T>(D) && 2 * h->ev_next + 1 < (int)h->ev.size();
     hipEvent_t e0 = rec ? h->ev[2 * h->ev_next] : nullptr, e1 = rec ? h->ev[2 * h->ev_next + 1] : nullptr;
     if (rec) ++h->ev_next;
     launch_smooth_a<T>(D.args, uo, Prec<T>::b(D), un, D.mask, uzero, Prec<T>::P(D), st, e0, e1);
     launch_smooth_b<T>(Prec<T>::P(D), un, st);
-    D.cur = 1 - D.cur;
+    D.cur = nx;
+}
+
+// n block-smoother sweeps on level l: in pairs where the level has two-sweep
+// tiles, the last one alone when n is odd
+template <typename T>
+void smooth_n(mg_handle h, int l, int n, bool uzero, hipStream_t st) {
+    DevLevel &D = h->dev[l];
+    int k = 0;
+    for (; use_pairs<T>(D) && k + 2 <= n; k += 2) {
+        const int n1 = (D.cur + 1) % 3, n2 = (D.cur + 2) % 3;
+        const bool rec = h->tim_capture && l == 0 && 2 * h->ev_next + 1 < (int)h->ev.size();
+        hipEvent_t e0 = rec ? h->ev[2 * h->ev_next] : nullptr, e1 = rec ? h->ev[2 * h->ev_next + 1] : nullptr;
+        if (rec) ++h->ev_next;
+        launch_smooth_pair<T>(D.args, Prec<T>::u(D, D.cur), Prec<T>::b(D), Prec<T>::u(D, n1), Prec<T>::u(D, n2),
+                              D.mask, uzero && k == 0, Prec<T>::P(D), D.pair_tiles, D.npair, D.single_tiles,
+                              D.nsingle, st, e0, e1);
+        D.cur = n2;
+    }
+    for (; k < n; ++k) smooth<T>(h, l, uzero && k == 0, st);
 }
 
 // Algorithm 3 on level l; uzero: the iterate on entry is zero (the coarse
@@ -540,7 +615,7 @@ void vcycle(mg_handle h, int l, bool uzero, hipStream_t st) {
     }
     const int nu1 = h->opt.nu1;
     if (nu1 == 0 && uzero) launch_fill_zero<T>(D.ncells, Prec<T>::u(D, D.cur), st);
-    for (int k = 0; k < nu1; ++k) smooth<T>(h, l, uzero && k == 0, st);
+    smooth_n<T>(h, l, nu1, uzero, st);
     DevLevel &C = h->dev[l + 1];
     T *u = Prec<T>::u(D, D.cur);
     // after a block-smoother sweep the PLG residuals are zero; without
@@ -552,11 +627,11 @@ void vcycle(mg_handle h, int l, bool uzero, hipStream_t st) {
     }
     C.cur = 0;
     launch_restrict<T>(D.args, C.args, u, Prec<T>::b(D), D.mask, D.plgidx, rplg, D.rmask, Prec<T>::b(C),
-                       nu1 == 0 ? Prec<T>::u(C, 0) : nullptr, D.ex_nt, D.ex_ptr, D.ex_target, D.ex_child, st);
+                       nu1 == 0 ? Prec<T>::u(C, 0) : nullptr, D.ex_nt, D.ex_ptr, D.ex_target, D.ex_child, true, st);
     vcycle<T>(h, l + 1, true, st);
     launch_prolong<T>(D.args, C.args, D.mask, C.mask, Prec<T>::u(C, C.cur), Prec<T>::u(D, D.cur), D.pex_n, D.pex_fine,
                       D.pex_coarse, false, st);
-    for (int k = 0; k < h->opt.nu2; ++k) smooth<T>(h, l, false, st);
+    smooth_n<T>(h, l, h->opt.nu2, false, st);
 }
 
 // Algorithm 4 on level l for the residual equation whose right-hand side is
@@ -573,7 +648,7 @@ void fmg(mg_handle h, int l, hipStream_t st) {
     }
     DevLevel &C = h->dev[l + 1];
     launch_restrict<T>(D.args, C.args, nullptr, Prec<T>::b(D), D.mask, D.plgidx, nullptr, D.rmask, Prec<T>::b(C),
-                       nullptr, D.ex_nt, D.ex_ptr, D.ex_target, D.ex_child, st);
+                       nullptr, D.ex_nt, D.ex_ptr, D.ex_target, D.ex_child, true, st);
     C.cur = 0;
     fmg<T>(h, l + 1, st);
     D.cur = 0;
@@ -630,18 +705,16 @@ void enqueue_iteration(mg_handle h, int par, int slot, hipStream_t st) {
     } else if (fmg_cycle) {
         // the FP64 cycle runs on the residual equation's own buffers
         std::swap(D.b64, D.r64);
-        std::swap(D.u64[0], D.e64[0]);
-        std::swap(D.u64[1], D.e64[1]);
+        for (int k = 0; k < D.nbuf; ++k) std::swap(D.u64[k], D.e64[k]);
         fmg<double>(h, 0, st);
         const double *e = D.u64[D.cur];
         std::swap(D.b64, D.r64);
-        std::swap(D.u64[0], D.e64[0]);
-        std::swap(D.u64[1], D.e64[1]);
+        for (int k = 0; k < D.nbuf; ++k) std::swap(D.u64[k], D.e64[k]);
         D.cur = 0;
         enqueue_residual(h, par, e, true, slot, st);
     } else {
         vcycle<double>(h, 0, false, st);
-        if (D.cur != 0) HIPCHECK(hipMemcpyAsync(D.u64[0], D.u64[1], D.ncells * 8, hipMemcpyDeviceToDevice, st));
+        if (D.cur != 0) HIPCHECK(hipMemcpyAsync(D.u64[0], D.u64[D.cur], D.ncells * 8, hipMemcpyDeviceToDevice, st));
         D.cur = 0;
         enqueue_residual(h, 0, nullptr, false, slot, st);
     }
@@ -827,7 +900,7 @@ void restrict_step(mg_handle h, int level, const T *b, const T *u, T *bc, hipStr
     T *rplg = Prec<T>::rplg(D);
     launch_plg_residual<T>(D.m, D.plg_cell, D.full_ptr, D.full_col, Prec<T>::fval(D), b, u, rplg, st);
     launch_restrict<T>(D.args, C.args, u, b, D.mask, D.plgidx, rplg, D.rmask, bc, nullptr, D.ex_nt, D.ex_ptr,
-                       D.ex_target, D.ex_child, st);
+                       D.ex_target, D.ex_child, false, st);
 }
 
 }  // namespace
@@ -854,6 +927,7 @@ mg_status mg_default_options(mg_options *opt) {
     opt->split_b_sep = 0;
     opt->seg_max = 0;
     opt->seg_whole = 0;
+    opt->pair_sweeps = 0;
     return MG_OK;
 }
 
@@ -873,7 +947,8 @@ mg_status mg_setup(const mg_grid *grid, int n_curves, const mg_curve *curves, do
         (o.cycle != MG_CYCLE_V && o.cycle != MG_CYCLE_FMG) || !(o.omega > 0 && o.omega < 2) ||
         !(o.w_min > 0 && o.w_min < 1e6) || (o.colouring != MG_SMOOTH_JACOBI && o.colouring != MG_SMOOTH_MULTICOLOUR) ||
         o.split_cells < 0 || o.small_cells < -1 || o.split_b_sep < 0 || o.seg_max < 0 ||
-        (o.seg_max > 0 && (o.seg_max < 32 || o.seg_max > PLG_LMAX)) || o.seg_whole < 0 || o.seg_whole > PLG_LMAX)
+        (o.seg_max > 0 && (o.seg_max < 32 || o.seg_max > PLG_LMAX)) || o.seg_whole < 0 || o.seg_whole > PLG_LMAX ||
+        (o.pair_sweeps != 0 && o.pair_sweeps != -1))
         return MG_ERR_INVALID_ARG;
     if (o.degree != 4) {
         g_last_error = "only degree-4 fits (lattices of 15 cells) are built";
@@ -966,8 +1041,7 @@ mg_status mg_setup(const mg_grid *grid, int n_curves, const mg_curve *curves, do
         if (o.cycle == MG_CYCLE_FMG && o.precision == MG_FP64) {
             DevLevel &D0 = h->dev[0];
             D0.r64 = h->alloc<double>(D0.ncells);
-            D0.e64[0] = h->alloc<double>(D0.ncells);
-            D0.e64[1] = h->alloc<double>(D0.ncells);
+            for (int k = 0; k < D0.nbuf; ++k) D0.e64[k] = h->alloc<double>(D0.ncells);
         }
         int maxblk = 1;
         for (auto &D : h->dev)
@@ -1010,7 +1084,7 @@ mg_status mg_vcycle(mg_handle h, const double *b_dev, double *u_dev, void *strea
         D.b64 = const_cast<double *>(b_dev);
         D.cur = 0;
         vcycle<double>(h, 0, false, st);
-        if (D.cur != 0) HIPCHECK(hipMemcpyAsync(u_dev, D.u64[1], D.ncells * 8, hipMemcpyDeviceToDevice, st));
+        if (D.cur != 0) HIPCHECK(hipMemcpyAsync(u_dev, D.u64[D.cur], D.ncells * 8, hipMemcpyDeviceToDevice, st));
         D.u64[0] = keep_u;
         D.b64 = keep_b;
         D.cur = 0;
@@ -1179,6 +1253,7 @@ mg_status mg_query(mg_handle h, mg_info *info) {
         info->sweep_words[l] = h->dev[l].sweep_words;
         info->n_sfv[l] = h->dev[l].nsfv;
         info->cond_A22[l] = l < (int)h->cond_a22.size() ? h->cond_a22[l] : 0.0;
+        info->n_pair_sfv[l] = h->dev[l].n_pair_sfv;
         info->nnz_plg += (long long)L.col.size();
     }
     info->n_face = h->levels[0]->n_face;

@@ -257,6 +257,19 @@ constexpr int rows_unroll() {
     return 2;
 }
 
+// AND of the class flags of the 64 x 8 blocks that make up the tile of TYv
+// rows at (i0, j0); rows beyond the grid count as blocks with no cells.
+template <int TYv>
+__device__ __forceinline__ unsigned tile_flags(const LevelArgs &L, int i0, int j0) {
+    unsigned f = 0xffu;
+#pragma unroll
+    for (int q = 0; q < TYv / 8; ++q) {
+        const int by = (j0 >> 3) + q;
+        f &= by < L.full_by ? (unsigned)L.full[by * L.full_bx + (i0 >> 6)] : (unsigned)(FULL_NO_SFV | FULL_DEAD);
+    }
+    return f;
+}
+
 // ---------------------------------------------------------------------------
 // Launch A, tile role: weighted Jacobi on the SFV cells, eq. (5.5),
 // D = -5(a+c)/(2h^2).  uzero: the old iterate is zero (first sweep of a
@@ -268,14 +281,12 @@ __device__ __forceinline__ void jacobi_tile(const LevelArgs &L, const T *__restr
     constexpr int R = TYv / (NT / TX);           // consecutive rows per thread
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     const int i = i0 + tx, r0 = ty * R;
-    // a tile made of blocks whose cells are all SFV cells skips the class
-    // bytes (TYv is a multiple of 8, i0 of 64, j0 of TYv)
-    bool full = true;
-#pragma unroll
-    for (int q = 0; q < TYv / 8; ++q) {
-        const int by = (j0 >> 3) + q;
-        full = full && by < L.full_by && L.full[by * L.full_bx + (i0 >> 6)] != 0;
-    }
+    // a tile with no SFV cell has nothing to update; one made of blocks whose
+    // cells are all SFV cells skips the class bytes (TYv is a multiple of 8,
+    // i0 of 64, j0 of TYv)
+    const unsigned tf = tile_flags<TYv>(L, i0, j0);
+    if (tf & FULL_NO_SFV) return;
+    const bool full = (tf & FULL_ALL_SFV) != 0;
     // the per-cell loads are issued before the tile barrier so that their
     // latency overlaps the tile load
     uint8_t mk[R];
@@ -337,6 +348,7 @@ __device__ __forceinline__ void multicolour_tile(const LevelArgs &L, const T *__
     constexpr int NC = MIXED ? 9 : 3, MULT = MIXED ? 3 : 1;
     constexpr int PER_ROW = (TX + NC - 1) / NC;          // cells of one colour per tile row, at most
     constexpr int R = TYv / (NT / TX);
+    if (tile_flags<TYv>(L, i0, j0) & FULL_NO_SFV) return;      // nothing to update
     // b and the class bytes of the tile, row-coalesced, into LDS
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     const int gi = i0 + tx;
@@ -525,18 +537,151 @@ __global__ __launch_bounds__(NT) void k_smooth_a(LevelArgs L, const T *__restric
 // tile height of k_smooth_tiles (the shorter FP64 tiles need fewer registers)
 template <typename T>
 constexpr int ty_split() {
-    return sizeof(T) == 4 ? 32 : 16;
+    return split_tile_rows((int)sizeof(T));
 }
 
 template <typename T, bool MIXED, int TYv>
 __global__ __launch_bounds__(NT) void k_smooth_tiles(LevelArgs L, const T *__restrict__ uold,
                                                      const T *__restrict__ b, T *__restrict__ unew,
-                                                     const uint8_t *__restrict__ mask, int tiles_x, int uzero) {
+                                                     const uint8_t *__restrict__ mask, int tiles_x, int uzero,
+                                                     const int *__restrict__ list) {
     __shared__ __align__(16) T smem[(TYv + 4) * HX];
     __shared__ double gws[32];
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int k = xcd_tile(blockIdx.x, gridDim.x);
+    const int t = list ? list[k] : k;
     jacobi_tile<T, MIXED, TYv>(L, uold, b, unew, mask, uzero != 0, (t % tiles_x) * TX, (t / tiles_x) * TYv,
                                reinterpret_cast<T(*)[HX]>(smem), gws);
+}
+
+// Two consecutive sweeps of eq. (5.5) on a tile in one pass, for tiles whose
+// cells and 2-cell halo are all SFV cells and whose 4-cell halo lies inside
+// the box: the halo's first-sweep values need only old values (no PLG cell
+// and no ghost among them), so the tile's second-sweep values follow from
+// the first without the PLG block solve in between.  The arithmetic of each
+// cell's update is that of jacobi_tile.  The first sweep's values of the
+// tile go to ub (the PLG groups and the neighbouring tiles read them), the
+// second sweep's to uc.  E2: the tile with its 4-cell halo (old values); E1:
+// the tile with its 2-cell halo (first-sweep values).
+constexpr int PX = TX + 8;
+template <typename T, bool MIXED, int TYv>
+__device__ __forceinline__ void pair_tile(const LevelArgs &L, const T *__restrict__ uold, const T *__restrict__ b,
+                                          T *__restrict__ ub, T *__restrict__ uc, bool uzero, int i0, int j0,
+                                          T (*s2)[PX], T (*s1)[HX]) {
+    constexpr int E1 = TYv + 4, RR = (E1 + 3) / 4, R = TYv / 4, NX1 = 4 * E1;
+    static_assert(NT == 4 * TX, "four thread rows of 64 columns");
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const T wod = (T)L.omega_over_d;
+    // right-hand sides: E1's 64 middle columns (RR rows per thread row),
+    // E1's 4 outer columns (one cell per thread), the tile (second sweep)
+    T b1[RR], bx = 0, b2[R];
+#pragma unroll
+    for (int k = 0; k < RR; ++k) {
+        const int er = ty * RR + k;
+        b1[k] = er < E1 ? b[pidx(L, i0 + tx, j0 - 2 + er)] : (T)0;
+    }
+    const int xc = threadIdx.x / E1, xr = threadIdx.x - xc * E1;      // outer column xc (0..3), row xr
+    const int xe = xc < 2 ? xc : TX + xc;                               // its E1 column
+    if (threadIdx.x < NX1) bx = b[pidx(L, i0 - 2 + xe, j0 - 2 + xr)];
+#pragma unroll
+    for (int k = 0; k < R; ++k) b2[k] = b[pidx(L, i0 + tx, j0 + ty * R + k)];
+    if (!uzero) {
+        constexpr int N2 = (TYv + 8) * PX, NL = (N2 + NT - 1) / NT;
+        T v[NL];
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int t = threadIdx.x + k * NT;
+            const int r = t / PX, c = t - r * PX;
+            v[k] = t < N2 ? uold[pidx(L, i0 - 4 + c, j0 - 4 + r)] : (T)0;
+        }
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int t = threadIdx.x + k * NT;
+            if (t < N2) s2[t / PX][t % PX] = v[k];
+        }
+        __syncthreads();
+    }
+    // first sweep on E1
+    if (uzero) {
+#pragma unroll
+        for (int k = 0; k < RR; ++k) {
+            const int er = ty * RR + k;
+            if (er < E1) s1[er][tx + 2] = wod * b1[k];
+        }
+        if (threadIdx.x < NX1) s1[xr][xe] = wod * bx;
+    } else {
+        T w[5][5];
+#pragma unroll
+        for (int a = 1; a < 5; ++a)
+#pragma unroll
+            for (int c = 0; c < 5; ++c) w[a][c] = s2[ty * RR + a - 1][tx + 2 + c];
+#pragma unroll
+        for (int k = 0; k < RR; ++k) {
+            const int er = ty * RR + k;
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 5; ++c) w[a][c] = w[a + 1][c];
+            if (er >= E1) break;
+#pragma unroll
+            for (int c = 0; c < 5; ++c) w[4][c] = s2[er + 4][tx + 2 + c];
+            const T au = apply_sfv<T, MIXED>(L, [&](int dx, int dy) { return w[dy + 2][dx + 2]; });
+            s1[er][tx + 2] = w[2][2] + wod * (b1[k] - au);
+        }
+        if (threadIdx.x < NX1) {
+            const int ly = xr + 2, lx = xe + 2;
+            const T au = apply_sfv<T, MIXED>(L, [&](int dx, int dy) { return s2[ly + dy][lx + dx]; });
+            s1[xr][xe] = s2[ly][lx] + wod * (bx - au);
+        }
+    }
+    __syncthreads();
+    // second sweep on the tile
+    const int r0 = ty * R;
+    T w[5][5];
+#pragma unroll
+    for (int a = 1; a < 5; ++a)
+#pragma unroll
+        for (int c = 0; c < 5; ++c) w[a][c] = s1[r0 + a - 1][tx + c];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 5; ++c) w[a][c] = w[a + 1][c];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) w[4][c] = s1[r0 + k + 4][tx + c];
+        const T au = apply_sfv<T, MIXED>(L, [&](int dx, int dy) { return w[dy + 2][dx + 2]; });
+        const size_t id = pidx(L, i0 + tx, j0 + r0 + k);
+        ub[id] = w[2][2];
+        uc[id] = w[2][2] + wod * (b2[k] - au);
+    }
+}
+
+// Launch of the first sweep of a pair on a level with two-sweep tiles:
+// blocks [0, npad) take the two-sweep tiles (list pairs, padded to a
+// multiple of 8 blocks so that the other role keeps its XCD-aligned order),
+// the rest the other tiles with SFV cells (list singles), which do the first
+// sweep alone into ub; tiles without SFV cells are not launched.
+template <typename T, bool MIXED, int TYv>
+__global__ __launch_bounds__(NT) void k_smooth_pair(LevelArgs L, const T *__restrict__ uold,
+                                                    const T *__restrict__ b, T *__restrict__ ub, T *__restrict__ uc,
+                                                    const uint8_t *__restrict__ mask, int tiles_x, int uzero,
+                                                    const int *__restrict__ pairs, int npair, int npad,
+                                                    const int *__restrict__ singles, int nsingle) {
+    __shared__ __align__(16) T s2[(TYv + 8) * PX];
+    __shared__ __align__(16) T s1[(TYv + 4) * HX];
+    __shared__ double gws[32];
+    const int bid = blockIdx.x;
+    if (bid < npad) {
+        const int k = xcd_tile(bid, npad);
+        if (k >= npair) return;
+        const int t = pairs[k];
+        pair_tile<T, MIXED, TYv>(L, uold, b, ub, uc, uzero != 0, (t % tiles_x) * TX, (t / tiles_x) * TYv,
+                                 reinterpret_cast<T(*)[PX]>(s2), reinterpret_cast<T(*)[HX]>(s1));
+        return;
+    }
+    const int t = singles[xcd_tile(bid - npad, nsingle)];
+    jacobi_tile<T, MIXED, TYv>(L, uold, b, ub, mask, uzero != 0, (t % tiles_x) * TX, (t / tiles_x) * TYv,
+                               reinterpret_cast<T(*)[HX]>(s1), gws);
 }
 
 template <typename T, bool MIXED, int TYv>
@@ -658,7 +803,7 @@ __global__ __launch_bounds__(NT) void k_restrict(LevelArgs L, LevelArgs C, int t
                                                  const T *__restrict__ rplg, const uint8_t *__restrict__ rmask,
                                                  T *__restrict__ bc, T *__restrict__ uc, int nt,
                                                  const int *__restrict__ ex_ptr, const int *__restrict__ ex_target,
-                                                 const int *__restrict__ ex_child) {
+                                                 const int *__restrict__ ex_child, int skip_dead) {
     __shared__ T s[HY][HX];
     __shared__ double gws[32];
     if ((int)blockIdx.x >= ntile) {
@@ -685,11 +830,15 @@ __global__ __launch_bounds__(NT) void k_restrict(LevelArgs L, LevelArgs C, int t
     // lane, and the even lanes write the coarse cells
     const int tile = xcd_tile(blockIdx.x, ntile);
     const int i0 = (tile % tiles_x) * TX, j0 = (tile / tiles_x) * TY;
+    // a tile with no active cell over inactive coarse cells would write
+    // zeros over zeros (buffers of the hierarchy only)
+    if (skip_dead && (tile_flags<TY>(L, i0, j0) & FULL_DEAD)) return;
     constexpr int R = TY / (NT / TX);
     static_assert(R % 2 == 0, "rows per thread come in pairs");
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     const int i = i0 + tx, r0 = ty * R;
     const bool col_in = i < L.nx;
+    const bool full = (tile_flags<TY>(L, i0, j0) & FULL_ALL_SFV) != 0;
     uint8_t mk[R];
     T bv[R];
 #pragma unroll
@@ -697,8 +846,18 @@ __global__ __launch_bounds__(NT) void k_restrict(LevelArgs L, LevelArgs C, int t
         const int j = j0 + r0 + k;
         const bool in = col_in && j < L.ny;
         const size_t id = pidx(L, in ? i : 0, in ? j : 0);
-        mk[k] = in ? mask[id] : (uint8_t)0;
+        mk[k] = full ? (uint8_t)1 : in ? mask[id] : (uint8_t)0;
         bv[k] = b[id];
+    }
+    // the residuals of this thread's PLG cells, loaded before the tile
+    // barrier (they overwrite bv)
+    if (RESID && !full) {
+        int pq[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) pq[k] = (mk[k] == 2 && rplg) ? plgidx[pidx(L, i, j0 + r0 + k)] : -1;
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if (pq[k] >= 0) bv[k] = rplg[pq[k]];
     }
     const int ci = i >> 1;
     // row pair (k - 1, k) complete: sum across the lane pair, even lanes write
@@ -734,7 +893,7 @@ __global__ __launch_bounds__(NT) void k_restrict(LevelArgs L, LevelArgs C, int t
             if (mk[k] == 1)
                 r = bv[k] - apply_sfv<T, MIXED>(L, [&](int dx, int dy) { return w[dy + 2][dx + 2]; });
             else if (mk[k] == 2 && rplg)
-                r = rplg[plgidx[pidx(L, i, j0 + r0 + k)]];
+                r = bv[k];
             if (k & 1) emit(k - 1, pair + r);
             else pair = r;
         }
@@ -935,37 +1094,52 @@ __global__ __launch_bounds__(NT) void k_residual_norm(LevelArgs L, int tiles_x, 
             if (r64) r64[id] = r;
             mx = fabs(r);
         }
-    } else {
+    } else if (!(r64 == nullptr && (tile_flags<TY>(L, (xcd_tile(blockIdx.x, ntile) % tiles_x) * TX,
+                                                   (xcd_tile(blockIdx.x, ntile) / tiles_x) * TY) &
+                                        FULL_DEAD))) {
+        // (a tile with no active cell writes only zeros, which the
+        // hierarchy's own buffers already hold there; it is skipped unless
+        // the caller's residual buffer r64 is to be written)
+        // each thread owns R consecutive rows of one column and slides a
+        // 5 x 5 window of the tile down it (as in the smoother)
         constexpr int R = TY / (NT / TX);
         const int tile = xcd_tile(blockIdx.x, ntile);
         const int i0 = (tile % tiles_x) * TX, j0 = (tile / tiles_x) * TY;
         const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-        const int i = i0 + tx;
+        const int i = i0 + tx, r0 = ty * R;
+        const bool full = (tile_flags<TY>(L, i0, j0) & FULL_ALL_SFV) != 0;
         uint8_t mk[R];
         double bv[R];
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            const int j = j0 + ty + k * (NT / TX);
+            const int j = j0 + r0 + k;
             const bool in = i < L.nx && j < L.ny;
             const size_t id = pidx(L, in ? i : 0, in ? j : 0);
-            mk[k] = in ? mask[id] : 0;
+            mk[k] = full ? (uint8_t)1 : in ? mask[id] : (uint8_t)0;
             bv[k] = b[id];
         }
         load_tile<double>(s, gws, [&](int a, int c) { return uat(pidx(L, a, c)); }, L, i0, j0);
         __syncthreads();
+        double w[5][5];
+#pragma unroll
+        for (int a = 1; a < 5; ++a)
+#pragma unroll
+            for (int c = 0; c < 5; ++c) w[a][c] = s[r0 + a - 1][tx + c];
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            const int rr = ty + k * (NT / TX);
-            const int j = j0 + rr;
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 5; ++c) w[a][c] = w[a + 1][c];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) w[4][c] = s[r0 + k + 4][tx + c];
+            const int j = j0 + r0 + k;
             if (i >= L.nx || j >= L.ny) continue;
             const size_t id = pidx(L, i, j);
-            if (CORRECT) uout[id] = mk[k] ? s[rr + 2][tx + 2] : 0.0;
+            if (CORRECT) uout[id] = mk[k] ? w[2][2] : 0.0;
             if (mk[k] == 2) continue;                 // PLG rows: the blocks after the tiles
             double r = 0.0;
-            if (mk[k] == 1) {
-                const int lx = tx + 2, ly = rr + 2;
-                r = bv[k] - apply_sfv<double, MIXED>(L, [&](int dx, int dy) { return s[ly + dy][lx + dx]; });
-            }
+            if (mk[k] == 1) r = bv[k] - apply_sfv<double, MIXED>(L, [&](int dx, int dy) { return w[dy + 2][dx + 2]; });
             if (WRITE32) r32[id] = (float)r;
             if (r64) r64[id] = r;
             mx = fmax(mx, fabs(r));
@@ -1122,10 +1296,10 @@ void launch_smooth_a(const LevelArgs &L, const T *uold, const T *b, T *unew, con
         const int nts = tiles_x * ((L.ny + tys - 1) / tys);
         if (L.mixed)
             hipLaunchKernelGGL((k_smooth_tiles<T, true, tys>), dim3(nts), dim3(NT), 0, st, L, uold, b, unew,
-                               mask, tiles_x, uz);
+                               mask, tiles_x, uz, nullptr);
         else
             hipLaunchKernelGGL((k_smooth_tiles<T, false, tys>), dim3(nts), dim3(NT), 0, st, L, uold, b, unew,
-                               mask, tiles_x, uz);
+                               mask, tiles_x, uz, nullptr);
         if (ev1) (void)hipEventRecord(ev1, st);
         if (P.nblk1 == 0) return;
         // no stencil is evaluated here, so one instantiation serves b = 0 and b != 0
@@ -1140,6 +1314,44 @@ void launch_smooth_a(const LevelArgs &L, const T *uold, const T *b, T *unew, con
     else { if (small) MG_SA(false, TY_SMALL); else MG_SA(false, TY); }
     if (ev1) (void)hipEventRecord(ev1, st);
 #undef MG_SA
+}
+
+// Two sweeps on a level whose launch A is split: the first sweep's tiles
+// (two-sweep tiles also doing the second) into ub, the PLG groups and launch
+// B on ub; the second sweep's remaining tiles from ub into uc, the PLG groups
+// and launch B on uc.
+template <typename T>
+void launch_smooth_pair(const LevelArgs &L, const T *uold, const T *b, T *ub, T *uc, const uint8_t *mask,
+                        bool uzero, const PlgDev<T> &P, const int *pairs, int npair, const int *singles, int nsingle,
+                        hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+    constexpr int tys = ty_split<T>();
+    const int tiles_x = (L.nx + TX - 1) / TX;
+    const int npad = (npair + 7) & ~7;
+    const int uz = uzero ? 1 : 0;
+    if (ev0) (void)hipEventRecord(ev0, st);
+    if (L.mixed)
+        hipLaunchKernelGGL((k_smooth_pair<T, true, tys>), dim3(npad + nsingle), dim3(NT), 0, st, L, uold, b, ub, uc,
+                           mask, tiles_x, uz, pairs, npair, npad, singles, nsingle);
+    else
+        hipLaunchKernelGGL((k_smooth_pair<T, false, tys>), dim3(npad + nsingle), dim3(NT), 0, st, L, uold, b, ub,
+                           uc, mask, tiles_x, uz, pairs, npair, npad, singles, nsingle);
+    if (ev1) (void)hipEventRecord(ev1, st);
+    if (P.nblk1)
+        hipLaunchKernelGGL((k_smooth_a<T, false, TY, true>), dim3(P.nblk1), dim3(NT), 0, st, L, uold, b, ub, mask,
+                           tiles_x, 0, uz, P);
+    launch_smooth_b<T>(P, ub, st);
+    if (nsingle) {
+        if (L.mixed)
+            hipLaunchKernelGGL((k_smooth_tiles<T, true, tys>), dim3(nsingle), dim3(NT), 0, st, L, ub, b, uc, mask,
+                               tiles_x, 0, singles);
+        else
+            hipLaunchKernelGGL((k_smooth_tiles<T, false, tys>), dim3(nsingle), dim3(NT), 0, st, L, ub, b, uc, mask,
+                               tiles_x, 0, singles);
+    }
+    if (P.nblk1)
+        hipLaunchKernelGGL((k_smooth_a<T, false, TY, true>), dim3(P.nblk1), dim3(NT), 0, st, L, ub, b, uc, mask,
+                           tiles_x, 0, 0, P);
+    launch_smooth_b<T>(P, uc, st);
 }
 
 template <typename T>
@@ -1176,13 +1388,13 @@ void launch_plg_residual(int m, const int *cell, const int *ptr, const int *col,
 template <typename T>
 void launch_restrict(const LevelArgs &L, const LevelArgs &C, const T *u, const T *b, const uint8_t *mask,
                      const int *plgidx, const T *rplg, const uint8_t *rmask, T *bc, T *uc, int nt, const int *ex_ptr,
-                     const int *ex_target, const int *ex_child, hipStream_t st) {
+                     const int *ex_target, const int *ex_child, bool skip_dead, hipStream_t st) {
     const int tx = (C.nx + TX / 2 - 1) / (TX / 2), ty = (C.ny + TY / 2 - 1) / (TY / 2);
     const int ntile = tx * ty;
     const dim3 grid(ntile + (nt + NT - 1) / NT);
 #define MG_RS(MX, RS)                                                                                            \
     hipLaunchKernelGGL((k_restrict<T, MX, RS>), grid, dim3(NT), 0, st, L, C, tx, ntile, u, b, mask, plgidx, rplg, \
-                       rmask, bc, uc, nt, ex_ptr, ex_target, ex_child)
+                       rmask, bc, uc, nt, ex_ptr, ex_target, ex_child, skip_dead ? 1 : 0)
     if (!u) MG_RS(false, false);
     else if (L.mixed) MG_RS(true, true);
     else MG_RS(false, true);
@@ -1284,14 +1496,20 @@ template void launch_smooth_a<double>(const LevelArgs &, const double *, const d
                                       bool, const PlgDev<double> &, hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_smooth_a<float>(const LevelArgs &, const float *, const float *, float *, const uint8_t *, bool,
                                      const PlgDev<float> &, hipStream_t, hipEvent_t, hipEvent_t);
+template void launch_smooth_pair<double>(const LevelArgs &, const double *, const double *, double *, double *,
+                                         const uint8_t *, bool, const PlgDev<double> &, const int *, int, const int *,
+                                         int, hipStream_t, hipEvent_t, hipEvent_t);
+template void launch_smooth_pair<float>(const LevelArgs &, const float *, const float *, float *, float *,
+                                        const uint8_t *, bool, const PlgDev<float> &, const int *, int, const int *,
+                                        int, hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_smooth_b<double>(const PlgDev<double> &, double *, hipStream_t);
 template void launch_smooth_b<float>(const PlgDev<float> &, float *, hipStream_t);
 template void launch_fill_zero<double>(size_t, double *, hipStream_t);
 template void launch_fill_zero<float>(size_t, float *, hipStream_t);
 template void launch_plg_residual<double>(int, const int *, const int *, const int *, const double *, const double *, const double *, double *, hipStream_t);
 template void launch_plg_residual<float>(int, const int *, const int *, const int *, const float *, const float *, const float *, float *, hipStream_t);
-template void launch_restrict<double>(const LevelArgs &, const LevelArgs &, const double *, const double *, const uint8_t *, const int *, const double *, const uint8_t *, double *, double *, int, const int *, const int *, const int *, hipStream_t);
-template void launch_restrict<float>(const LevelArgs &, const LevelArgs &, const float *, const float *, const uint8_t *, const int *, const float *, const uint8_t *, float *, float *, int, const int *, const int *, const int *, hipStream_t);
+template void launch_restrict<double>(const LevelArgs &, const LevelArgs &, const double *, const double *, const uint8_t *, const int *, const double *, const uint8_t *, double *, double *, int, const int *, const int *, const int *, bool, hipStream_t);
+template void launch_restrict<float>(const LevelArgs &, const LevelArgs &, const float *, const float *, const uint8_t *, const int *, const float *, const uint8_t *, float *, float *, int, const int *, const int *, const int *, bool, hipStream_t);
 template void launch_prolong<double>(const LevelArgs &, const LevelArgs &, const uint8_t *, const uint8_t *, const double *, double *, int, const int *, const int *, bool, hipStream_t);
 template void launch_prolong<float>(const LevelArgs &, const LevelArgs &, const uint8_t *, const uint8_t *, const float *, float *, int, const int *, const int *, bool, hipStream_t);
 template void launch_bottom<double, double>(int, const int *, const double *, const double *, double *, hipStream_t);

@@ -7,6 +7,11 @@
 
 namespace mgc {
 
+constexpr uint8_t FULL_ALL_SFV = 1, FULL_NO_SFV = 2, FULL_DEAD = 4;
+
+// rows of the SFV tiles (64 cells wide) of a split launch A, by word size
+constexpr int split_tile_rows(int word) { return word == 4 ? 32 : 16; }
+
 // Launch-time parameters of one level (passed by value).
 struct LevelArgs {
     int nx, ny, pitch;          // pitch = nx + 4, origin at (2, 2)
@@ -17,9 +22,13 @@ struct LevelArgs {
     // enter through the right-hand side), device array gw[(side * 2 + depth - 1) * 4 + k],
     // sides bottom, right, top, left, k = steps inward
     const double *gw;
-    // per block of 64 x 8 cells (row-major, full_bx x full_by blocks): 1 when
-    // every cell of the block is an SFV cell, so that tiles made of such
-    // blocks need not read the class bytes
+    // per block of 64 x 8 cells (row-major, full_bx x full_by blocks), flags:
+    // FULL_ALL_SFV, every cell is an SFV cell (tiles made of such blocks need
+    // not read the class bytes); FULL_NO_SFV, no cell is (the smoother's
+    // tiles have nothing to update); FULL_DEAD, no cell is active, nor any of
+    // the 32 x 4 cells of the next coarser level under the block (the
+    // residual and restriction tiles would only write zeros that are already
+    // there)
     const uint8_t *full;
     int full_bx, full_by;
     int mixed;                  // b != 0

@@ -17,6 +17,16 @@ void launch_smooth_a(const LevelArgs &L, const T *uold, const T *b, T *unew, con
                      const PlgDev<T> &P, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 template <typename T>
 void launch_smooth_b(const PlgDev<T> &P, T *unew, hipStream_t st);
+// two block-smoother sweeps uold -> ub -> uc on a level whose launch A is
+// split (LevelArgs::split_a, Jacobi): pairs[0, npair) are the tiles of
+// split_tile_rows(sizeof(T)) rows (row-major tile numbers, 64 cells wide)
+// whose cells and 2-cell halo are SFV cells and whose 4-cell halo lies in
+// the box, singles[0, nsingle) the other tiles with SFV cells; ev0/ev1 (may
+// be null) are recorded around the first kernel (the two-sweep tiles)
+template <typename T>
+void launch_smooth_pair(const LevelArgs &L, const T *uold, const T *b, T *ub, T *uc, const uint8_t *mask,
+                        bool uzero, const PlgDev<T> &P, const int *pairs, int npair, const int *singles, int nsingle,
+                        hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
 template <typename T>
 void launch_fill_zero(size_t n, T *u, hipStream_t st);
 template <typename T>
@@ -26,7 +36,7 @@ void launch_plg_residual(int m, const int *cell, const int *ptr, const int *col,
 template <typename T>
 void launch_restrict(const LevelArgs &L, const LevelArgs &C, const T *u, const T *b, const uint8_t *mask,
                      const int *plgidx, const T *rplg, const uint8_t *rmask, T *bc, T *uc, int nt, const int *ex_ptr,
-                     const int *ex_target, const int *ex_child, hipStream_t st);
+                     const int *ex_target, const int *ex_child, bool skip_dead, hipStream_t st);
 // set: u = P ec (FMG), else u += P ec
 template <typename T>
 void launch_prolong(const LevelArgs &L, const LevelArgs &C, const uint8_t *mask, const uint8_t *cmask, const T *ec,

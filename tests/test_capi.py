@@ -67,7 +67,8 @@ def test_setup_rejects_a_non_elliptic_equation(abc):
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libmgcut.so not built")
 @pytest.mark.parametrize("opt,code", [({"degree": 3}, -8), ({"w_min": 0.0}, -1), ({"colouring": 2}, -1),
-                                      ({"omega": 0.0}, -1), ({"small_cells": -2}, -1), ({"nu1": -1}, -1)])
+                                      ({"omega": 0.0}, -1), ({"small_cells": -2}, -1), ({"nu1": -1}, -1),
+                                      ({"pair_sweeps": 1}, -1)])
 def test_setup_rejects_bad_options(opt, code):
     import paper_2601_02975_amd as mg
     assert _setup_args(mg, **opt) == code
