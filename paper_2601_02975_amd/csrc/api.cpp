@@ -306,6 +306,22 @@ void upload_level(mg_handle h, int l, bool last, hipStream_t st) {
                 (uint8_t)((all ? FULL_ALL_SFV : 0) | (none ? FULL_NO_SFV : 0) | (dead ? FULL_DEAD : 0));
         }
     D.args.full = h->upload(full);
+    // 64 x 32 tiles with an active cell here or on the next level under them
+    {
+        const int tiles_x = (nx + 63) / 64, tiles_y = (ny + 31) / 32;
+        std::vector<int> live;
+        for (int t = 0; t < tiles_x * tiles_y; ++t) {
+            const int bx = t % tiles_x, by0 = (t / tiles_x) * 4;
+            bool dead = true;
+            for (int by = by0; by < std::min(by0 + 4, D.args.full_by); ++by)
+                dead = dead && (full[(size_t)by * D.args.full_bx + bx] & FULL_DEAD);
+            if (!dead) live.push_back(t);
+        }
+        if ((int)live.size() < tiles_x * tiles_y && !live.empty()) {
+            D.args.live = h->upload(live);
+            D.args.nlive = (int)live.size();
+        }
+    }
     D.ncells = (size_t)(nx + 4) * (ny + 4);
     std::vector<uint8_t> mask(D.ncells, 0);
     std::vector<int> plgidx(D.ncells, -1);

@@ -415,6 +415,8 @@ __device__ __forceinline__ void plg_group(const LevelArgs &L, const T *__restric
         ce_slot = P.ce_slot[ce];
         ce_val = P.ce_val[ce];
     }
+    // the cell of this thread's output row (levels without separators)
+    const int out_cell = (P.nsep == 0 && g < P.nseg && (int)threadIdx.x < r1 - r0) ? P.cell[r0 + threadIdx.x] : 0;
     // u1 after the Jacobi sweep on the SFV cells the group couples to
     for (int k = threadIdx.x; k < bk.nh; k += NT) {
         const int id = P.hcell[bk.h0 + k];
@@ -464,7 +466,7 @@ __device__ __forceinline__ void plg_group(const LevelArgs &L, const T *__restric
     }
     __syncthreads();
     if (P.nsep == 0) {
-        for (int q = threadIdx.x; q < nr; q += NT) unew[P.cell[r0 + q]] = yy[q];
+        if ((int)threadIdx.x < nr) unew[out_cell] = yy[threadIdx.x];      // nr <= PLG_SLICE <= NT
         return;
     }
     for (int q = threadIdx.x; q < nr; q += NT) P.y[r0 + q] = yy[q];
@@ -727,6 +729,10 @@ __global__ __launch_bounds__(NT) void k_smooth_b(PlgDev<T> P, T *__restrict__ u)
         yr = P.y[r];
         cr = P.cell[r];
     }
+    // the cells of a separator block's output rows, loaded before the barrier
+    __shared__ int ocell[PLG_SEP_ROWS];
+    if (MODE != 2 && seprows && (int)threadIdx.x < bk.r1 - bk.r0)
+        ocell[threadIdx.x] = P.cell[P.sep_begin + bk.r0 + threadIdx.x];
     if (MODE == 2) {
         const int *fc = P.fcols + P.fcols_ptr[bk.j];
         for (int kk = threadIdx.x; kk < bk.kj; kk += NT) xk[kk] = u[P.cell[P.sep_begin + fc[kk]]];
@@ -753,7 +759,7 @@ __global__ __launch_bounds__(NT) void k_smooth_b(PlgDev<T> P, T *__restrict__ u)
 #pragma unroll
             for (int k = 0; k < 8; ++k)
                 if (rb + k < nr) {
-                    if (seprows) u[P.cell[P.sep_begin + bk.r0 + rb + k]] = out[k];
+                    if (seprows) u[ocell[rb + k]] = out[k];
                     else xk[rb + k] = out[k];
                 }
     }
@@ -828,11 +834,11 @@ __global__ __launch_bounds__(NT) void k_restrict(LevelArgs L, LevelArgs C, int t
     // column and slides a 5 x 5 window down it (as in the smoother); each
     // pair of rows is summed as it completes, then across the neighbouring
     // lane, and the even lanes write the coarse cells
-    const int tile = xcd_tile(blockIdx.x, ntile);
+    // with skip_dead the launch covers the listed tiles only (a tile with no
+    // active cell over inactive coarse cells would write zeros over zeros)
+    const int tk = xcd_tile(blockIdx.x, ntile);
+    const int tile = skip_dead ? L.live[tk] : tk;
     const int i0 = (tile % tiles_x) * TX, j0 = (tile / tiles_x) * TY;
-    // a tile with no active cell over inactive coarse cells would write
-    // zeros over zeros (buffers of the hierarchy only)
-    if (skip_dead && (tile_flags<TY>(L, i0, j0) & FULL_DEAD)) return;
     constexpr int R = TY / (NT / TX);
     static_assert(R % 2 == 0, "rows per thread come in pairs");
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
@@ -1094,16 +1100,15 @@ __global__ __launch_bounds__(NT) void k_residual_norm(LevelArgs L, int tiles_x, 
             if (r64) r64[id] = r;
             mx = fabs(r);
         }
-    } else if (!(r64 == nullptr && (tile_flags<TY>(L, (xcd_tile(blockIdx.x, ntile) % tiles_x) * TX,
-                                                   (xcd_tile(blockIdx.x, ntile) / tiles_x) * TY) &
-                                        FULL_DEAD))) {
-        // (a tile with no active cell writes only zeros, which the
-        // hierarchy's own buffers already hold there; it is skipped unless
-        // the caller's residual buffer r64 is to be written)
-        // each thread owns R consecutive rows of one column and slides a
-        // 5 x 5 window of the tile down it (as in the smoother)
+    } else {
+        // without a caller's buffer r64 the launch covers the listed tiles
+        // only (a tile with no active cell writes only zeros, which the
+        // hierarchy's own buffers already hold there).  Each thread owns R
+        // consecutive rows of one column and slides a 5 x 5 window of the
+        // tile down it (as in the smoother).
         constexpr int R = TY / (NT / TX);
-        const int tile = xcd_tile(blockIdx.x, ntile);
+        const int tk = xcd_tile(blockIdx.x, ntile);
+        const int tile = (L.live && !r64) ? L.live[tk] : tk;
         const int i0 = (tile % tiles_x) * TX, j0 = (tile / tiles_x) * TY;
         const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
         const int i = i0 + tx, r0 = ty * R;
@@ -1390,7 +1395,10 @@ void launch_restrict(const LevelArgs &L, const LevelArgs &C, const T *u, const T
                      const int *plgidx, const T *rplg, const uint8_t *rmask, T *bc, T *uc, int nt, const int *ex_ptr,
                      const int *ex_target, const int *ex_child, bool skip_dead, hipStream_t st) {
     const int tx = (C.nx + TX / 2 - 1) / (TX / 2), ty = (C.ny + TY / 2 - 1) / (TY / 2);
-    const int ntile = tx * ty;
+    // the list numbers the fine level's 64 x 32 tiles, the same tiles when
+    // the fine grid is twice the coarse one
+    skip_dead = skip_dead && L.live && tx == (L.nx + TX - 1) / TX;
+    const int ntile = skip_dead ? L.nlive : tx * ty;
     const dim3 grid(ntile + (nt + NT - 1) / NT);
 #define MG_RS(MX, RS)                                                                                            \
     hipLaunchKernelGGL((k_restrict<T, MX, RS>), grid, dim3(NT), 0, st, L, C, tx, ntile, u, b, mask, plgidx, rplg, \
@@ -1424,7 +1432,7 @@ int launch_residual_norm(const LevelArgs &L, const double *u, const void *e, boo
                          const uint8_t *mask, int m, const int *pcell, const int *fe_col, const double *fe_val,
                          float *r32, double *r64, double *partial, hipStream_t st) {
     const dim3 tg = tile_grid(L);
-    const int ntile = (int)(tg.x * tg.y), nblk = ntile + (m + NT - 1) / NT;
+    const int ntile = (L.live && !r64) ? L.nlive : (int)(tg.x * tg.y), nblk = ntile + (m + NT - 1) / NT;
 #define MG_RES(MX, W32, CORR, TE)                                                                                      \
     hipLaunchKernelGGL((k_residual_norm<MX, W32, CORR, TE>), dim3(nblk), dim3(NT), 0, st, L, (int)tg.x, ntile, u,       \
                        static_cast<const TE *>(e), uout, b, mask, m, pcell, fe_col, fe_val, r32, r64, partial)

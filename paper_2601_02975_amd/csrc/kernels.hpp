@@ -31,6 +31,12 @@ struct LevelArgs {
     // there)
     const uint8_t *full;
     int full_bx, full_by;
+    // tiles of 64 x 32 cells (row-major tile numbers) that hold an active
+    // cell or lie over one of the next coarser level, in order; the
+    // residual and restriction launch only these on the hierarchy's own
+    // buffers (null: every tile is such a tile)
+    const int *live;
+    int nlive;
     int mixed;                  // b != 0
     // launch shape of the smoother's launch A on this level (chosen at setup
     // from the grid size, or forced by the options): split_a = 1 runs the
