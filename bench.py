@@ -91,8 +91,9 @@ def timed_solves(torch, S, f, g, steps, warmup, tol):
 
 def kernel_time(torch, S, f, g, solves, tol):
     """Average duration of the finest level's SFV tile kernel over `solves`
-    solves launched eagerly (no graph replay) with HIP events recorded
-    around each of its launches on the stream it runs on, and the time per
+    solves launched eagerly (no graph replay) with a pair of HIP events that
+    take the start and end of each of its launches (hipExtLaunchKernel on
+    the stream it runs on), and the time per
     solve in that mode."""
     u = torch.zeros_like(f)
     S.kernel_timing(True)

@@ -275,8 +275,8 @@ const char *mg_error_string(mg_status s);
 
 /* Kernel timing for measurement: enable = 1 clears the record and makes
  * mg_solve launch its outer iterations eagerly (instead of replaying its
- * captured graphs) with a pair of HIP events recorded on the launch stream
- * around every finest-level launch of the smoother's SFV tile kernel (the
+ * captured graphs) with a pair of HIP events that take the start and end of
+ * the execution of every finest-level launch of the smoother's SFV tile kernel (the
  * dominant kernel: the omega-Jacobi sweep of eq. (5.5); on levels where
  * launch A is one kernel, that whole kernel; where sweeps run in pairs
  * (pair_sweeps), only the kernel of the two-sweep tiles, and sweeps left

@@ -99,8 +99,9 @@ struct mg_handle_s {
     hipGraph_t iter_graph[3][4] = {};
     int upar = 0;                 // mixed precision: which FP64 buffer holds the iterate
     // timing of the finest-level SFV tile kernel: in timing mode the outer
-    // iterations are launched eagerly with an event pair around each such
-    // launch, read after each synchronisation
+    // iterations are launched eagerly, each such launch with an event pair
+    // that takes the start and end of its execution, read after each
+    // synchronisation
     bool timing = false;
     std::vector<hipEvent_t> ev;          // pool, 2 per recorded launch of one graph
     int ev_next = 0;                     // next free pair while capturing
@@ -746,9 +747,9 @@ void run_iterations(mg_handle h, int k, hipStream_t st) {
         for (int i = 0; i < k; ++i) enqueue_iteration(h, corr ? (par + i) & 1 : 0, i, s);
     };
     if (h->eager || h->timing) {
-        // kernel timing: eager launches with an event pair around each
-        // finest-level tile kernel (HIP events recorded inside graphs cannot
-        // be timed)
+        // kernel timing: eager launches, an event pair taking the start and
+        // end of each finest-level tile kernel (HIP events recorded inside
+        // graphs cannot be timed)
         h->ev_next = 0;
         h->tim_capture = h->timing;
         enqueue(st);

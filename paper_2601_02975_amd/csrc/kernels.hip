@@ -16,6 +16,7 @@
 //      (only on levels with separators; two launches from 768 separators).
 // Tiles and PLG blocks are handed to the 8 XCDs in runs of consecutive
 // indices, so that neighbours share cache lines in one L2.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -591,9 +592,9 @@ __device__ __forceinline__ void pair_tile(const LevelArgs &L, const T *__restric
         T v[NL];
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
-            const int t = threadIdx.x + k * NT;
+            const int t = min((int)threadIdx.x + k * NT, N2 - 1);
             const int r = t / PX, c = t - r * PX;
-            v[k] = t < N2 ? uold[pidx(L, i0 - 4 + c, j0 - 4 + r)] : (T)0;
+            v[k] = uold[pidx(L, i0 - 4 + c, j0 - 4 + r)];
         }
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
@@ -1276,19 +1277,17 @@ void launch_smooth_a(const LevelArgs &L, const T *uold, const T *b, T *unew, con
     const int ty = small ? TY_SMALL : TY;
     const int tiles_x = (L.nx + TX - 1) / TX, ntile = tiles_x * ((L.ny + ty - 1) / ty);
     const int uz = uzero ? 1 : 0;
-    if (ev0) (void)hipEventRecord(ev0, st);
     if (L.colouring) {
         // the PLG groups read the SFV values the tiles wrote (they cannot
         // recompute a multicolour sweep)
         constexpr int tys = ty_split<T>();
         const int nts = tiles_x * ((L.ny + tys - 1) / tys);
         if (L.mixed)
-            hipLaunchKernelGGL((k_smooth_tiles_mc<T, true, tys>), dim3(nts), dim3(NT), 0, st, L, uold, b, unew, mask,
-                               tiles_x, uz);
+            hipExtLaunchKernelGGL((k_smooth_tiles_mc<T, true, tys>), dim3(nts), dim3(NT), 0, st, ev0, ev1, 0, L,
+                                  uold, b, unew, mask, tiles_x, uz);
         else
-            hipLaunchKernelGGL((k_smooth_tiles_mc<T, false, tys>), dim3(nts), dim3(NT), 0, st, L, uold, b, unew,
-                               mask, tiles_x, uz);
-        if (ev1) (void)hipEventRecord(ev1, st);
+            hipExtLaunchKernelGGL((k_smooth_tiles_mc<T, false, tys>), dim3(nts), dim3(NT), 0, st, ev0, ev1, 0, L,
+                                  uold, b, unew, mask, tiles_x, uz);
         if (P.nblk1 == 0) return;
         hipLaunchKernelGGL((k_smooth_a<T, false, TY, true>), dim3(P.nblk1), dim3(NT), 0, st, L, uold, b, unew,
                            mask, tiles_x, 0, uz, P);
@@ -1300,12 +1299,11 @@ void launch_smooth_a(const LevelArgs &L, const T *uold, const T *b, T *unew, con
         constexpr int tys = ty_split<T>();
         const int nts = tiles_x * ((L.ny + tys - 1) / tys);
         if (L.mixed)
-            hipLaunchKernelGGL((k_smooth_tiles<T, true, tys>), dim3(nts), dim3(NT), 0, st, L, uold, b, unew,
-                               mask, tiles_x, uz, nullptr);
+            hipExtLaunchKernelGGL((k_smooth_tiles<T, true, tys>), dim3(nts), dim3(NT), 0, st, ev0, ev1, 0, L, uold,
+                                  b, unew, mask, tiles_x, uz, (const int *)nullptr);
         else
-            hipLaunchKernelGGL((k_smooth_tiles<T, false, tys>), dim3(nts), dim3(NT), 0, st, L, uold, b, unew,
-                               mask, tiles_x, uz, nullptr);
-        if (ev1) (void)hipEventRecord(ev1, st);
+            hipExtLaunchKernelGGL((k_smooth_tiles<T, false, tys>), dim3(nts), dim3(NT), 0, st, ev0, ev1, 0, L, uold,
+                                  b, unew, mask, tiles_x, uz, (const int *)nullptr);
         if (P.nblk1 == 0) return;
         // no stencil is evaluated here, so one instantiation serves b = 0 and b != 0
         hipLaunchKernelGGL((k_smooth_a<T, false, TY, true>), dim3(P.nblk1), dim3(NT), 0, st, L, uold, b, unew,
@@ -1313,11 +1311,11 @@ void launch_smooth_a(const LevelArgs &L, const T *uold, const T *b, T *unew, con
         return;
     }
     const dim3 grid(ntile + plg_section<T>(P.nblk1));
-#define MG_SA(MX, TYV) \
-    hipLaunchKernelGGL((k_smooth_a<T, MX, TYV>), grid, dim3(NT), 0, st, L, uold, b, unew, mask, tiles_x, ntile, uz, P)
+#define MG_SA(MX, TYV)                                                                                           \
+    hipExtLaunchKernelGGL((k_smooth_a<T, MX, TYV>), grid, dim3(NT), 0, st, ev0, ev1, 0, L, uold, b, unew, mask, tiles_x, \
+                          ntile, uz, P)
     if (L.mixed) { if (small) MG_SA(true, TY_SMALL); else MG_SA(true, TY); }
     else { if (small) MG_SA(false, TY_SMALL); else MG_SA(false, TY); }
-    if (ev1) (void)hipEventRecord(ev1, st);
 #undef MG_SA
 }
 
@@ -1333,14 +1331,12 @@ void launch_smooth_pair(const LevelArgs &L, const T *uold, const T *b, T *ub, T 
     const int tiles_x = (L.nx + TX - 1) / TX;
     const int npad = (npair + 7) & ~7;
     const int uz = uzero ? 1 : 0;
-    if (ev0) (void)hipEventRecord(ev0, st);
     if (L.mixed)
-        hipLaunchKernelGGL((k_smooth_pair<T, true, tys>), dim3(npad + nsingle), dim3(NT), 0, st, L, uold, b, ub, uc,
-                           mask, tiles_x, uz, pairs, npair, npad, singles, nsingle);
+        hipExtLaunchKernelGGL((k_smooth_pair<T, true, tys>), dim3(npad + nsingle), dim3(NT), 0, st, ev0, ev1, 0, L,
+                              uold, b, ub, uc, mask, tiles_x, uz, pairs, npair, npad, singles, nsingle);
     else
-        hipLaunchKernelGGL((k_smooth_pair<T, false, tys>), dim3(npad + nsingle), dim3(NT), 0, st, L, uold, b, ub,
-                           uc, mask, tiles_x, uz, pairs, npair, npad, singles, nsingle);
-    if (ev1) (void)hipEventRecord(ev1, st);
+        hipExtLaunchKernelGGL((k_smooth_pair<T, false, tys>), dim3(npad + nsingle), dim3(NT), 0, st, ev0, ev1, 0, L,
+                              uold, b, ub, uc, mask, tiles_x, uz, pairs, npair, npad, singles, nsingle);
     if (P.nblk1)
         hipLaunchKernelGGL((k_smooth_a<T, false, TY, true>), dim3(P.nblk1), dim3(NT), 0, st, L, uold, b, ub, mask,
                            tiles_x, 0, uz, P);

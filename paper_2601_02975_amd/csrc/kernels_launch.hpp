@@ -10,8 +10,8 @@ namespace mgc {
 // one block-smoother sweep (Definition 5.6), uold -> unew: launch A (SFV
 // tiles, PLG gathers and segment solves), then launch B (separators and
 // segment corrections; nothing on levels without separators);
-// ev0/ev1 (may be null) are recorded around the SFV tile kernel (the whole
-// launch A where it is one kernel)
+// ev0/ev1 (may be null) take the start and end of the SFV tile kernel's
+// execution (the whole launch A where it is one kernel)
 template <typename T>
 void launch_smooth_a(const LevelArgs &L, const T *uold, const T *b, T *unew, const uint8_t *mask, bool uzero,
                      const PlgDev<T> &P, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
@@ -22,7 +22,8 @@ void launch_smooth_b(const PlgDev<T> &P, T *unew, hipStream_t st);
 // split_tile_rows(sizeof(T)) rows (row-major tile numbers, 64 cells wide)
 // whose cells and 2-cell halo are SFV cells and whose 4-cell halo lies in
 // the box, singles[0, nsingle) the other tiles with SFV cells; ev0/ev1 (may
-// be null) are recorded around the first kernel (the two-sweep tiles)
+// be null) take the start and end of the first kernel's execution (the
+// two-sweep tiles)
 template <typename T>
 void launch_smooth_pair(const LevelArgs &L, const T *uold, const T *b, T *ub, T *uc, const uint8_t *mask,
                         bool uzero, const PlgDev<T> &P, const int *pairs, int npair, const int *singles, int nsingle,
