@@ -3,7 +3,7 @@
 Headline workload: [0,1]^2 minus a seeded 8-point star joined to circular
 arcs, 4096 x 4096 cells, a=2, b=-1, c=1, Robin (1, 0.5) on the star,
 Dirichlet outside, 8 seeded sine modes (seed 0).  A step is one whole solve
-from u = 0 (V-cycles of Algorithm 3 with nu = (6, 6) until
+from u = 0 (V-cycles of Algorithm 3 with nu = (6, 4) until
 ||b - A u||_inf <= 1e-10 ||b||_inf) with the inputs already resident on the
 device.  `value` is the mixed-precision rate (FP32 V-cycles inside FP64
 defect correction); the plain FP64 rate is reported beside it, timed the same
@@ -28,10 +28,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# smoothing steps (nu1, nu2) of every solve here; the paper's (3, 3) is
-# reported as a variant (deep V(3,3)-cycles are not h-independent with the
-# piecewise-constant interpolation of eq. (5.9))
-NU = (6, 6)
+# smoothing steps (nu1, nu2) of every solve here (--nu); the paper's (3, 3)
+# is reported as a variant (deep V(3,3)-cycles are not h-independent with the
+# piecewise-constant interpolation of eq. (5.9)); (6, 4) is the fastest of
+# (5,5) .. (8,8), (6,4), (4,6), (8,4), (8,6) on the 4096^2 star
+NU = (6, 4)
 # Gauss points per direction for the cell averages <f> over full cells
 # (exact to degree 2 GP - 1 per variable; the cut cells use the library's
 # own rules): 8 up to 1024^2, 4 above, where the quadrature error of a
@@ -282,16 +283,18 @@ def serving_leg(torch, mg, W, geoms, n_rhs, qps, slots, tol, label):
         tickets.append(srv.submit(pids[reqs[i][0]], f, g, outs[i], tol))
     res = [srv.wait(t) for t in tickets]
     t_all = time.perf_counter() - t_start
+    st = srv.stats()
     srv.close()
     lat = sorted(r["latency_s"] for r in res)
     pct = lambda q: lat[min(len(lat) - 1, int(math.ceil(q * len(lat))) - 1)]
     return {"workload": "%s, resident after one warm-up request each; %d right-hand sides per geometry arriving "
-                        "as a Poisson process at %g/s; %d slots; V-cycles (nu = (6, 6)) in mixed precision to %g" % (
-                            label, n_rhs, qps, slots, tol),
+                        "as a Poisson process at %g/s; %d slots; V-cycles (nu = %s) in mixed precision to %g" % (
+                            label, n_rhs, qps, slots, NU, tol),
             "requests": len(reqs), "failed": sum(r["status"] != 0 for r in res),
             "p50_latency_s": pct(0.50), "p99_latency_s": pct(0.99), "solves_per_s": len(reqs) / t_all,
             "sequential_mixed_solves_per_s": seq_rate["mixed"], "sequential_fp64_solves_per_s": seq_rate["fp64"],
-            "setup_latency_s_max": max(setup_lat)}
+            "setup_latency_s_max": max(setup_lat),
+            "server_sweep_gbs": st["sweep_gbs"]}
 
 
 def _project_all(torch, mg, probs, threads=4):
@@ -354,8 +357,8 @@ def serving_fresh_trace(torch, mg, W, n_req, slots, tol):
     probs = [W.serving_request(0, k) for k in range(n_req)]
     inputs = _project_all(torch, mg, probs)
     out = {"workload": "%d requests of serving trace 0 (grids %s), a fresh geometry each; mixed precision, "
-                       "V-cycles nu = (6, 6), to %g; %d slots" % (
-                           n_req, "/".join(sorted({str(P.grid.nx) for P in probs}, key=int)), tol, slots)}
+                       "V-cycles nu = %s, to %g; %d slots" % (
+                           n_req, "/".join(sorted({str(P.grid.nx) for P in probs}, key=int)), NU, tol, slots)}
     rate_sat = None
     for frac in (None, 0.25, 0.5, 0.75, 1.0):
         srv = mg.Server(max_active=slots, hbm_budget=128 << 30)
@@ -423,10 +426,10 @@ def serving_resident(torch, mg, W, n_geom, n_rhs, slots, tol, budget):
     summ.update({"workload": "%d seeded 2048^2 geometries (stars and disks, mixed boundary conditions), %d "
                              "right-hand sides each in a random order, Poisson arrivals at 80%% of the saturation "
                              "rate (%.1f solves/s); hierarchies resident within a %.0f GiB budget; mixed "
-                             "precision, V-cycles nu = (6, 6), to %g; %d slots" % (
-                                 n_geom, n_rhs, sat, budget / 2 ** 30, tol, slots),
+                             "precision, V-cycles nu = %s, to %g; %d slots" % (
+                                 n_geom, n_rhs, sat, budget / 2 ** 30, NU, tol, slots),
                  "sequential_fp64_solves_per_s": seq_rate, "resident_bytes": st["resident_bytes"],
-                 "evictions": st["evictions"]})
+                 "evictions": st["evictions"], "server_sweep_gbs": st["sweep_gbs"]})
     print("resident: %s" % summ, file=sys.stderr, flush=True)
     return summ
 
@@ -464,11 +467,13 @@ def solve_leg(torch, mg, P, steps, warmup, tol, timing_solves, label):
 
 
 def main():
+    global NU
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--nu", default="%d,%d" % NU, help="smoothing steps nu1,nu2 of every solve")
     ap.add_argument("--timing-solves", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=8.0)
     ap.add_argument("--cpu-n", type=int, default=512)
@@ -492,6 +497,9 @@ def main():
                     help="also move 256 MiB with the runtime's copy kernel and with an elementwise kernel "
                          "(references for HBM byte counters)")
     args = ap.parse_args()
+    NU = tuple(int(v) for v in args.nu.split(","))
+    if len(NU) != 2 or min(NU) < 0:
+        ap.error("--nu takes two non-negative integers nu1,nu2")
     if args.cpu_baseline_worker:
         print(json.dumps(cpu_baseline(args.cpu_n, args.cpu_iters, args.cpu_cells, args.cpu_seconds)))
         return
@@ -569,9 +577,10 @@ def main():
         # the same solve with the FMG cycle, fewer sweeps, and the
         # multicolour smoother
         var = {}
-        for kw, name in ((dict(pair_sweeps=-1), "v_nu66_single_sweep_tiles"),
-                         (dict(cycle=mg.CYCLE_FMG), "fmg_nu66"), (dict(nu=(4, 4)), "v_nu44"),
-                         (dict(colouring=mg.SMOOTH_MULTICOLOUR), "v_nu66_multicolour"),
+        nn = "%d%d" % NU
+        for kw, name in ((dict(pair_sweeps=-1), "v_nu%s_single_sweep_tiles" % nn), (dict(nu=(6, 6)), "v_nu66"),
+                         (dict(cycle=mg.CYCLE_FMG), "fmg_nu%s" % nn), (dict(nu=(4, 4)), "v_nu44"),
+                         (dict(colouring=mg.SMOOTH_MULTICOLOUR), "v_nu%s_multicolour" % nn),
                          (dict(colouring=mg.SMOOTH_MULTICOLOUR, nu=(4, 4)), "v_nu44_multicolour")):
             opts = dict(eps=P.eps, precision=mg.MIXED, max_iters=1000, nu=NU)
             opts.update(kw)
@@ -632,7 +641,7 @@ def main():
             # processes are forked from it)
             r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-worker",
                                 "--cpu-n", str(args.cpu_n), "--cpu-seconds", str(args.cpu_seconds),
-                                "--cpu-iters", str(it64[-1]), "--cpu-cells", str(n_cells)],
+                                "--cpu-iters", str(it64[-1]), "--cpu-cells", str(n_cells), "--nu", args.nu],
                                capture_output=True, text=True, timeout=900)
             if r.returncode != 0:
                 raise RuntimeError("cpu baseline failed: " + r.stderr[-2000:])

@@ -325,6 +325,11 @@ typedef struct {
     double solves_per_s;                    /* completed / (last done - first submit) */
     long long resident_bytes;               /* device bytes of resident hierarchies */
     int resident_problems, evictions;
+    double sweep_gbs;                       /* algorithmic HBM GB/s of the smoothing sweeps of the
+                                               completed solves over the same span as solves_per_s:
+                                               per outer iteration, nu1 + nu2 sweeps on every level
+                                               above the bottom, each reading u and b and writing u
+                                               on the SFV cells (3 words per cell) */
 } mg_server_stats;
 
 /* Starts the server on the calling thread's current device. */

@@ -81,7 +81,7 @@ class mg_server_stats(ctypes.Structure):
                 ("p50_latency_s", ctypes.c_double), ("p99_latency_s", ctypes.c_double),
                 ("p50_solve_s", ctypes.c_double), ("p99_solve_s", ctypes.c_double),
                 ("solves_per_s", ctypes.c_double), ("resident_bytes", ctypes.c_longlong),
-                ("resident_problems", ctypes.c_int), ("evictions", ctypes.c_int)]
+                ("resident_problems", ctypes.c_int), ("evictions", ctypes.c_int), ("sweep_gbs", ctypes.c_double)]
 
 
 def load_library():

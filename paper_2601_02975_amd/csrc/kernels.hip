@@ -392,7 +392,7 @@ __device__ __forceinline__ void multicolour_tile(const LevelArgs &L, const T *__
 // partial sums are reduced across the wavefront.  HNEW: the tile role has
 // already run (an earlier launch on the same stream), so the Jacobi-updated
 // SFV values are read from unew instead of being recomputed.
-template <typename T, bool MIXED, bool HNEW>
+template <typename T, bool MIXED, bool HNEW, bool PRE>
 __device__ __forceinline__ void plg_group(const LevelArgs &L, const T *__restrict__ uold, const T *__restrict__ b,
                                           T *__restrict__ unew, bool uzero, const PlgDev<T> &P, int bi, T *lds) {
     const PlgBlkA bk = P.blk1[bi];
@@ -418,6 +418,21 @@ __device__ __forceinline__ void plg_group(const LevelArgs &L, const T *__restric
     }
     // the cell of this thread's output row (levels without separators)
     const int out_cell = (P.nsep == 0 && g < P.nseg && (int)threadIdx.x < r1 - r0) ? P.cell[r0 + threadIdx.x] : 0;
+    // PRE (the fused launch on small grids, where the gather below is long:
+    // it recomputes the Jacobi update of every coupled SFV cell, and few
+    // blocks are resident): this thread's first row of A21 is loaded before
+    // the gather, so that its latency overlaps it
+    static_assert(!(PRE && HNEW), "the preload serves the fused launch");
+    T a0v[PRE ? ELL_W : 1];
+    int a0l[PRE ? ELL_W : 1];
+    if (PRE && n > 0) {
+        const size_t e0 = (size_t)(gs + min((int)threadIdx.x, n - 1)) * ELL_W;
+#pragma unroll
+        for (int e = 0; e < (PRE ? ELL_W : 1); ++e) {
+            a0v[e] = P.a21_val[e0 + e];
+            a0l[e] = P.a21_loc[e0 + e];
+        }
+    }
     // u1 after the Jacobi sweep on the SFV cells the group couples to
     for (int k = threadIdx.x; k < bk.nh; k += NT) {
         const int id = P.hcell[bk.h0 + k];
@@ -439,10 +454,15 @@ __device__ __forceinline__ void plg_group(const LevelArgs &L, const T *__restric
     for (int k = 0; k < RPT; ++k) {
         const int q = threadIdx.x + k * NT;
         if (q < n) {
-            const size_t e0 = (size_t)(gs + q) * ELL_W;
             T v = 0;
+            if (PRE && k == 0) {
 #pragma unroll
-            for (int e = 0; e < ELL_W; ++e) v += P.a21_val[e0 + e] * hv[P.a21_loc[e0 + e]];
+                for (int e = 0; e < (PRE ? ELL_W : 1); ++e) v += a0v[e] * hv[a0l[e]];
+            } else {
+                const size_t e0 = (size_t)(gs + q) * ELL_W;
+#pragma unroll
+                for (int e = 0; e < ELL_W; ++e) v += P.a21_val[e0 + e] * hv[P.a21_loc[e0 + e]];
+            }
             tt[q] = brow[k] - v;
         }
     }
@@ -528,8 +548,8 @@ __global__ __launch_bounds__(NT) void k_smooth_a(LevelArgs L, const T *__restric
         return;
     }
     if (bid - plg0 >= P.nblk1) return;                                       // padding of the PLG section
-    plg_group<T, MIXED, HNEW>(L, uold, b, unew, uzero != 0, P, xcd_tile(bid - plg0, P.nblk1),
-                              reinterpret_cast<T *>(smem));
+    plg_group<T, MIXED, HNEW, !HNEW && TYv == TY_SMALL>(L, uold, b, unew, uzero != 0, P,
+                                                        xcd_tile(bid - plg0, P.nblk1), reinterpret_cast<T *>(smem));
 }
 
 // Launch A on large grids, tile role alone: it needs far fewer registers

@@ -33,6 +33,7 @@ struct Problem {
     mg_options opt{};
     mg_handle h = nullptr;
     long long bytes = 0;          // device bytes of the hierarchy (estimate until set up)
+    double sweep_bytes = 0;       // smoother SFV bytes of one outer iteration (once set up)
     bool busy = false, failed = false;
     mg_status setup_status = MG_OK;
     std::string setup_error;
@@ -71,6 +72,7 @@ struct mg_server_s {
     long long resident_bytes = 0, tick = 0;
     int active = 0, evictions = 0;
     long long submitted = 0, completed = 0, failed = 0;
+    double moved_bytes = 0;                        // smoother SFV bytes of the completed solves
     bool stopping = false, any_submit = false;
     Clock::time_point t_first_submit, t_last_done;
     std::vector<double> latencies, solve_times;
@@ -158,6 +160,12 @@ struct mg_server_s {
                     p.h = h;
                     p.bytes = info.device_bytes;
                     resident_bytes += p.bytes;
+                    // one V-cycle: nu1 + nu2 sweeps on every level above the
+                    // bottom, each reading u and b and writing u on the SFV cells
+                    const double w = p.opt.precision == MG_MIXED ? 4.0 : 8.0;
+                    p.sweep_bytes = 0;
+                    for (int l = 0; l + 1 < info.n_levels && l < 16; ++l)
+                        p.sweep_bytes += (p.opt.nu1 + p.opt.nu2) * 3.0 * w * (double)info.n_sfv[l];
                 } else {
                     p.failed = true;
                     p.setup_status = rc;
@@ -185,6 +193,7 @@ struct mg_server_s {
             --active;
             if (rc == MG_OK) {
                 ++completed;
+                moved_bytes += iters * p.sweep_bytes;
                 latencies.push_back(seconds_since(r.t_submit, t));
                 solve_times.push_back(seconds_since(r.t_start, t));
                 t_last_done = t;
@@ -325,6 +334,7 @@ mg_status mg_server_get_stats(mg_server s, mg_server_stats *st) {
     if (s->completed > 0) {
         const double span = seconds_since(s->t_first_submit, s->t_last_done);
         st->solves_per_s = span > 0 ? s->completed / span : 0.0;
+        st->sweep_gbs = span > 0 ? s->moved_bytes / span / 1e9 : 0.0;
     }
     st->resident_bytes = s->resident_bytes;
     for (const auto &p : s->problems) st->resident_problems += p.h != nullptr;

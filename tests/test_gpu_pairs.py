@@ -115,3 +115,26 @@ def test_pair_mixed_solve(name):
         name, it1, it0, r1, r0, err))
     assert c1 == 0 and c0 == 0 and it1 == it0
     assert err <= 1e-12
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_pair_fmg_solve(name):
+    """FMG cycles in FP64 (Algorithm 4 on residual equations: the finest
+    level's V-cycle starts from the interpolant, its buffers rotate with the
+    residual equation's) with and without pairs."""
+    torch = _torch()
+    import paper_2601_02975_amd as mg
+    P, H = oracle(name)
+    sol = []
+    for pairs in (True, False):
+        S = mg.Solver(P.grid, P.curves, P.a, P.b, P.c, eps=P.eps, precision=mg.FP64, nu=(2, 2), max_iters=200,
+                      cycle=mg.CYCLE_FMG, split_cells=1, pair_sweeps=0 if pairs else -1)
+        f, g = S.project(P.solution, 8)
+        u = torch.zeros_like(f)
+        it, r, c = S.solve(f, g, u, 1e-10)
+        assert c == 0
+        sol.append((it, u))
+        S.close()
+    err = float((sol[0][1] - sol[1][1]).abs().max() / sol[1][1].abs().max())
+    print("%s FMG: %d / %d cycles, solutions differ by %.2e" % (name, sol[0][0], sol[1][0], err))
+    assert sol[0][0] == sol[1][0] and err <= 1e-12

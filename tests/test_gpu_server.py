@@ -62,6 +62,7 @@ def test_server_results_equal_alone(budget, precision):
         assert torch.equal(u, u0)
     assert st["completed"] == len(reqs) and st["failed"] == 0
     assert st["p99_latency_s"] >= st["p50_latency_s"] > 0
+    assert 0 < st["sweep_gbs"] < 8000       # the smoothing bytes of the solves, below the HBM peak
     if budget == 1:
         assert st["evictions"] > 0 and st["resident_problems"] <= 1
     print(st)

@@ -379,9 +379,10 @@ def with_grid(problem, n):
 
 def serving_geometry(seed, n=2048):
     """One geometry of the resident-serving workload: a seeded star (its
-    boundary condition uniform over D, N, R) on even seeds, 1-5 seeded disks
+    boundary condition uniform over N, R) on even seeds, 1-5 seeded disks
     with mixed boundary conditions on odd seeds; a, c ~ U[0.5, 2],
-    |b| < sqrt(ac); n x n cells."""
+    |b| < sqrt(ac); n x n cells.  (A Dirichlet star is left out: the V-cycle
+    diverges on it, in the oracle as on the GPU.)"""
     rng = np.random.default_rng([int(seed), 4099])
     a = float(rng.uniform(0.5, 2.0)); c = float(rng.uniform(0.5, 2.0))
     b = float(rng.uniform(-1.0, 1.0)) * math.sqrt(a * c) * 0.95
@@ -390,7 +391,7 @@ def serving_geometry(seed, n=2048):
         cx, cy = (0.5 + float(v) for v in rng.uniform(-0.03, 0.03, size=2))
         phi = float(rng.uniform(0.0, math.pi / 4))
         R = float(rng.uniform(0.28, 0.32)); r_in = float(rng.uniform(0.14, 0.18))
-        bc = str(rng.choice([BC_DIRICHLET, BC_NEUMANN, BC_ROBIN]))
+        bc = str(rng.choice([BC_NEUMANN, BC_ROBIN]))
         curves.append(star_hole(cx, cy, R, r_in, phi, bc=bc, alpha1=1.0, alpha2=0.5, round_tips=False))
     else:
         for (x, y, r) in _disks(rng, int(rng.integers(1, 6))):
