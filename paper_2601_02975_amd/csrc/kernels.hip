@@ -594,9 +594,10 @@ __device__ __forceinline__ void pair_tile(const LevelArgs &L, const T *__restric
     static_assert(NT == 4 * TX, "four thread rows of 64 columns");
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     const T wod = (T)L.omega_over_d;
-    // right-hand sides: E1's 64 middle columns (RR rows per thread row),
-    // E1's 4 outer columns (one cell per thread), the tile (second sweep)
-    T b1[RR], bx = 0, b2[R];
+    // right-hand sides: E1's 64 middle columns (RR rows per thread row) and
+    // its 4 outer columns (one cell per thread); the second sweep takes the
+    // tile's from LDS
+    T b1[RR], bx = 0;
 #pragma unroll
     for (int k = 0; k < RR; ++k) {
         const int er = ty * RR + k;
@@ -605,16 +606,17 @@ __device__ __forceinline__ void pair_tile(const LevelArgs &L, const T *__restric
     const int xc = threadIdx.x / E1, xr = threadIdx.x - xc * E1;      // outer column xc (0..3), row xr
     const int xe = xc < 2 ? xc : TX + xc;                               // its E1 column
     if (threadIdx.x < NX1) bx = b[pidx(L, i0 - 2 + xe, j0 - 2 + xr)];
-#pragma unroll
-    for (int k = 0; k < R; ++k) b2[k] = b[pidx(L, i0 + tx, j0 + ty * R + k)];
     if (!uzero) {
         constexpr int N2 = (TYv + 8) * PX, NL = (N2 + NT - 1) / NT;
         T v[NL];
+        // (32-bit offsets from the tile's E2 corner: the arrays of a level
+        // hold fewer than 2^31 cells)
+        const T *e2 = uold + pidx(L, i0 - 4, j0 - 4);
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
             const int t = min((int)threadIdx.x + k * NT, N2 - 1);
             const int r = t / PX, c = t - r * PX;
-            v[k] = uold[pidx(L, i0 - 4 + c, j0 - 4 + r)];
+            v[k] = e2[(unsigned)(r * L.pitch + c)];
         }
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
@@ -657,6 +659,16 @@ __device__ __forceinline__ void pair_tile(const LevelArgs &L, const T *__restric
         }
     }
     __syncthreads();
+    // the tile's right-hand side into the space of E2, which is no longer
+    // read (rows 2 .. TYv+1 of E1 are the tile's rows)
+    static_assert(TYv * TX <= (TYv + 8) * PX, "the tile's b fits in E2's space");
+    T (*bt)[TX] = reinterpret_cast<T(*)[TX]>(&s2[0][0]);
+#pragma unroll
+    for (int k = 0; k < RR; ++k) {
+        const int er = ty * RR + k;
+        if (er >= 2 && er < TYv + 2) bt[er - 2][tx] = b1[k];
+    }
+    __syncthreads();
     // second sweep on the tile
     const int r0 = ty * R;
     T w[5][5];
@@ -675,7 +687,7 @@ __device__ __forceinline__ void pair_tile(const LevelArgs &L, const T *__restric
         const T au = apply_sfv<T, MIXED>(L, [&](int dx, int dy) { return w[dy + 2][dx + 2]; });
         const size_t id = pidx(L, i0 + tx, j0 + r0 + k);
         ub[id] = w[2][2];
-        uc[id] = w[2][2] + wod * (b2[k] - au);
+        uc[id] = w[2][2] + wod * (bt[r0 + k][tx] - au);
     }
 }
 
